@@ -1,0 +1,171 @@
+"""Closed forms and fits used to pin the oracle and to compare runs.
+
+Test infrastructure.  Nothing here calls the PIC step; these are the
+independent references the oracle is checked against, plus the growth-rate
+fit and the parity metrics that compare a run with the oracle.
+
+Running this file writes ``tests/golden/weibel_cold_rates.txt`` from the
+closed forms below (it calls nothing outside ``oracle/``).
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Cold-fluid filamentation (Weibel) rate of drifting cold electron species
+# with immobile ions, k along x, drifts along z, full Maxwell equations.
+# Linearising the relativistic cold-fluid equations with E = (E_x, 0, E_z),
+# B = (0, B_y, 0) gives, with W = omega^2 and per-species alpha = n_s/n0,
+#   A0 = sum alpha/gamma, A1 = sum alpha v/gamma, A2 = sum alpha v^2/gamma,
+#   A3 = sum alpha/gamma^3,
+#   (W^2 - (k^2 + A3) W - k^2 A2) (W - A0) = k^2 A1^2 .
+# The growth rate is sqrt(-W) for the negative real root.  The paper's
+# collisionless warm-beam theory (Eqs. 8-11) is the long-wavelength
+# non-relativistic limit of the same physics; this is the cold, relativistic,
+# all-k form used to pin the cold-beam run.
+def weibel_cold_rate(k: float, species) -> float:
+    """species: iterable of (alpha, u_z).  Returns the growth rate (1/w_p)."""
+    A0 = A1 = A2 = A3 = 0.0
+    for alpha, u in species:
+        g = math.sqrt(1.0 + u * u)
+        v = u / g
+        A0 += alpha / g
+        A1 += alpha * v / g
+        A2 += alpha * v * v / g
+        A3 += alpha / g ** 3
+    k2 = k * k
+    # expand: W^3 - (A0 + k2 + A3) W^2 + (A0 (k2 + A3) - k2 A2) W + k2 A2 A0 - k2 A1^2 = 0
+    coeffs = [1.0, -(A0 + k2 + A3), A0 * (k2 + A3) - k2 * A2, k2 * A2 * A0 - k2 * A1 * A1]
+    roots = np.roots(coeffs)
+    neg = [r.real for r in roots if abs(r.imag) < 1e-12 * max(1.0, abs(r)) and r.real < 0.0]
+    if not neg:
+        return 0.0
+    return math.sqrt(-min(neg))
+
+
+def beam_plasma_species(n_b=0.1, u_beam=math.sqrt(8.0)):
+    """Cold beam and the cold return current that cancels it."""
+    v_b = u_beam / math.sqrt(1 + u_beam ** 2)
+    v_p = -n_b * v_b / (1 - n_b)
+    u_p = v_p / math.sqrt(1 - v_p ** 2)
+    return [(n_b, u_beam), (1 - n_b, u_p)]
+
+
+def two_stream_cold_rate_weak(n_b, n_p, gamma_b):
+    """Maximum growth rate of the weak cold beam-plasma two-stream
+    instability (beam much thinner than the plasma), in w_pe of the plasma:
+    (sqrt(3)/2^{4/3}) (n_b/n_p)^{1/3} / gamma_b."""
+    return math.sqrt(3.0) / 2 ** (4.0 / 3.0) * (n_b / n_p) ** (1.0 / 3.0) / gamma_b
+
+
+# ---------------------------------------------------------------------------
+# Discrete closed forms of the time integrators.
+def boris_gyration(u_perp: float, u_par: float, qB_over_m: float, dt: float):
+    """Exact discrete orbit of the Boris rotation in a uniform B.
+
+    With gamma = sqrt(1 + u_perp^2 + u_par^2), Omega = |q B|/(m gamma) and
+    a = Omega dt / 2, each step turns u_perp by 2 atan(a) and keeps |u|; the
+    positions lie on a circle of radius r_L sqrt(1 + a^2), r_L = u_perp/|qB/m|.
+    Returns (angle per step, polygon radius)."""
+    g = math.sqrt(1.0 + u_perp ** 2 + u_par ** 2)
+    a = abs(qB_over_m) * dt / (2.0 * g)
+    r_L = u_perp / abs(qB_over_m)
+    return 2.0 * math.atan(a), r_L * math.sqrt(1.0 + a * a)
+
+
+def yee_vacuum_omega(k, d, dt):
+    """Discrete vacuum dispersion of the Yee scheme:
+    sin^2(w dt/2)/dt^2 = sum_i sin^2(k_i d_i/2)/d_i^2."""
+    s = sum(math.sin(ki * di / 2) ** 2 / di ** 2 for ki, di in zip(k, d))
+    return 2.0 / dt * math.asin(dt * math.sqrt(s))
+
+
+def leapfrog_plasma_omega(wp: float, dt: float) -> float:
+    """Oscillation frequency of a cold plasma under leap-frog integration:
+    sin(w dt/2) = wp dt / 2."""
+    return 2.0 / dt * math.asin(wp * dt / 2.0)
+
+
+# ---------------------------------------------------------------------------
+# Growth-rate fit and parity metrics.
+def fit_growth_window(t, W, span=21, tol=0.10, frac_max=0.10):
+    """Window of linear growth of ln W(t): the longest contiguous range where
+    the centred local slope (least squares over `span` samples) stays within
+    +-tol of the range mean and W stays below frac_max of its running max at
+    the end of the series.  Returns (i0, i1) inclusive-exclusive indices."""
+    t = np.asarray(t, dtype=float)
+    y = np.log(np.asarray(W, dtype=float))
+    n = len(t)
+    h = span // 2
+    slope = np.full(n, np.nan)
+    for i in range(h, n - h):
+        tt = t[i - h:i + h + 1]
+        yy = y[i - h:i + h + 1]
+        slope[i] = np.polyfit(tt, yy, 1)[0]
+    wmax = float(np.max(W))
+    ok = (np.asarray(W) < frac_max * wmax) & np.isfinite(slope) & (slope > 0)
+    best = (0, 0)
+    i = 0
+    while i < n:
+        if not ok[i]:
+            i += 1
+            continue
+        j = i
+        while j < n and ok[j]:
+            j += 1
+        # shrink from the left until all slopes are within tol of the mean
+        a, b = i, j
+        while b - a > 2:
+            m = float(np.mean(slope[a:b]))
+            dev = np.abs(slope[a:b] - m) / abs(m)
+            if np.all(dev <= tol):
+                break
+            worst = a + int(np.argmax(dev))
+            if worst - a < b - 1 - worst:
+                a = worst + 1
+            else:
+                b = worst
+        if b - a > best[1] - best[0]:
+            best = (a, b)
+        i = j
+    return best
+
+
+def fit_growth_rate(t, W, window):
+    """Growth rate of a field amplitude from an energy series:
+    half the least-squares slope of ln W over the window."""
+    i0, i1 = window
+    t = np.asarray(t, dtype=float)[i0:i1]
+    y = np.log(np.asarray(W, dtype=float)[i0:i1])
+    return 0.5 * float(np.polyfit(t, y, 1)[0])
+
+
+def stacked_rel_err(F, F_ref):
+    """||F - F_ref||_2 / ||F_ref||_2 over all components stacked."""
+    F = np.asarray(F, dtype=float)
+    F_ref = np.asarray(F_ref, dtype=float)
+    return float(np.linalg.norm((F - F_ref).ravel()) / np.linalg.norm(F_ref.ravel()))
+
+
+def _write_golden(path):
+    sp = beam_plasma_species(0.1, math.sqrt(8.0))
+    L = 64 * 0.2
+    lines = ["# Cold-fluid filamentation growth rate, beam n_b=0.1 gamma=3 (u=sqrt(8)) + cancelling",
+             "# cold return current, immobile ions; written by oracle/theory.py from the",
+             "# closed-form dispersion relation (W^2-(k^2+A3)W-k^2A2)(W-A0)=k^2A1^2.",
+             "# columns: mode m on a box of side 12.8 c/w_p, k (w_p/c), rate (w_p)"]
+    for m in (1, 2, 4, 8, 16):
+        k = 2 * math.pi * m / L
+        lines.append(f"{m} {k:.12f} {weibel_cold_rate(k, sp):.12f}")
+    lines.append(f"inf inf {weibel_cold_rate(1e6, sp):.12f}")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    here = os.path.dirname(os.path.abspath(__file__))
+    _write_golden(os.path.join(here, "..", "tests", "golden", "weibel_cold_rates.txt"))

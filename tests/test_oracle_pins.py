@@ -1,0 +1,448 @@
+"""Pins of the FP64 oracle against closed forms, invariants and published
+values (CPU only).  Each test names the fact it checks; together they are
+chosen so that a dropped term, a wrong sign, a wrong stagger or a wrong
+normalisation anywhere in the oracle's step fails at least one of them."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import theory
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _species(wl, parts, orc, weights=None):
+    out = []
+    for i, (sc, p) in enumerate(zip(wl.species, parts)):
+        w = sc.weight if weights is None else weights[i]
+        out.append(orc.SpeciesState(sc.q, sc.m, w, sc.nu, p.x.copy(), p.u.copy(), p.id.copy()))
+    return out
+
+
+def _single(orc, x, u, q=-1.0, m=1.0, w=0.0, nu=0.0, pid=0):
+    x = np.asarray(x, dtype=float).reshape(-1, 1)
+    u = np.asarray(u, dtype=float).reshape(3, 1)
+    return orc.SpeciesState(q, m, w, nu, x.copy(), u.copy(), np.array([pid], dtype=np.uint32))
+
+
+# --------------------------------------------------------------------------- RNG
+def test_philox_known_answers(orc):
+    """Philox4x32-10 reproduces the published known-answer vectors."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(h, 16) for h in r]
+        out = orc.philox4x32_10(v[0:4], v[4:6])
+        assert [int(o) for o in out] == v[6:10]
+
+
+def test_philox_uniformity(orc):
+    """Word 0 over consecutive counters is uniform (chi-square, 64 bins)."""
+    n = 20000
+    vals = np.array([orc.philox4x32_10([i, 7, 1, 0], [0x08084078, 0])[0] for i in range(n)],
+                    dtype=np.float64)
+    h, _ = np.histogram(vals / 2.0 ** 32, bins=64, range=(0, 1))
+    chi2 = float(((h - n / 64) ** 2 / (n / 64)).sum())
+    # 63 dof: mean 63, sd ~11.2; 5 sigma bound
+    assert chi2 < 63 + 5 * math.sqrt(2 * 63)
+
+
+# --------------------------------------------------------------------------- push
+def test_boris_gyration_exact_discrete_orbit(orc):
+    """Uniform B_z, no current (w = 0): |u| is constant, u_perp turns by
+    2 atan(Omega dt/2) per step in the electron's (positive) sense, and the
+    positions lie on a circle of radius r_L sqrt(1 + a^2)."""
+    B0, u_perp, u_par, dt = 1.0, 0.1, 0.3, 0.1
+    n = (8, 8)
+    sp = _single(orc, [0.8, 0.8], [u_perp, 0.0, u_par])
+    run = orc.OracleRun(2, n, (0.2, 0.2), dt, [sp], seed=1)
+    run.f.B[2][:] = B0
+    ang, R = theory.boris_gyration(u_perp, u_par, B0, dt)
+    steps = 10000
+    us, xs = [], []
+    for _ in range(steps):
+        xs.append(sp.x[:, 0].copy())
+        run.step(1)
+        us.append(sp.u[:, 0].copy())
+    us = np.array(us)
+    xs = np.array(xs)
+    umag = np.linalg.norm(us, axis=1)
+    assert np.max(np.abs(umag - math.hypot(u_perp, u_par))) < 1e-13
+    phi = np.unwrap(np.arctan2(us[:, 1], us[:, 0]))
+    dphi = np.diff(phi)
+    assert np.max(np.abs(dphi - ang)) < 1e-12          # q < 0, B > 0: counter-clockwise
+    assert abs(us[-1, 2] - u_par) < 1e-14
+    # circle through the positions: centre from a least-squares fit
+    A = np.c_[2 * xs[:, 0], 2 * xs[:, 1], np.ones(len(xs))]
+    bvec = (xs ** 2).sum(axis=1)
+    cx, cy, c0 = np.linalg.lstsq(A, bvec, rcond=None)[0]
+    r = np.hypot(xs[:, 0] - cx, xs[:, 1] - cy)
+    assert np.max(np.abs(r - R)) < 1e-11
+    assert abs(run.f.B[2].mean() - B0) < 1e-15 and np.abs(run.f.E).max() == 0.0
+
+
+def test_boris_uniform_electric_field(orc):
+    """Uniform E, B = 0: u^{n+1/2} = u^{n-1/2} + q E dt/m exactly per step."""
+    E0, dt = np.array([0.02, -0.01, 0.03]), 0.1
+    sp = _single(orc, [0.3, 0.5], [0.1, 0.0, 0.5])
+    run = orc.OracleRun(2, (8, 8), (0.2, 0.2), dt, [sp], seed=1)
+    for c in range(3):
+        run.f.E[c][:] = E0[c]
+    u_expect = np.array([0.1, 0.0, 0.5])
+    for _ in range(100):
+        run.step(1)
+        u_expect = u_expect + (-1.0) * E0 * dt
+    assert np.max(np.abs(sp.u[:, 0] - u_expect)) < 1e-13
+
+
+def test_gather_reproduces_linear_fields_at_staggered_points(orc):
+    """Bilinear gather is exact for fields linear in x and y; sampling each
+    component at its own Yee location (Ex at (i+1/2,j), Ey at (i,j+1/2),
+    Ez at (i,j), Bx at (i,j+1/2), By at (i+1/2,j), Bz at (i+1/2,j+1/2))
+    makes the gathered value equal the linear function at the particle."""
+    n, d = (16, 16), (0.2, 0.25)
+    run = orc.OracleRun(2, n, d, 0.05, [], seed=1)
+    stag = [(0.5, 0), (0, 0.5), (0, 0), (0, 0.5), (0.5, 0), (0.5, 0.5)]
+    coef = [(0.3, -0.7, 0.1), (1.1, 0.2, -0.4), (-0.5, 0.9, 0.3), (0.25, 0.5, -0.2),
+            (-0.6, -0.3, 0.7), (0.8, -0.1, 0.05)]
+    jj, ii = np.meshgrid(np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    for c, ((sx, sy), (a, b, k0)) in enumerate(zip(stag, coef)):
+        F = k0 + a * (ii + sx) * d[0] + b * (jj + sy) * d[1]
+        (run.f.E if c < 3 else run.f.B)[c % 3][0] = F
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        x = np.array([rng.uniform(3, 12) * d[0], rng.uniform(3, 12) * d[1]])
+        E, B = run.gather(x)
+        got = np.r_[E, B]
+        want = [k0 + a * x[0] + b * x[1] for (a, b, k0) in coef]
+        assert np.max(np.abs(got - want)) < 1e-13
+
+
+# --------------------------------------------------------------------------- deposit
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_esirkepov_continuity_per_node(orc, ndim):
+    """rho^{n+1} - rho^n + dt div J^{n+1/2} = 0 at every node to round-off
+    for random moves shorter than a cell, with rho deposited by CIC."""
+    rng = np.random.default_rng(11 + ndim)
+    n = (7, 6, 5)[:ndim]
+    d = (0.2, 0.3, 0.25)[:ndim]
+    dt = 0.1
+    N = 300
+    L = np.array([n[a] * d[a] for a in range(ndim)])
+    x0 = rng.uniform(0, 1, (ndim, N)) * L[:, None]
+    step = rng.uniform(-0.95, 0.95, (ndim, N)) * np.array(d)[:, None]
+    x1u = x0 + step
+    x1 = np.mod(x1u, L[:, None])
+    q, w = -1.0, 0.37
+    sp0 = orc.SpeciesState(q, 1.0, w, 0.0, x0.copy(), np.zeros((3, N)), np.arange(N, dtype=np.uint32))
+    run = orc.OracleRun(ndim, n, d, dt, [sp0], seed=1)
+    rho0 = run.rho()
+    J = np.zeros_like(run.f.J)
+    for p in range(N):
+        run.deposit(q * w, x0[:, p], x1u[:, p], 0.0, J)
+    sp0.x[:] = x1
+    rho1 = run.rho()
+    res = rho1 - rho0 + dt * run.divergence(J)
+    assert np.max(np.abs(res)) < 1e-13 * max(1.0, np.abs(rho0).max())
+    # total current: sum over nodes of J_a equals sum q w dx_a/dt
+    for a in range(ndim):
+        assert abs(J[a].sum() - q * w * step[a].sum() / dt) < 1e-12 * N
+
+
+def test_esirkepov_straight_move_closed_form(orc):
+    """A particle sitting on row j = 3 moving along x inside one cell puts
+    all of its current on the single face between nodes i and i+1:
+    J_x(i+1/2, j) = q w (x1 - x0)/dt, nothing else; its out-of-plane current
+    q w v_z splits by the time-averaged CIC weights along x."""
+    dx, dy, dt = 0.2, 0.2, 0.1
+    run = orc.OracleRun(2, (8, 8), (dx, dy), dt, [], seed=1)
+    q, w, vz = -1.0, 0.5, 0.3
+    x0 = np.array([(4 + 0.3) * dx, 3 * dy])
+    x1 = np.array([(4 + 0.55) * dx, 3 * dy])
+    J = run.deposit(q * w, x0, x1, vz)
+    want = np.zeros_like(J)
+    want[0][0, 3, 4] = q * w * (x1[0] - x0[0]) / dt
+    # W_z = S0x S0y + DSx S0y/2 with S0y = 1 at j = 3: the x weights averaged
+    s0 = np.array([0.7, 0.3])
+    s1 = np.array([0.45, 0.55])
+    want[2][0, 3, 4:6] = q * w * vz * 0.5 * (s0 + s1)
+    assert np.max(np.abs(J - want)) < 1e-15
+
+
+def test_out_of_plane_current_sums_to_q_w_vz(orc):
+    rng = np.random.default_rng(5)
+    run = orc.OracleRun(2, (8, 8), (0.2, 0.2), 0.1, [], seed=1)
+    J = np.zeros_like(run.f.J)
+    tot = 0.0
+    for _ in range(100):
+        x0 = rng.uniform(0, 1.6, 2)
+        x1 = x0 + rng.uniform(-0.09, 0.09, 2)
+        vz = rng.uniform(-1, 1)
+        run.deposit(-0.25, x0, x1, vz, J)
+        tot += -0.25 * vz
+    assert abs(J[2].sum() - tot) < 1e-13
+
+
+# --------------------------------------------------------------------------- fields
+@pytest.mark.parametrize("mode", ["TM", "TE"])
+def test_yee_standing_wave_discrete_dispersion(orc, mode):
+    """A vacuum standing wave started with the other field at zero stays a
+    pure cos(w n dt) in time, with sin^2(w dt/2)/dt^2 = sum sin^2(k d/2)/d^2
+    (the Yee scheme's exact discrete dispersion), over 1000 steps."""
+    n, d, dt = (32, 16), (0.2, 0.25), 0.1
+    run = orc.OracleRun(2, n, d, dt, [], seed=1)
+    kx, ky = 2 * math.pi * 3 / (n[0] * d[0]), 2 * math.pi * 2 / (n[1] * d[1])
+    w = theory.yee_vacuum_omega((kx, ky), d, dt)
+    jj, ii = np.meshgrid(np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    if mode == "TM":          # E_z at (i, j)
+        F0 = np.cos(kx * ii * d[0] + ky * jj * d[1])
+        run.f.E[2][0] = F0
+    else:                     # B_z at (i+1/2, j+1/2)
+        F0 = np.cos(kx * (ii + 0.5) * d[0] + ky * (jj + 0.5) * d[1])
+        run.f.B[2][0] = F0
+    for s in range(1, 1001):
+        run.yee_b(0.5)
+        run.yee_e()
+        run.yee_b(0.5)
+        if s % 250 == 0:
+            F = run.f.E[2][0] if mode == "TM" else run.f.B[2][0]
+            assert np.max(np.abs(F - F0 * math.cos(w * s * dt))) < 1e-11
+
+
+# --------------------------------------------------------------------------- whole step
+def _small_noisy(orc, n=(32, 32), ppc=8, steps=0, nu=0.0):
+    wl = synth.beam_plasma(n, ppc=ppc, u_th_beam=0.1, nu=nu, steps=steps)
+    parts = synth.load(wl)
+    sp = _species(wl, parts, orc)
+    return wl, orc.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, sp, wl.seed)
+
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_yee_3d_standing_wave(orc, comp):
+    """3D: a divergence-free B mode along one axis varying along the other
+    two (B_x(y,z), B_y(x,z), B_z(x,y)) with E = 0 stays B0 cos(w n dt),
+    w from the discrete dispersion."""
+    n, d, dt = (12, 10, 8), (0.2, 0.25, 0.3), 0.08
+    run = orc.OracleRun(3, n, d, dt, [], seed=1)
+    m = [2, 1, 1]
+    k = [2 * math.pi * m[a] / (n[a] * d[a]) for a in range(3)]
+    k[comp] = 0.0
+    stag = {0: (0, 0.5, 0.5), 1: (0.5, 0, 0.5), 2: (0.5, 0.5, 0)}[comp]
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ph = k[0] * (ii + stag[0]) * d[0] + k[1] * (jj + stag[1]) * d[1] + k[2] * (kk + stag[2]) * d[2]
+    F0 = np.cos(ph)
+    run.f.B[comp][:] = F0
+    w = theory.yee_vacuum_omega(k, d, dt)
+    for s in range(1, 401):
+        run.yee_b(0.5)
+        run.yee_e()
+        run.yee_b(0.5)
+    assert np.max(np.abs(run.f.B[comp] - F0 * math.cos(w * 400 * dt))) < 1e-11
+    others = [c for c in range(3) if c != comp]
+    assert np.max(np.abs(run.f.B[others])) < 1e-12
+
+
+def test_gauss_law_kept_by_the_step(orc):
+    """With the ions' charge equal and opposite to the electrons' initial
+    deposited charge and E(0) = 0, div E^n = rho^n - rho^0 stays at
+    round-off for every n: the Esirkepov current and the Yee update are
+    charge-consistent."""
+    wl, run = _small_noisy(orc)
+    rho0 = run.rho()
+    for _ in range(5):
+        run.step(10)
+        res = run.divergence(run.f.E) - (run.rho() - rho0)
+        assert np.max(np.abs(res)) < 1e-12
+
+
+def test_gauss_law_kept_by_the_3d_step(orc):
+    wl = synth.beam_plasma((8, 8, 8), ppc=2, u_th_beam=0.3, u_th_plasma=0.05)
+    parts = synth.load(wl)
+    run = orc.OracleRun(3, wl.n, wl.d, wl.dt, _species(wl, parts, orc), wl.seed)
+    rho0 = run.rho()
+    for _ in range(3):
+        run.step(5)
+        res = run.divergence(run.f.E) - (run.rho() - rho0)
+        assert np.max(np.abs(res)) < 1e-12
+    assert np.abs(run.f.E).max() > 1e-6
+
+
+def test_langmuir_frequency_and_energy_exchange(orc):
+    """Cold plasma of density n0 against the immobile ions: a small velocity
+    perturbation oscillates at the leap-frog plasma frequency
+    sin(w dt/2) = dt/2 (w_p = 1), and kinetic plus field energy is
+    conserved while it sloshes between the two."""
+    nx, ny, dt = 64, 4, 0.1
+    sc = synth.SpeciesCfg("e", 1.0, 4, (0, 0, 0), 0.0)
+    wl = synth.Workload("langmuir", 2, (nx, ny), (0.2, 0.2), dt, 400, (sc,), lattice=True)
+    p = synth.load(wl)[0]
+    k = 2 * math.pi / (nx * 0.2)
+    p.u[0] = 1e-3 * np.sin(k * p.x[0])
+    run = orc.OracleRun(2, wl.n, wl.d, dt, [orc.SpeciesState(-1, 1, sc.weight, 0, p.x, p.u, p.id)], 1)
+    xs = (np.arange(nx) + 0.5) * 0.2
+    amp, etot, wfield = [], [], []
+    for _ in range(wl.steps):
+        r = run.step(1, diag=True)[0]
+        etot.append(r["kinetic"].sum() + 0.5 * r["W"].sum())
+        wfield.append(0.5 * r["W"].sum())
+        amp.append(float(np.sum(run.f.E[0][0].mean(axis=0) * np.sin(k * xs))))
+    amp = np.array(amp)
+    t = (np.arange(len(amp)) + 1) * dt
+    s = np.sign(amp)
+    idx = np.where(s[:-1] * s[1:] < 0)[0]
+    zc = [t[i] - amp[i] * (t[i + 1] - t[i]) / (amp[i + 1] - amp[i]) for i in idx]
+    omega = math.pi * (len(zc) - 1) / (zc[-1] - zc[0])
+    assert abs(omega / theory.leapfrog_plasma_omega(1.0, dt) - 1) < 0.01
+    etot = np.array(etot)
+    # the field takes up about half the energy at its peak; the sum stays flat
+    assert max(wfield) > 0.3 * etot[0]
+    assert np.max(np.abs(etot - etot[0])) < 0.01 * etot[0]
+
+
+def test_cold_beam_weibel_growth_rate(orc):
+    """A noise-free (lattice) cold beam n_b = 0.1, gamma = 3 with its cold
+    return current, seeded with B_y of mode 4 along x on a 12.8 c/w_p box,
+    grows at the cold-fluid filamentation rate of that k to within 3%."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "weibel_cold_rates.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    rate = {r[0]: float(r[2]) for r in rows}
+    m, nx, ny = 4, 64, 4
+    wl = synth.beam_plasma((nx, ny), ppc=4, u_th_beam=0.0, u_th_plasma=0.0, lattice=True, steps=660)
+    parts = synth.load(wl)
+    run = orc.OracleRun(2, wl.n, wl.d, wl.dt, _species(wl, parts, orc), wl.seed)
+    L = nx * 0.2
+    k = 2 * math.pi * m / L
+    xh = (np.arange(nx) + 0.5) * 0.2
+    run.f.B[1][0] = 1e-6 * np.cos(k * xh)[None, :]
+    amps = []
+    for _ in range(wl.steps):
+        By = run.f.B[1][0].mean(axis=0)
+        amps.append(abs(np.sum(By * np.exp(-1j * k * xh))) * 2 / nx)
+        run.step(1)
+    t = np.arange(len(amps)) * wl.dt
+    W = np.array(amps) ** 2
+    win = theory.fit_growth_window(t, W)
+    assert win[1] - win[0] > 150
+    g = theory.fit_growth_rate(t, W, win)
+    assert abs(g / rate["4"] - 1) < 0.03, (g, rate["4"])
+
+
+def test_canonical_z_momentum_eq6(orc):
+    """Eq. (6): in 2D with no z dependence each particle keeps
+    u_z + q A_z(x_p), A_z advanced with dA_z/dt = -E_z on the E_z nodes
+    (B_x = d_y A_z, B_y = -d_x A_z hold exactly on the grid).  The
+    violation stays a small fraction of the actual change of u_z."""
+    wl, run = _small_noisy(orc, n=(32, 32), ppc=8)
+    nx, ny = wl.n
+    dx, dy = wl.d
+    Az = np.zeros((ny, nx))
+    s = run.species[0]
+
+    def interp(F, x, y):
+        X, Y = x / dx, y / dy
+        i0, j0 = np.floor(X).astype(int), np.floor(Y).astype(int)
+        fx, fy = X - i0, Y - j0
+        i1, j1 = (i0 + 1) % nx, (j0 + 1) % ny
+        i0, j0 = i0 % nx, j0 % ny
+        return ((1 - fx) * (1 - fy) * F[j0, i0] + fx * (1 - fy) * F[j0, i1]
+                + (1 - fx) * fy * F[j1, i0] + fx * fy * F[j1, i1])
+
+    uz0 = s.u[2].copy()
+    P0 = None
+    for n in range(200):
+        x = s.x.copy()
+        uold = s.u[2].copy()
+        Ez_n = run.f.E[2][0].copy()
+        run.step(1)
+        uc = 0.5 * (uold + s.u[2])
+        P = uc + s.q * interp(Az, x[0], x[1])
+        if P0 is None:
+            P0 = P.copy()
+        Az = Az - 0.5 * wl.dt * (Ez_n + run.f.E[2][0])
+        if n >= 40 and n % 40 == 39:
+            ratio = np.sqrt(np.mean((P - P0) ** 2)) / np.sqrt(np.mean((uc - uz0) ** 2))
+            assert ratio < 0.12, (n, ratio)
+            assert abs(np.mean(P - P0)) < 1e-3 * synth.U_BEAM
+    assert np.max(np.abs(run.f.B[0][0] - (np.roll(Az, -1, 0) - Az) / dy)) < 1e-14
+    assert np.max(np.abs(run.f.B[1][0] + (np.roll(Az, -1, 1) - Az) / dx)) < 1e-14
+
+
+def test_energy_drift_c1_like(orc):
+    """Total energy dV[sum w (gamma - 1) + 1/2 sum (E^2 + B^2)] drifts by
+    less than 1e-3 of itself over 200 steps of the 2D beam-plasma case."""
+    wl, run = _small_noisy(orc, n=(32, 32), ppc=8)
+    recs = run.step(200, diag=True)
+    tot = np.array([r["kinetic"].sum() + 0.5 * r["W"].sum() for r in recs])
+    assert np.max(np.abs(tot - tot[0])) / tot[0] < 1e-3
+    # the fields grew from zero (the system is Weibel unstable)
+    assert recs[-1]["W"][3] + recs[-1]["W"][4] > 0
+
+
+# --------------------------------------------------------------------------- collisions
+def test_collision_threshold_is_integer_floor(orc):
+    nu, dt = 0.05, 0.1
+    P = 1 - math.exp(-nu * dt)
+    assert orc.collision_threshold(nu, dt) == math.floor(P * 2 ** 32)
+    assert orc.collision_threshold(0.0, dt) == 0
+
+
+def test_collisions_drag_isotropy_and_norm(orc):
+    """Scattering with P = 1 - exp(-nu dt) per step relaxes the mean drift as
+    u_z0 exp(-nu t) (the drag of Eq. 3), keeps every |u| to round-off and
+    sends the scattered particles into isotropic directions."""
+    N, nu, dt, steps, u0 = 60000, 0.05, 0.1, 100, 0.2
+    x = np.zeros((2, N)) + 0.1
+    u = np.zeros((3, N))
+    u[2] = u0
+    sp = orc.SpeciesState(-1.0, 1.0, 0.0, nu, x, u, np.arange(N, dtype=np.uint32))
+    run = orc.OracleRun(2, (4, 4), (0.2, 0.2), dt, [sp], seed=0x08084078)
+    recs = run.step(steps, diag=True)
+    ncoll = sum(r["collisions"] for r in recs)
+    P = 1 - math.exp(-nu * dt)
+    assert abs(ncoll - N * steps * P) < 5 * math.sqrt(N * steps * P)
+    assert np.max(np.abs(np.linalg.norm(sp.u, axis=0) - u0)) < 1e-15
+    ps = math.exp(-nu * steps * dt)
+    mean = sp.u[2].mean()
+    var = ps * (1 - ps) * u0 ** 2 + (1 - ps) * u0 ** 2 / 3
+    assert abs(mean - u0 * ps) < 4 * math.sqrt(var / N)
+    hit = sp.u[2] != u0
+    ct = sp.u[2][hit] / u0
+    h, _ = np.histogram(ct, bins=10, range=(-1, 1))
+    e = hit.sum() / 10
+    assert float(((h - e) ** 2 / e).sum()) < 9 + 5 * math.sqrt(18)
+    ph = np.arctan2(sp.u[1][hit], sp.u[0][hit])
+    h, _ = np.histogram(ph, bins=10, range=(-math.pi, math.pi))
+    assert float(((h - e) ** 2 / e).sum()) < 9 + 5 * math.sqrt(18)
+
+
+def test_collision_draw_is_keyed_by_id_and_step(orc):
+    """Same (id, step, seed, run) gives the same event and direction."""
+    thr = orc.collision_threshold(5.0, 0.1)      # P ~ 0.39
+    u = np.array([0.1, 0.2, -0.3])
+    a = orc.collide(u, 17, 5, 99, 0, thr)
+    b = orc.collide(u, 17, 5, 99, 0, thr)
+    assert a[1] == b[1] and np.array_equal(a[0], b[0])
+    hits = [orc.collide(u, i, 5, 99, 0, thr)[1] for i in range(2000)]
+    assert 0.33 < np.mean(hits) < 0.45
+
+
+# --------------------------------------------------------------------------- inputs
+def test_synthetic_load_properties():
+    """Exactly ppc particles per cell and species, zero mean transverse
+    momentum, zero realised net current, unique ids."""
+    wl = synth.beam_plasma((16, 16), ppc=16, u_th_beam=0.3, nu=0.05)
+    parts = synth.load(wl)
+    for sc, p in zip(wl.species, parts):
+        ix = np.floor(p.x[0] / wl.d[0]).astype(int)
+        iy = np.floor(p.x[1] / wl.d[1]).astype(int)
+        counts = np.bincount(iy * wl.n[0] + ix, minlength=wl.cells)
+        assert np.all(counts == sc.ppc)
+        assert abs(p.u[0].mean()) < 1e-15 and abs(p.u[1].mean()) < 1e-15
+    assert abs(synth.net_current_z(parts, wl.species)) < 1e-12
+    ids = np.concatenate([p.id for p in parts])
+    assert len(np.unique(ids)) == len(ids)
+    assert abs(parts[1].u[2].mean() - synth.cold_return_drift()) < 0.01
