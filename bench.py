@@ -1,0 +1,191 @@
+"""Throughput of the beam-plasma PIC step on one MI355X.
+
+Workload (the headline configuration): 2D3V periodic 1024 x 1024 grid,
+dx = 0.2 c/w_p, dt = 0.1/w_p, 64 particles per cell per species (beam n_b =
+0.1 n0 at gamma = 3 with u_th = 0.3 m c; return-current plasma 0.9 n0, u_th =
+0.01 m c, scattering off the ions at nu = 0.05 w_p), 134,217,728 particles,
+mixed precision.  The same workload in FP64 (the plain-method baseline) is
+timed beside it.  A step is the whole hot path: gather, Boris push, move,
+Esirkepov deposit, scattering, tile binning, FP64 current reduction, Yee
+update, diagnostics every 10 steps.  Inputs are generated on the device
+before the timed region.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs
+on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (gather+push+deposit), mixed-FP32 vs FP64, 2D 1024^2 64 ppc"
+HBM_PEAK_GBS = 8000.0
+
+
+def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
+    """Algorithmic HBM bytes of one particle-kernel launch: every particle's
+    state read once and written once (mixed: int32 cell, 2 FP32 offsets,
+    3 FP32 momenta = 24 B; FP64: 2 FP64 positions, 3 FP64 momenta = 40 B),
+    the 4-byte id read for collisional particles (it keys their draw), plus
+    each tile's E/B halo stage and its partial-current write."""
+    r = 4 if precision == "mixed" else 8
+    state = (3 * r + 4 * 3) if precision == "mixed" else 5 * 8
+    total = 0.0
+    for sc in wl.species:
+        n = wl.cells * sc.ppc
+        total += n * 2 * state + (n * 4 if sc.nu > 0 else 0)
+    tiles = wl.cells // (tile * tile)
+    total += tiles * (6 * (tile + 2) ** 2 * r + 3 * (tile + 3) ** 2 * r)
+    return total
+
+
+def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int):
+    import torch
+    from paper_0808_4078_amd import pic
+
+    prec = pic.PIC_PREC_MIXED if precision == "mixed" else pic.PIC_PREC_FP64
+    g, sp = pic.workload_descs(wl, precision=prec, tile=tile, diag_every=diag_every)
+    t0 = time.time()
+    run = pic.Run(g, sp)
+    run.sync()
+    init_s = time.time() - t0
+    run.step(warmup)
+    run.sync()
+    stream = run.stream
+    # timed region: the K steps as replayed graphs
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    run.sync()
+    graph_ms = e0.elapsed_time(e1)
+    # the same K steps launched one by one with HIP events around each kernel group
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    groups = run.step_profiled(steps)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    prof_ms = p0.elapsed_time(p1)
+    diag = run.diagnostics()
+    n = int(sum(wl.cells * s.ppc for s in wl.species))
+    out = dict(particles=n, init_s=init_s, graph_ms=graph_ms, profiled_ms=prof_ms, groups_ms=groups,
+               diag=diag, device_bytes=run.device_bytes)
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
+    """The FP64 oracle on a bounded sample of the workload: a 256 x 256 box
+    with the same per-cell load and physics, timed for whole steps until
+    about target_s seconds have passed."""
+    import oracle
+    import synth
+    from dataclasses import replace
+
+    sample = replace(wl, n=(256, 256), name=wl.name + "-256^2-sample")
+    parts = synth.load(sample)
+    sp = [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x, p.u, p.id) for sc, p in zip(sample.species, parts)]
+    run = oracle.OracleRun(sample.ndim, sample.n, sample.d, sample.dt, sp, sample.seed)
+    run.step(1)
+    n = sample.particles
+    steps = 0
+    t0 = time.time()
+    while steps < max_steps and (time.time() - t0) < target_s:
+        run.step(1)
+        steps += 1
+    dt = time.time() - t0
+    return dict(value=n * steps / dt, unit="particle-steps/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"2D3V 256x256 box of the same workload ({n} particles, 64 ppc/species, same "
+                       f"physics), {steps} FP64 oracle steps in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--diag-every", type=int, default=10)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="256^2 grid instead of 1024^2 (for profiling)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: --gpus {a.gpus} refused: this PIC build runs on a single GPU "
+              "(multi-GPU domain decomposition is not built)", file=sys.stderr)
+        sys.exit(2)
+    import synth
+    from dataclasses import replace
+
+    wl = synth.C3
+    if a.quick:
+        wl = replace(wl, n=(256, 256), name="C3-quick-256^2")
+    mixed = run_gpu(wl, "mixed", a.steps, a.warmup, a.tile, a.diag_every)
+    fp64 = None if a.skip_fp64 else run_gpu(replace(wl, name="C2"), "fp64", a.steps, a.warmup, a.tile,
+                                            a.diag_every)
+    n = mixed["particles"]
+    ms_step = mixed["graph_ms"] / a.steps
+    value = n / (ms_step * 1e-3)
+    pk_ms = mixed["groups_ms"]["particle"] / a.steps
+    pk_bytes = particle_kernel_bytes(wl, "mixed", a.tile)
+    achieved = pk_bytes / (pk_ms * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (device-generated seeded load)",
+        "config": {
+            "workload": f"{wl.name}: 2D3V periodic {wl.n[0]}x{wl.n[1]}, dx=0.2, dt=0.1, 64 ppc per species; "
+                        "beam n_b=0.1 gamma=3 u_th=0.3 + return-current plasma 0.9 u_th=0.01 nu=0.05",
+            "particles": n,
+            "precision": "mixed: int32 cell + FP32 offset/momentum/push/tile current; FP64 grid current "
+                         "reduction and diagnostics",
+            "tile": a.tile,
+            "diag_every": a.diag_every,
+            "parallelism": "single GPU",
+        },
+        "particle_kernel": {"ms": pk_ms, "particle_steps_per_s": n / (pk_ms * 1e-3),
+                            "algorithmic_bytes": pk_bytes},
+        "step_breakdown_ms": {k: v / a.steps for k, v in mixed["groups_ms"].items()},
+        "profiled_ms_per_step": mixed["profiled_ms"] / a.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if fp64 is not None:
+        f_ms = fp64["graph_ms"] / a.steps
+        f_pk = fp64["groups_ms"]["particle"] / a.steps
+        f_bytes = particle_kernel_bytes(wl, "fp64", a.tile)
+        rec["fp64"] = {"workload": "C2 (same workload, FP64 throughout)", "value": n / (f_ms * 1e-3),
+                       "ms_per_step": f_ms, "particle_kernel_ms": f_pk,
+                       "particle_kernel_GBs": f_bytes / (f_pk * 1e-3) / 1e9,
+                       "step_breakdown_ms": {k: v / a.steps for k, v in fp64["groups_ms"].items()}}
+        rec["mixed_over_fp64"] = rec["value"] / rec["fp64"]["value"]
+    if not a.skip_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * pic.h -- C ABI of the MI355X beam-plasma particle-in-cell library (libpic.so).
+ *
+ * The library advances the relativistic beam / return-current system of
+ * Karmakar, Kumar, Shvets, Polomarov and Pukhov (arXiv:0808.4078): electron
+ * species drifting along z through a quasi-neutral plasma with an immobile
+ * neutralising ion background (problem statement at the start of the theory
+ * part; the 2D and 3D PIC-simulation paragraphs).  One step is: field gather,
+ * relativistic Boris push, charge-conserving (Esirkepov) current deposit,
+ * isotropic scattering of collisional species off the ions (whose fluid
+ * limit is the drag term of Eq. (3)), and a Yee update of E and B.
+ *
+ * Units are normalised: t in 1/w_p, x in c/w_p, u = gamma v/c, fields
+ * eF/(m c w_p) (the normalisation of the paper's field-energy diagnostic),
+ * densities in n0, charge in e, mass in m_e.
+ *
+ * Conventions for every entry point:
+ *  - Return value: PIC_OK (0) or a negative PIC_E_* code.  No C++ exception
+ *    crosses the ABI.  pic_last_error() gives a message for the last failure
+ *    on a handle.
+ *  - Device memory is owned by the caller.  pic_query() gives the four
+ *    buffer sizes; the caller allocates them on the device that is current
+ *    when pic_init() is called and keeps them alive until pic_destroy().
+ *    The library never allocates or frees device memory.  It keeps small
+ *    host-side state (descriptors, a captured graph) in the handle.
+ *  - Streams are owned by the caller.  Work is enqueued on the stream given
+ *    to pic_init(); entry points marked "synchronising" wait for it.
+ *  - Device-side faults and capacity exhaustion surface as PIC_E_HIP /
+ *    PIC_E_CAPACITY at the next synchronising call.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PIC_OK = 0,
+    PIC_E_INVALID_ARG = -1,      /* bad descriptor, pointer or size */
+    PIC_E_UNSUPPORTED = -2,      /* valid physics, configuration not built */
+    PIC_E_CFL = -3,              /* Courant condition of the scheme violated */
+    PIC_E_BUFFER_TOO_SMALL = -4, /* caller buffer smaller than pic_query's size */
+    PIC_E_HIP = -5,              /* HIP runtime error (launch, copy, device fault) */
+    PIC_E_STATE = -6,            /* call not valid in the handle's current state */
+    PIC_E_CAPACITY = -7          /* particle store overflowed its reserve */
+};
+
+enum { PIC_PREC_FP64 = 0, PIC_PREC_MIXED = 1 };
+
+enum {
+    PIC_FLAG_FREEZE_FIELDS = 1u,  /* skip current reduction and field update (test-particle mode) */
+    PIC_FLAG_NO_COLLIDE = 2u,     /* ignore every species' collision rate */
+    PIC_FLAG_LATTICE_LOAD = 4u,   /* device loader: regular sub-lattice positions */
+    PIC_FLAG_HOST_LOAD = 8u,      /* do not load on the device; caller calls pic_load_particles */
+    PIC_FLAG_NO_GRAPH = 16u,      /* launch kernels one by one instead of replaying a graph */
+    PIC_FLAG_TRACK_IDS = 32u      /* carry particle ids for every species (by default only
+                                     collisional species, whose draws are keyed by id, do) */
+};
+
+#define PIC_MAX_SPECIES 8
+
+/* Grid and run parameters.
+ *   ndim      2 (2D3V: x,y resolved, z ignorable -- the paper's transverse plane)
+ *             or 3 (3D3V).
+ *   n[3]      cells per axis (n[2] ignored in 2D); periodic boundaries.
+ *   d[3]      cell size per axis in c/w_p.
+ *   dt        time step in 1/w_p.  Must satisfy dt <= d_i/2 on every resolved
+ *             axis (a particle crosses at most half a cell per step), which
+ *             also implies the Yee Courant condition.
+ *   precision PIC_PREC_FP64: FP64 positions, momenta, fields and currents.
+ *             PIC_PREC_MIXED: int32 cell index + FP32 in-cell offset, FP32
+ *             momenta, FP32 push and per-tile FP32 current, FP64 grid-level
+ *             current reduction and diagnostics, FP32 E and B.
+ *   seed, run counter-based random stream (Philox4x32-10) key and run index.
+ *   tile[3]   particle tile edge in cells (0 = library default); n must be a
+ *             multiple of the tile.
+ *   diag_every record diagnostics every diag_every steps (0 = never).
+ *   flags     PIC_FLAG_* bits. */
+typedef struct {
+    int32_t ndim;
+    int32_t n[3];
+    double d[3];
+    double dt;
+    int32_t precision;
+    uint64_t seed;
+    uint32_t run;
+    int32_t tile[3];
+    int32_t diag_every;
+    uint32_t flags;
+} pic_grid_desc;
+
+/* One particle species.
+ *   charge, mass        in e and m_e (electrons: -1, 1).
+ *   density             n_s / n0.
+ *   ppc                 macro-particles per cell; weight = density / ppc.  The
+ *                       store is sized for density*cells*ppc particles.
+ *   drift_u, u_th       device loader: u = drift_u + u_th * N(0,1) per component
+ *                       (mean of u_x, u_y removed afterwards).
+ *   cancel_current_of   device loader: shift this species' u_z so the total
+ *                       current sum q w u_z/gamma of all species is zero
+ *                       (the return current neutralising the beam); -1 = no.
+ *   nu_coll             scattering rate off the ions in w_p (0 = collisionless):
+ *                       probability 1 - exp(-nu dt) per step, isotropic, |u| kept. */
+typedef struct {
+    double charge, mass, density;
+    int32_t ppc;
+    double drift_u[3];
+    double u_th;
+    int32_t cancel_current_of;
+    double nu_coll;
+} pic_species_desc;
+
+/* Sizes in bytes of the caller-owned device buffers. */
+typedef struct {
+    size_t particle_bytes[PIC_MAX_SPECIES];
+    size_t field_bytes, scratch_bytes, diag_bytes;
+} pic_sizes;
+
+/* Device pointers (256-byte aligned) of the caller-owned buffers. */
+typedef struct {
+    void *particles[PIC_MAX_SPECIES];
+    void *fields;
+    void *scratch;
+    void *diag;
+} pic_buffers;
+
+/* One diagnostic record for time level `step` (taken while that step runs):
+ *   W[6]           sum over cells of F_i^2 dV for Ex,Ey,Ez,Bx,By,Bz at time step
+ *                  (the paper's per-component field energy, no factor 1/2).
+ *   kinetic[s]     dV sum w (gamma - 1), gamma time-centred at the step.
+ *   p_particles[3] dV sum w u, time-centred, all species.
+ *   p_field_z      dV sum (E x B)_z.
+ *   collisions     scattering events during the step.
+ *   n_particles[s] particles of species s.
+ *   rebins         particle-store re-layouts performed so far. */
+typedef struct {
+    int64_t step;
+    double time;
+    double W[6];
+    double kinetic[PIC_MAX_SPECIES];
+    double p_particles[3];
+    double p_field_z;
+    int64_t collisions;
+    int64_t n_particles[PIC_MAX_SPECIES];
+    int64_t rebins;
+} pic_diag;
+
+typedef struct pic_run pic_run;
+
+/* Host only (touches no device).  Validates the descriptors and returns the
+ * buffer sizes.  Errors: INVALID_ARG (null pointer, nspecies out of 1..8,
+ * n or ppc <= 0, n not a multiple of the tile), CFL, UNSUPPORTED. */
+int pic_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+              pic_sizes *out);
+
+/* Binds the caller's buffers (sizes checked against pic_query), zeroes the
+ * fields, lays out the particle store and, unless PIC_FLAG_HOST_LOAD, loads
+ * the species on the device (exactly ppc per cell, uniform in-cell positions,
+ * Gaussian momenta, mean transverse momentum removed, net current cancelled by
+ * a Newton shift in FP64).  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  Synchronising.  On success *out owns host state only. */
+int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+             const pic_buffers *buffers, void *hip_stream, pic_run **out);
+
+/* Test path: replaces species s with n host particles.  x is FP64 SoA
+ * [ndim][n] in c/w_p (wrapped into the box), u is FP64 SoA [3][n], id is
+ * [n] uint32 (keys the collision draw).  n must not exceed ppc * cells of
+ * the species.  Synchronising. */
+int pic_load_particles(pic_run *run, int species, const double *x, const double *u,
+                       const uint32_t *id, int64_t n);
+
+/* Enqueues nsteps full steps on the bound stream (asynchronous). */
+int pic_step(pic_run *run, int32_t nsteps);
+
+/* Measurement path: enqueues nsteps full steps exactly as pic_step but with
+ * individual launches bracketed by HIP events on the bound stream, waits for
+ * them, and adds each kernel group's elapsed milliseconds into group_ms[6]:
+ * [0] field diagnostics, [1] particle kernel (gather, push, move, deposit,
+ * scattering, binning), [2] store re-layout, [3] current reduction,
+ * [4] Yee update, [5] end-of-step bookkeeping.  Synchronising. */
+int pic_step_profiled(pic_run *run, int32_t nsteps, double *group_ms);
+
+/* Waits for the bound stream; reports device-side capacity failures. */
+int pic_sync(pic_run *run);
+
+/* Synchronising.  Copies the most recent diagnostic record; PIC_E_STATE if
+ * none has been recorded yet. */
+int pic_diagnostics(pic_run *run, pic_diag *out);
+
+/* Synchronising.  Copies up to `max` of the most recent records, oldest first
+ * (the device ring keeps the last 4096); *count receives the number copied. */
+int pic_diag_history(pic_run *run, pic_diag *out, int64_t max, int64_t *count);
+
+/* Synchronising.  FP64 host copies of the grid planes, each n0*n1*n2 values,
+ * [n2][n1][n0] x fastest, half-integer positions stored at the lower index:
+ * E and B: [3][cells] (Ex,Ey,Ez / Bx,By,Bz), J: [3][cells] of the last step.
+ * Any pointer may be NULL. */
+int pic_read_fields(pic_run *run, double *E, double *B, double *J);
+
+/* Synchronising.  Overwrites E and B from FP64 host planes (layout as above;
+ * either may be NULL). */
+int pic_write_fields(pic_run *run, const double *E, const double *B);
+
+/* Synchronising.  Copies species s out: x FP64 [ndim][cap] in c/w_p, u FP64
+ * [3][cap], id [cap]; *count receives the particle number (PIC_E_BUFFER_TOO_SMALL
+ * if it exceeds cap).  Order is the store's order, not id order. */
+int pic_read_particles(pic_run *run, int species, double *x, double *u, uint32_t *id,
+                       int64_t cap, int64_t *count);
+
+/* Host only.  Frees the handle's host state (not the caller's buffers). */
+int pic_destroy(pic_run *run);
+
+/* Static string for a status code. */
+const char *pic_status_string(int status);
+
+/* Copies the last error message of the handle (or of the last failed
+ * pic_init / pic_query when run is NULL) into buf. */
+int pic_last_error(pic_run *run, char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

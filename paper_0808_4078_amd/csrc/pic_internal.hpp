@@ -1,0 +1,115 @@
+// Internal layout shared by the HIP kernels and the host runtime of libpic.
+//
+// Everything the kernels need lives in one device-resident KParams block
+// written once at initialisation, so a step is a fixed sequence of launches
+// with pointer-only arguments (replayable as a graph).  Per-step mutable
+// state (step counter, particle-set parity, overflow flags) is in DevState,
+// also in device memory, and is advanced by the last kernel of each step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = PIC_MAX_SPECIES;
+constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
+constexpr int kRing = 4096;          // diagnostic records kept on the device
+constexpr int kTileDiag = 6;         // per tile and species: KE, px, py, pz, count, collisions
+constexpr int kFieldDiag = 8;        // per block: W[6], p_field_z, unused
+constexpr int kFieldDiagBlocks = 512;
+constexpr int kMomentBlocks = 1024;  // loader reductions
+constexpr int kMomentVals = 6;
+
+// Philox counter word 2 tags the purpose of a draw.
+constexpr uint32_t kPurposeCollide = 1u;
+constexpr uint32_t kPurposeLoad = 2u;
+
+struct DevState {
+    int64_t step;        // index n of the step about to run
+    int32_t par;         // particle set holding the current particles (0/1)
+    int32_t rebin;       // an incoming-mover reserve overflowed during this step
+    int32_t fatal;       // sticky: the overflow list itself was exhausted
+    int32_t pad;
+    int64_t rebins;      // re-layouts performed so far
+    int64_t ring_head;   // diagnostic records written so far
+    uint32_t ovf_count[kMaxSpecies];
+};
+
+// Particle arrays of one species.  Sets 0 and 1 alternate as source and
+// destination from step to step; set 2 is the overflow list.
+//  mixed: cell (packed ix | iy << sh1 | iz << sh2), pos = FP32 in-cell offset
+//  fp64 : cell unused, pos = absolute FP64 position in cell units
+struct SpeciesDev {
+    uint32_t *cell[3];
+    void *pos[3][3];     // [set][axis]
+    void *u[3][3];       // [set][component]
+    uint32_t *id[3];
+    int32_t *start;      // [tiles] first slot of each tile's bin
+    int32_t *cap;        // [tiles] bin capacity
+    uint32_t *cnt_front; // [2][tiles] particles written from the bin's front
+    uint32_t *cnt_back;  // [2][tiles] movers written from the bin's back
+    int64_t ncap;        // slots per set
+    int64_t nominal;     // ppc * cells
+    uint32_t ovf_cap;
+    uint32_t coll_thr;   // scatter when the 32-bit draw is below this
+    int32_t collide;
+    int32_t track_id;    // carry ids (collisional species, or all in test mode)
+    double q, m, w;
+    double qmdt2;        // q dt / (2 m)
+    double qw;           // q w
+    int32_t ppc;
+    int32_t id_base;
+    double drift[3];     // loader: mean momentum
+    double uth;          // loader: Gaussian spread per component
+};
+
+struct Geometry {
+    int ndim;
+    int n[3];
+    double d[3];
+    double dt;
+    int tile[3];
+    int nt[3];           // tiles per axis
+    int ntiles;
+    int tshift[3];       // log2(tile)
+    int csh[3];          // cell packing shifts (mixed)
+    uint32_t cmask[3];
+    int64_t cells;
+};
+
+struct KParams {
+    Geometry g;
+    int nspecies;
+    int precision;       // PIC_PREC_*
+    int diag_every;
+    unsigned flags;
+    uint64_t seed;
+    uint32_t run;
+    SpeciesDev sp[kMaxSpecies];
+    void *F;             // 6 planes Ex Ey Ez Bx By Bz (float or double)
+    double *J;           // 3 planes
+    void *Jtile;         // [tiles][3][nj^ndim] per-tile partial currents
+    int nj;              // tile edge + 3
+    double *tile_diag;   // [tiles][nspecies][kTileDiag]
+    double *field_diag;  // [kFieldDiagBlocks][kFieldDiag]
+    double *moments;     // [kMomentBlocks][kMomentVals]
+    DevState *state;
+    pic_diag *ring;      // [kRing]
+    int32_t *rb_count;   // [nspecies][tiles]
+    int32_t *rb_start;   // [nspecies][tiles]
+    int32_t *rb_cap;     // [nspecies][tiles]
+    int32_t *rb_fill;    // [nspecies][tiles]
+};
+
+// Host-callable launchers (defined in the .hip translation units).
+constexpr int kNumGroups = 6;        // field-diag, particle, re-layout, reduction, Yee, advance
+hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
+hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
+hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);
+hipError_t launch_shift_u(const KParams &hp, const KParams *dp, int s, double dux, double duy,
+                          double duz, hipStream_t st);
+
+}  // namespace pic

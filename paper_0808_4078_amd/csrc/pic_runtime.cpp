@@ -1,0 +1,799 @@
+// Host runtime of libpic: the C ABI declared in include/pic.h.
+//
+// It validates descriptors, carves the caller-owned device buffers into the
+// particle store, field planes and scratch, writes the device-resident
+// KParams block, runs the device loader, and enqueues steps (as a captured
+// graph replay unless PIC_FLAG_NO_GRAPH).  It never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic_internal.hpp"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Layout {
+    size_t particle_bytes[kMaxSpecies] = {};
+    size_t field_bytes = 0, scratch_bytes = 0, diag_bytes = 0;
+    // offsets inside the particle buffer of each species
+    struct Sp {
+        size_t cell[3], pos[3][3], u[3][3], id[3];
+        size_t start, cap, cnt_front, cnt_back;
+        int64_t ncap, nominal, tile_nominal, reserve;
+        uint32_t ovf_cap;
+    } sp[kMaxSpecies];
+    size_t F, J;                                            // field buffer
+    size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4];   // scratch
+    Geometry g;
+    int nj;
+    size_t real;                                            // sizeof(float|double)
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; }
+};
+
+int ilog2_exact(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return (1 << b) == v ? b : -1;
+}
+
+int bits_for(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+int fail(std::string *err, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (err) *err = buf;
+    g_last_error = buf;
+    return code;
+}
+
+int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout *L, std::string *err)
+{
+    if (!g || !sp) return fail(err, PIC_E_INVALID_ARG, "null descriptor");
+    if (ns < 1 || ns > kMaxSpecies) return fail(err, PIC_E_INVALID_ARG, "nspecies %d out of 1..%d", ns, kMaxSpecies);
+    if (g->ndim != 2 && g->ndim != 3) return fail(err, PIC_E_INVALID_ARG, "ndim %d", g->ndim);
+    if (g->ndim == 3) return fail(err, PIC_E_UNSUPPORTED, "3D runs are not built in this library version");
+    if (g->precision != PIC_PREC_FP64 && g->precision != PIC_PREC_MIXED)
+        return fail(err, PIC_E_INVALID_ARG, "precision %d", g->precision);
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(err, PIC_E_INVALID_ARG, "dt must be positive");
+    if (g->diag_every < 0) return fail(err, PIC_E_INVALID_ARG, "diag_every < 0");
+    Geometry &G = L->g;
+    memset(&G, 0, sizeof(G));
+    G.ndim = g->ndim;
+    G.dt = g->dt;
+    G.ntiles = 1;
+    G.cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= g->ndim) {
+            G.n[a] = 1;
+            G.d[a] = 1.0;
+            G.tile[a] = 1;
+            G.nt[a] = 1;
+            continue;
+        }
+        if (g->n[a] <= 0) return fail(err, PIC_E_INVALID_ARG, "n[%d] = %d", a, g->n[a]);
+        if (!(g->d[a] > 0.0) || !std::isfinite(g->d[a])) return fail(err, PIC_E_INVALID_ARG, "d[%d] must be positive", a);
+        if (g->dt > 0.5 * g->d[a] * (1.0 + 1e-12))
+            return fail(err, PIC_E_CFL, "dt %.6g exceeds d[%d]/2 = %.6g (a particle must cross less than half a cell per step)",
+                        g->dt, a, 0.5 * g->d[a]);
+        int t = g->tile[a];
+        if (t == 0) {
+            // largest of 16, 8 that divides every resolved axis (tiles are cubes)
+            t = 16;
+            for (int b = 0; b < g->ndim; ++b)
+                if (g->n[b] > 0 && g->n[b] % 16) t = 8;
+        }
+        if (t != 8 && t != 16 && t != 32) return fail(err, PIC_E_UNSUPPORTED, "tile %d not in {8,16,32}", t);
+        if (g->n[a] % t) return fail(err, PIC_E_INVALID_ARG, "n[%d] = %d is not a multiple of the tile %d", a, g->n[a], t);
+        G.n[a] = g->n[a];
+        G.d[a] = g->d[a];
+        G.tile[a] = t;
+        G.nt[a] = g->n[a] / t;
+        G.tshift[a] = ilog2_exact(t);
+        G.ntiles *= G.nt[a];
+        G.cells *= g->n[a];
+    }
+    if (g->ndim == 2 && G.tile[0] != G.tile[1]) return fail(err, PIC_E_UNSUPPORTED, "tiles must be square");
+    // packed cell index of the mixed mode
+    int used = 0;
+    for (int a = 0; a < g->ndim; ++a) {
+        G.csh[a] = used;
+        const int b = bits_for(G.n[a]);
+        G.cmask[a] = (b >= 32) ? 0xFFFFFFFFu : ((1u << b) - 1u);
+        used += b;
+    }
+    if (used > 32) return fail(err, PIC_E_UNSUPPORTED, "grid too large for the packed 32-bit cell index");
+    const int64_t tile_cells = (int64_t)G.tile[0] * G.tile[1] * G.tile[2];
+    int64_t id_total = 0;
+    for (int s = 0; s < ns; ++s) {
+        const pic_species_desc &S = sp[s];
+        if (S.ppc <= 0) return fail(err, PIC_E_INVALID_ARG, "species %d: ppc %d", s, S.ppc);
+        if (!(S.mass > 0.0)) return fail(err, PIC_E_INVALID_ARG, "species %d: mass must be positive", s);
+        if (!(S.density >= 0.0)) return fail(err, PIC_E_INVALID_ARG, "species %d: density must be >= 0", s);
+        if (S.nu_coll < 0.0) return fail(err, PIC_E_INVALID_ARG, "species %d: nu_coll < 0", s);
+        if (!(S.u_th >= 0.0)) return fail(err, PIC_E_INVALID_ARG, "species %d: u_th < 0", s);
+        if (S.cancel_current_of >= ns || S.cancel_current_of < -1)
+            return fail(err, PIC_E_INVALID_ARG, "species %d: cancel_current_of %d", s, S.cancel_current_of);
+        Layout::Sp &P = L->sp[s];
+        P.tile_nominal = (int64_t)S.ppc * tile_cells;
+        P.nominal = P.tile_nominal * G.ntiles;
+        P.reserve = std::max<int64_t>(64, (P.tile_nominal + 3) / 4);
+        P.ncap = (P.tile_nominal + P.reserve) * G.ntiles;
+        if (P.ncap >= ((int64_t)1 << 31)) return fail(err, PIC_E_UNSUPPORTED, "species %d: store exceeds 2^31 slots", s);
+        P.ovf_cap = (uint32_t)std::max<int64_t>(4096, P.ncap / 8);
+        id_total += P.nominal;
+    }
+    if (id_total > 0xFFFFFFFFll) return fail(err, PIC_E_UNSUPPORTED, "more than 2^32 particles: ids do not fit");
+    L->real = g->precision == PIC_PREC_MIXED ? 4 : 8;
+    L->nj = G.tile[0] + 3;
+    // particle buffers
+    for (int s = 0; s < ns; ++s) {
+        Layout::Sp &P = L->sp[s];
+        Carver c;
+        for (int set = 0; set < 3; ++set) {
+            const size_t n = set < 2 ? (size_t)P.ncap : P.ovf_cap;
+            P.cell[set] = L->real == 4 ? c.take(n * 4) : 0;
+            for (int a = 0; a < 3; ++a) P.pos[set][a] = a < g->ndim ? c.take(n * L->real) : 0;
+            for (int a = 0; a < 3; ++a) P.u[set][a] = c.take(n * L->real);
+            P.id[set] = c.take(n * 4);
+        }
+        P.start = c.take((size_t)G.ntiles * 4);
+        P.cap = c.take((size_t)G.ntiles * 4);
+        P.cnt_front = c.take((size_t)G.ntiles * 8);
+        P.cnt_back = c.take((size_t)G.ntiles * 8);
+        L->particle_bytes[s] = c.off;
+    }
+    {
+        Carver c;
+        L->F = c.take((size_t)G.cells * 6 * L->real);
+        L->J = c.take((size_t)G.cells * 3 * 8);
+        L->field_bytes = c.off;
+    }
+    {
+        Carver c;
+        int64_t nj_cells = 1;
+        for (int a = 0; a < g->ndim; ++a) nj_cells *= L->nj;
+        L->Jtile = c.take((size_t)G.ntiles * 3 * nj_cells * L->real);
+        L->tile_diag = c.take((size_t)G.ntiles * ns * kTileDiag * 8);
+        L->field_diag = c.take((size_t)kFieldDiagBlocks * kFieldDiag * 8);
+        L->moments = c.take((size_t)kMomentBlocks * kMomentVals * 8);
+        L->state = c.take(sizeof(DevState));
+        L->kparams = c.take(sizeof(KParams));
+        for (int i = 0; i < 4; ++i) L->rb[i] = c.take((size_t)ns * G.ntiles * 4);
+        L->scratch_bytes = c.off;
+    }
+    L->diag_bytes = align256(sizeof(pic_diag) * kRing);
+    return PIC_OK;
+}
+
+}  // namespace
+
+struct pic_run {
+    pic_grid_desc grid;
+    pic_species_desc species[kMaxSpecies];
+    int ns = 0;
+    Layout L;
+    pic_buffers buf;
+    hipStream_t stream = nullptr;
+    KParams hp;                 // host copy of the device-resident parameters
+    KParams *dp = nullptr;      // device copy (inside scratch)
+    int64_t steps_enqueued = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int hip_fail(pic_run *r, hipError_t e, const char *what)
+{
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    if (r) r->err = buf;
+    g_last_error = buf;
+    return PIC_E_HIP;
+}
+
+#define HIPCHK(r, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(r, e_, #expr); \
+    } while (0)
+
+char *at(void *base, size_t off) { return (char *)base + off; }
+
+// Uniform bin layout: capacity tile_nominal + reserve per tile.
+void uniform_bins(const Layout::Sp &P, int ntiles, std::vector<int32_t> &start, std::vector<int32_t> &cap)
+{
+    start.resize(ntiles);
+    cap.resize(ntiles);
+    for (int t = 0; t < ntiles; ++t) {
+        cap[t] = (int32_t)(P.tile_nominal + P.reserve);
+        start[t] = (int32_t)((int64_t)t * cap[t]);
+    }
+}
+
+int upload_bins(pic_run *r, int s, const std::vector<int32_t> &start, const std::vector<int32_t> &cap,
+                const std::vector<uint32_t> &front0)
+{
+    const int nt = r->L.g.ntiles;
+    const Layout::Sp &P = r->L.sp[s];
+    void *b = r->buf.particles[s];
+    std::vector<uint32_t> zeros((size_t)2 * nt, 0u), fr((size_t)2 * nt, 0u);
+    std::copy(front0.begin(), front0.end(), fr.begin());
+    HIPCHK(r, hipMemcpyAsync(at(b, P.start), start.data(), nt * 4, hipMemcpyHostToDevice, r->stream));
+    HIPCHK(r, hipMemcpyAsync(at(b, P.cap), cap.data(), nt * 4, hipMemcpyHostToDevice, r->stream));
+    HIPCHK(r, hipMemcpyAsync(at(b, P.cnt_front), fr.data(), (size_t)2 * nt * 4, hipMemcpyHostToDevice, r->stream));
+    HIPCHK(r, hipMemcpyAsync(at(b, P.cnt_back), zeros.data(), (size_t)2 * nt * 4, hipMemcpyHostToDevice, r->stream));
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    return PIC_OK;
+}
+
+int read_state(pic_run *r, DevState *st)
+{
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipMemcpy(st, at(r->buf.scratch, r->L.state), sizeof(DevState), hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int check_fatal(pic_run *r, const DevState &st)
+{
+    if (st.fatal & 1) { r->err = "particle overflow list exhausted"; return PIC_E_CAPACITY; }
+    if (st.fatal & 4) { r->err = "particle store reserve exhausted"; return PIC_E_CAPACITY; }
+    if (st.fatal & 2) { r->err = "particle left the grid (corrupt state)"; return PIC_E_HIP; }
+    return PIC_OK;
+}
+
+int moments(pic_run *r, int s, double delta, double out[kMomentVals])
+{
+    HIPCHK(r, launch_moments(r->hp, r->dp, s, delta, r->stream));
+    std::vector<double> h((size_t)kMomentBlocks * kMomentVals);
+    HIPCHK(r, hipMemcpyAsync(h.data(), at(r->buf.scratch, r->L.moments), h.size() * 8, hipMemcpyDeviceToHost,
+                             r->stream));
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    for (int v = 0; v < kMomentVals; ++v) {
+        double a = 0.0;
+        for (int b = 0; b < kMomentBlocks; ++b) a += h[(size_t)b * kMomentVals + v];
+        out[v] = a;
+    }
+    return PIC_OK;
+}
+
+// Loader post-processing: remove mean u_x, u_y per species; Newton shift of
+// the cancelling species' u_z so that sum_s q_s w_s sum u_z/gamma = 0.
+int loader_moments(pic_run *r)
+{
+    double m[kMomentVals];
+    for (int s = 0; s < r->ns; ++s) {
+        int rc = moments(r, s, 0.0, m);
+        if (rc) return rc;
+        if (m[5] > 0) {
+            HIPCHK(r, launch_shift_u(r->hp, r->dp, s, -m[0] / m[5], -m[1] / m[5], 0.0, r->stream));
+        }
+    }
+    for (int c = 0; c < r->ns; ++c) {
+        if (r->species[c].cancel_current_of < 0) continue;
+        const double qwc = r->hp.sp[c].qw;
+        if (qwc == 0.0) continue;
+        for (int round = 0; round < 2; ++round) {
+            double other = 0.0;
+            for (int s = 0; s < r->ns; ++s) {
+                if (s == c) continue;
+                int rc = moments(r, s, 0.0, m);
+                if (rc) return rc;
+                other += r->hp.sp[s].qw * m[4];
+            }
+            int rc = moments(r, c, 0.0, m);
+            if (rc) return rc;
+            const double nc = std::max(m[5], 1.0);
+            double vt = -other / (qwc * nc);
+            vt = std::max(-0.99, std::min(0.99, vt));
+            double delta = round == 0 ? vt / std::sqrt(1.0 - vt * vt) - r->species[c].drift_u[2] : 0.0;
+            for (int it = 0; it < 60; ++it) {
+                rc = moments(r, c, delta, m);
+                if (rc) return rc;
+                const double f = other + qwc * m[2];
+                const double fp = qwc * m[3];
+                if (fp == 0.0) break;
+                const double step = f / fp;
+                delta -= step;
+                if (std::fabs(step) <= 1e-16 * std::max(1.0, std::fabs(delta))) break;
+            }
+            HIPCHK(r, launch_shift_u(r->hp, r->dp, c, 0.0, 0.0, delta, r->stream));
+        }
+    }
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    return PIC_OK;
+}
+
+int capture_graph(pic_run *r)
+{
+    hipStream_t cs;
+    HIPCHK(r, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipError_t le = launch_step(r->hp, r->dp, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) r->graph = g;
+            else (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        r->gexec = nullptr;
+        r->graph = nullptr;
+        (void)hipGetLastError();
+    }
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_status_string(int status)
+{
+    switch (status) {
+    case PIC_OK: return "ok";
+    case PIC_E_INVALID_ARG: return "invalid argument";
+    case PIC_E_UNSUPPORTED: return "unsupported configuration";
+    case PIC_E_CFL: return "time step violates the Courant condition";
+    case PIC_E_BUFFER_TOO_SMALL: return "buffer too small";
+    case PIC_E_HIP: return "HIP runtime error";
+    case PIC_E_STATE: return "invalid state for this call";
+    case PIC_E_CAPACITY: return "particle store capacity exceeded";
+    default: return "unknown status";
+    }
+}
+
+int pic_last_error(pic_run *run, char *buf, size_t n)
+{
+    if (!buf || n == 0) return PIC_E_INVALID_ARG;
+    const std::string &m = run ? run->err : g_last_error;
+    snprintf(buf, n, "%s", m.c_str());
+    return PIC_OK;
+}
+
+int pic_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, pic_sizes *out)
+{
+    if (!out) return fail(nullptr, PIC_E_INVALID_ARG, "null output");
+    Layout L;
+    const int rc = validate(grid, species, nspecies, &L, nullptr);
+    if (rc) return rc;
+    memset(out, 0, sizeof(*out));
+    for (int s = 0; s < nspecies; ++s) out->particle_bytes[s] = L.particle_bytes[s];
+    out->field_bytes = L.field_bytes;
+    out->scratch_bytes = L.scratch_bytes;
+    out->diag_bytes = L.diag_bytes;
+    return PIC_OK;
+}
+
+int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+             const pic_buffers *buffers, void *hip_stream, pic_run **out)
+{
+    if (!out || !buffers) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    pic_run *r = new (std::nothrow) pic_run();
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "host allocation failed");
+    int rc = validate(grid, species, nspecies, &r->L, &r->err);
+    if (rc) { delete r; return rc; }
+    for (int s = 0; s < nspecies; ++s)
+        if (!buffers->particles[s]) { delete r; return fail(nullptr, PIC_E_INVALID_ARG, "null particle buffer %d", s); }
+    if (!buffers->fields || !buffers->scratch || !buffers->diag) {
+        delete r;
+        return fail(nullptr, PIC_E_INVALID_ARG, "null field, scratch or diag buffer");
+    }
+    r->grid = *grid;
+    r->ns = nspecies;
+    for (int s = 0; s < nspecies; ++s) r->species[s] = species[s];
+    r->buf = *buffers;
+    r->stream = (hipStream_t)hip_stream;
+    const Layout &L = r->L;
+
+    KParams &K = r->hp;
+    memset(&K, 0, sizeof(K));
+    K.g = L.g;
+    K.nspecies = nspecies;
+    K.precision = grid->precision;
+    K.diag_every = grid->diag_every;
+    K.flags = grid->flags;
+    K.seed = grid->seed;
+    K.run = grid->run;
+    K.nj = L.nj;
+    int64_t id_base = 0;
+    for (int s = 0; s < nspecies; ++s) {
+        const pic_species_desc &S = species[s];
+        const Layout::Sp &P = L.sp[s];
+        SpeciesDev &D = K.sp[s];
+        void *b = buffers->particles[s];
+        for (int set = 0; set < 3; ++set) {
+            D.cell[set] = L.real == 4 ? (uint32_t *)at(b, P.cell[set]) : nullptr;
+            for (int a = 0; a < 3; ++a) D.pos[set][a] = a < grid->ndim ? at(b, P.pos[set][a]) : nullptr;
+            for (int a = 0; a < 3; ++a) D.u[set][a] = at(b, P.u[set][a]);
+            D.id[set] = (uint32_t *)at(b, P.id[set]);
+        }
+        D.start = (int32_t *)at(b, P.start);
+        D.cap = (int32_t *)at(b, P.cap);
+        D.cnt_front = (uint32_t *)at(b, P.cnt_front);
+        D.cnt_back = (uint32_t *)at(b, P.cnt_back);
+        D.ncap = P.ncap;
+        D.nominal = P.nominal;
+        D.ovf_cap = P.ovf_cap;
+        D.collide = (S.nu_coll > 0.0 && !(grid->flags & PIC_FLAG_NO_COLLIDE)) ? 1 : 0;
+        D.track_id = (D.collide || (grid->flags & PIC_FLAG_TRACK_IDS)) ? 1 : 0;
+        const double P_coll = 1.0 - std::exp(-S.nu_coll * grid->dt);
+        const double thr = std::floor(P_coll * 4294967296.0);
+        D.coll_thr = D.collide ? (uint32_t)std::min(4294967295.0, std::max(0.0, thr)) : 0u;
+        D.q = S.charge;
+        D.m = S.mass;
+        D.w = S.density / S.ppc;
+        D.qmdt2 = S.charge * grid->dt / (2.0 * S.mass);
+        D.qw = S.charge * D.w;
+        D.ppc = S.ppc;
+        D.id_base = (int32_t)id_base;
+        for (int c = 0; c < 3; ++c) D.drift[c] = S.drift_u[c];
+        D.uth = S.u_th;
+        id_base += P.nominal;
+    }
+    K.F = at(buffers->fields, L.F);
+    K.J = (double *)at(buffers->fields, L.J);
+    K.Jtile = at(buffers->scratch, L.Jtile);
+    K.tile_diag = (double *)at(buffers->scratch, L.tile_diag);
+    K.field_diag = (double *)at(buffers->scratch, L.field_diag);
+    K.moments = (double *)at(buffers->scratch, L.moments);
+    K.state = (DevState *)at(buffers->scratch, L.state);
+    K.ring = (pic_diag *)buffers->diag;
+    K.rb_count = (int32_t *)at(buffers->scratch, L.rb[0]);
+    K.rb_start = (int32_t *)at(buffers->scratch, L.rb[1]);
+    K.rb_cap = (int32_t *)at(buffers->scratch, L.rb[2]);
+    K.rb_fill = (int32_t *)at(buffers->scratch, L.rb[3]);
+    r->dp = (KParams *)at(buffers->scratch, L.kparams);
+
+#define INIT_CHK(expr)                                          \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) {                                 \
+            int c_ = hip_fail(r, e_, #expr);                    \
+            delete r;                                           \
+            return c_;                                          \
+        }                                                       \
+    } while (0)
+    INIT_CHK(hipMemcpyAsync(r->dp, &K, sizeof(K), hipMemcpyHostToDevice, r->stream));
+    INIT_CHK(hipMemsetAsync(buffers->fields, 0, L.field_bytes, r->stream));
+    INIT_CHK(hipMemsetAsync(K.Jtile, 0, L.tile_diag - L.Jtile, r->stream));
+    INIT_CHK(hipMemsetAsync(K.tile_diag, 0, L.state - L.tile_diag, r->stream));
+    INIT_CHK(hipMemsetAsync(buffers->diag, 0, L.diag_bytes, r->stream));
+    DevState st0;
+    memset(&st0, 0, sizeof(st0));
+    INIT_CHK(hipMemcpyAsync(K.state, &st0, sizeof(st0), hipMemcpyHostToDevice, r->stream));
+    for (int s = 0; s < nspecies; ++s) {
+        std::vector<int32_t> start, cap;
+        uniform_bins(L.sp[s], L.g.ntiles, start, cap);
+        const bool load = !(grid->flags & PIC_FLAG_HOST_LOAD);
+        std::vector<uint32_t> front((size_t)L.g.ntiles, load ? (uint32_t)L.sp[s].tile_nominal : 0u);
+        rc = upload_bins(r, s, start, cap, front);
+        if (rc) { delete r; return rc; }
+        if (load) INIT_CHK(launch_load_species(K, r->dp, s, r->stream));
+    }
+    if (!(grid->flags & PIC_FLAG_HOST_LOAD)) {
+        rc = loader_moments(r);
+        if (rc) { delete r; return rc; }
+    }
+    INIT_CHK(hipStreamSynchronize(r->stream));
+    if (!(grid->flags & PIC_FLAG_NO_GRAPH)) capture_graph(r);
+    *out = r;
+    return PIC_OK;
+}
+
+int pic_load_particles(pic_run *r, int s, const double *x, const double *u, const uint32_t *id, int64_t n)
+{
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    if (s < 0 || s >= r->ns) return fail(&r->err, PIC_E_INVALID_ARG, "species %d", s);
+    if (n < 0 || (n > 0 && (!x || !u || !id))) return fail(&r->err, PIC_E_INVALID_ARG, "bad particle arrays");
+    const Layout &L = r->L;
+    const Layout::Sp &P = L.sp[s];
+    if (n > P.nominal) return fail(&r->err, PIC_E_BUFFER_TOO_SMALL, "n = %lld exceeds ppc*cells = %lld",
+                                   (long long)n, (long long)P.nominal);
+    if (r->steps_enqueued != 0) return fail(&r->err, PIC_E_STATE, "particles can only be loaded before the first step");
+    const Geometry &G = L.g;
+    const int nd = G.ndim;
+    const int nt = G.ntiles;
+    std::vector<int> cellc((size_t)n * nd), tile((size_t)n);
+    std::vector<double> off((size_t)n * nd);
+    std::vector<int64_t> count(nt, 0);
+    for (int64_t p = 0; p < n; ++p) {
+        int t = 0, mul = 1;
+        for (int a = 0; a < nd; ++a) {
+            const double Lx = G.n[a] * G.d[a];
+            double xa = std::fmod(x[(size_t)a * n + p], Lx);
+            if (xa < 0) xa += Lx;
+            double X = xa / G.d[a];
+            int ic = (int)std::floor(X);
+            double o = X - ic;
+            if (L.real == 4) {
+                float of = (float)o;
+                if (of >= 1.0f) { of = 0.0f; ic += 1; }
+                o = of;
+            } else if (o >= 1.0) { o = 0.0; ic += 1; }
+            if (ic >= G.n[a]) ic -= G.n[a];
+            if (ic < 0) ic += G.n[a];
+            cellc[(size_t)p * nd + a] = ic;
+            off[(size_t)p * nd + a] = o;
+            t += (ic >> G.tshift[a]) * mul;
+            mul *= G.nt[a];
+        }
+        tile[p] = t;
+        count[t] += 1;
+    }
+    const int64_t reserve = (P.ncap - n) / nt;
+    std::vector<int32_t> start(nt), cap(nt);
+    std::vector<uint32_t> front(nt);
+    int64_t o = 0;
+    for (int t = 0; t < nt; ++t) {
+        start[t] = (int32_t)o;
+        cap[t] = (int32_t)(count[t] + reserve);
+        front[t] = (uint32_t)count[t];
+        o += cap[t];
+    }
+    std::vector<int64_t> fill(start.begin(), start.end());
+    const size_t R = L.real;
+    const size_t ncap = (size_t)P.ncap;
+    std::vector<uint32_t> hcell(R == 4 ? ncap : 0), hid(ncap, 0xFFFFFFFFu);
+    std::vector<char> hpos[3], hu[3];
+    for (int a = 0; a < nd; ++a) hpos[a].assign(ncap * R, 0);
+    for (int c = 0; c < 3; ++c) hu[c].assign(ncap * R, 0);
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t slot = fill[tile[p]]++;
+        if (R == 4) {
+            uint32_t c = 0;
+            for (int a = 0; a < nd; ++a) c |= (uint32_t)cellc[(size_t)p * nd + a] << G.csh[a];
+            hcell[slot] = c;
+            for (int a = 0; a < nd; ++a) ((float *)hpos[a].data())[slot] = (float)off[(size_t)p * nd + a];
+            for (int c3 = 0; c3 < 3; ++c3) ((float *)hu[c3].data())[slot] = (float)u[(size_t)c3 * n + p];
+        } else {
+            for (int a = 0; a < nd; ++a)
+                ((double *)hpos[a].data())[slot] = cellc[(size_t)p * nd + a] + off[(size_t)p * nd + a];
+            for (int c3 = 0; c3 < 3; ++c3) ((double *)hu[c3].data())[slot] = u[(size_t)c3 * n + p];
+        }
+        hid[slot] = id[p];
+    }
+    void *b = r->buf.particles[s];
+    if (R == 4) HIPCHK(r, hipMemcpy(at(b, P.cell[0]), hcell.data(), ncap * 4, hipMemcpyHostToDevice));
+    for (int a = 0; a < nd; ++a) HIPCHK(r, hipMemcpy(at(b, P.pos[0][a]), hpos[a].data(), ncap * R, hipMemcpyHostToDevice));
+    for (int c3 = 0; c3 < 3; ++c3) HIPCHK(r, hipMemcpy(at(b, P.u[0][c3]), hu[c3].data(), ncap * R, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(at(b, P.id[0]), hid.data(), ncap * 4, hipMemcpyHostToDevice));
+    return upload_bins(r, s, start, cap, front);
+}
+
+int pic_step(pic_run *r, int32_t nsteps)
+{
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
+    for (int32_t i = 0; i < nsteps; ++i) {
+        if (r->gexec) {
+            HIPCHK(r, hipGraphLaunch(r->gexec, r->stream));
+        } else {
+            HIPCHK(r, launch_step(r->hp, r->dp, r->stream));
+        }
+        r->steps_enqueued += 1;
+    }
+    return PIC_OK;
+}
+
+int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
+{
+    if (!r || !group_ms) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
+    for (int g = 0; g < kNumGroups; ++g) group_ms[g] = 0.0;
+    if (nsteps == 0) return PIC_OK;
+    const int ne = kNumGroups + 1;
+    std::vector<hipEvent_t> ev((size_t)nsteps * ne, nullptr);
+    int rc = PIC_OK;
+    for (auto &e : ev) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) { rc = hip_fail(r, he, "hipEventCreate"); break; }
+    }
+    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i) {
+        hipError_t he = launch_step(r->hp, r->dp, r->stream, &ev[(size_t)i * ne]);
+        if (he != hipSuccess) rc = hip_fail(r, he, "launch_step");
+        else r->steps_enqueued += 1;
+    }
+    if (rc == PIC_OK) {
+        hipError_t he = hipStreamSynchronize(r->stream);
+        if (he != hipSuccess) rc = hip_fail(r, he, "hipStreamSynchronize");
+    }
+    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i)
+        for (int g = 0; g < kNumGroups; ++g) {
+            float ms = 0.f;
+            hipError_t he = hipEventElapsedTime(&ms, ev[(size_t)i * ne + g], ev[(size_t)i * ne + g + 1]);
+            if (he != hipSuccess) { rc = hip_fail(r, he, "hipEventElapsedTime"); break; }
+            group_ms[g] += ms;
+        }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int pic_sync(pic_run *r)
+{
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    DevState st;
+    int rc = read_state(r, &st);
+    if (rc) return rc;
+    return check_fatal(r, st);
+}
+
+int pic_diag_history(pic_run *r, pic_diag *out, int64_t max, int64_t *count)
+{
+    if (!r || !out || !count || max < 0) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    DevState st;
+    int rc = read_state(r, &st);
+    if (rc) return rc;
+    rc = check_fatal(r, st);
+    if (rc) return rc;
+    const int64_t avail = std::min<int64_t>(st.ring_head, kRing);
+    const int64_t n = std::min(avail, max);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t rec = st.ring_head - n + i;
+        HIPCHK(r, hipMemcpy(&out[i], (char *)r->buf.diag + (rec % kRing) * sizeof(pic_diag), sizeof(pic_diag),
+                            hipMemcpyDeviceToHost));
+    }
+    *count = n;
+    return PIC_OK;
+}
+
+int pic_diagnostics(pic_run *r, pic_diag *out)
+{
+    if (!r || !out) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    int64_t n = 0;
+    int rc = pic_diag_history(r, out, 1, &n);
+    if (rc) return rc;
+    if (n == 0) return fail(&r->err, PIC_E_STATE, "no diagnostic record yet");
+    return PIC_OK;
+}
+
+int pic_read_fields(pic_run *r, double *E, double *B, double *J)
+{
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    const size_t cells = (size_t)r->L.g.cells;
+    const size_t R = r->L.real;
+    std::vector<char> h(cells * 6 * R);
+    HIPCHK(r, hipMemcpy(h.data(), at(r->buf.fields, r->L.F), h.size(), hipMemcpyDeviceToHost));
+    for (int c = 0; c < 6; ++c) {
+        double *dst = c < 3 ? E : B;
+        if (!dst) continue;
+        dst += (size_t)(c % 3) * cells;
+        for (size_t o = 0; o < cells; ++o)
+            dst[o] = R == 4 ? (double)((const float *)h.data())[c * cells + o] : ((const double *)h.data())[c * cells + o];
+    }
+    if (J) HIPCHK(r, hipMemcpy(J, at(r->buf.fields, r->L.J), cells * 3 * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_write_fields(pic_run *r, const double *E, const double *B)
+{
+    if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    const size_t cells = (size_t)r->L.g.cells;
+    const size_t R = r->L.real;
+    for (int c = 0; c < 6; ++c) {
+        const double *src = c < 3 ? E : B;
+        if (!src) continue;
+        src += (size_t)(c % 3) * cells;
+        std::vector<char> h(cells * R);
+        for (size_t o = 0; o < cells; ++o) {
+            if (R == 4) ((float *)h.data())[o] = (float)src[o];
+            else ((double *)h.data())[o] = src[o];
+        }
+        HIPCHK(r, hipMemcpy(at(r->buf.fields, r->L.F + (size_t)c * cells * R), h.data(), h.size(),
+                            hipMemcpyHostToDevice));
+    }
+    return PIC_OK;
+}
+
+int pic_read_particles(pic_run *r, int s, double *x, double *u, uint32_t *id, int64_t cap, int64_t *count)
+{
+    if (!r || !count) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    if (s < 0 || s >= r->ns) return fail(&r->err, PIC_E_INVALID_ARG, "species %d", s);
+    DevState st;
+    int rc = read_state(r, &st);
+    if (rc) return rc;
+    rc = check_fatal(r, st);
+    if (rc) return rc;
+    const Layout &L = r->L;
+    const Layout::Sp &P = L.sp[s];
+    const Geometry &G = L.g;
+    const int nt = G.ntiles, nd = G.ndim, par = st.par;
+    void *b = r->buf.particles[s];
+    std::vector<int32_t> start(nt), tcap(nt);
+    std::vector<uint32_t> cf((size_t)2 * nt), cb((size_t)2 * nt);
+    HIPCHK(r, hipMemcpy(start.data(), at(b, P.start), nt * 4, hipMemcpyDeviceToHost));
+    HIPCHK(r, hipMemcpy(tcap.data(), at(b, P.cap), nt * 4, hipMemcpyDeviceToHost));
+    HIPCHK(r, hipMemcpy(cf.data(), at(b, P.cnt_front), (size_t)2 * nt * 4, hipMemcpyDeviceToHost));
+    HIPCHK(r, hipMemcpy(cb.data(), at(b, P.cnt_back), (size_t)2 * nt * 4, hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (int t = 0; t < nt; ++t) n += (int64_t)cf[(size_t)par * nt + t] + cb[(size_t)par * nt + t];
+    *count = n;
+    if (n == 0) return PIC_OK;
+    if (n > cap) return fail(&r->err, PIC_E_BUFFER_TOO_SMALL, "%lld particles, capacity %lld", (long long)n,
+                             (long long)cap);
+    if (!x || !u) return fail(&r->err, PIC_E_INVALID_ARG, "null output arrays");
+    const size_t ncap = (size_t)P.ncap, R = L.real;
+    std::vector<uint32_t> hcell(R == 4 ? ncap : 0), hid(ncap);
+    std::vector<char> hpos[3], hu[3];
+    if (R == 4) HIPCHK(r, hipMemcpy(hcell.data(), at(b, P.cell[par]), ncap * 4, hipMemcpyDeviceToHost));
+    for (int a = 0; a < nd; ++a) {
+        hpos[a].resize(ncap * R);
+        HIPCHK(r, hipMemcpy(hpos[a].data(), at(b, P.pos[par][a]), ncap * R, hipMemcpyDeviceToHost));
+    }
+    for (int c = 0; c < 3; ++c) {
+        hu[c].resize(ncap * R);
+        HIPCHK(r, hipMemcpy(hu[c].data(), at(b, P.u[par][c]), ncap * R, hipMemcpyDeviceToHost));
+    }
+    HIPCHK(r, hipMemcpy(hid.data(), at(b, P.id[par]), ncap * 4, hipMemcpyDeviceToHost));
+    const bool tracked = r->hp.sp[s].track_id != 0;
+    int64_t k = 0;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t nf = cf[(size_t)par * nt + t], nb = cb[(size_t)par * nt + t];
+        for (int64_t j = 0; j < nf + nb; ++j, ++k) {
+            const int64_t slot = j < nf ? start[t] + j : start[t] + tcap[t] - nb + (j - nf);
+            for (int a = 0; a < nd; ++a) {
+                double X;
+                if (R == 4) {
+                    const uint32_t c = hcell[slot];
+                    const int ic = (int)((c >> G.csh[a]) & G.cmask[a]);
+                    X = ic + (double)((const float *)hpos[a].data())[slot];
+                } else {
+                    X = ((const double *)hpos[a].data())[slot];
+                }
+                x[(size_t)a * cap + k] = X * G.d[a];
+            }
+            for (int c = 0; c < 3; ++c)
+                u[(size_t)c * cap + k] = R == 4 ? (double)((const float *)hu[c].data())[slot]
+                                              : ((const double *)hu[c].data())[slot];
+            if (id) id[k] = tracked ? hid[slot] : 0xFFFFFFFFu;
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_destroy(pic_run *r)
+{
+    if (!r) return PIC_OK;
+    if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    delete r;
+    return PIC_OK;
+}
+
+}  // extern "C"

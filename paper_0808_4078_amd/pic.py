@@ -1,0 +1,309 @@
+"""Python binding of libpic.so (argument marshalling only).
+
+Every step of the PIC path runs in the HIP kernels behind the C ABI in
+``include/pic.h``; this module converts arguments, allocates the
+caller-owned device buffers with PyTorch and passes the current HIP stream.
+It fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK = 0
+PIC_PREC_FP64 = 0
+PIC_PREC_MIXED = 1
+PIC_FLAG_FREEZE_FIELDS = 1
+PIC_FLAG_NO_COLLIDE = 2
+PIC_FLAG_LATTICE_LOAD = 4
+PIC_FLAG_HOST_LOAD = 8
+PIC_FLAG_NO_GRAPH = 16
+PIC_FLAG_TRACK_IDS = 32
+MAX_SPECIES = 8
+
+STATUS = {0: "PIC_OK", -1: "PIC_E_INVALID_ARG", -2: "PIC_E_UNSUPPORTED", -3: "PIC_E_CFL",
+          -4: "PIC_E_BUFFER_TOO_SMALL", -5: "PIC_E_HIP", -6: "PIC_E_STATE", -7: "PIC_E_CAPACITY"}
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("run", C.c_uint32),
+                ("tile", C.c_int32 * 3), ("diag_every", C.c_int32), ("flags", C.c_uint32)]
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("density", C.c_double), ("ppc", C.c_int32),
+                ("drift_u", C.c_double * 3), ("u_th", C.c_double), ("cancel_current_of", C.c_int32),
+                ("nu_coll", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("particle_bytes", C.c_size_t * MAX_SPECIES), ("field_bytes", C.c_size_t),
+                ("scratch_bytes", C.c_size_t), ("diag_bytes", C.c_size_t)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("particles", C.c_void_p * MAX_SPECIES), ("fields", C.c_void_p),
+                ("scratch", C.c_void_p), ("diag", C.c_void_p)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("time", C.c_double), ("W", C.c_double * 6),
+                ("kinetic", C.c_double * MAX_SPECIES), ("p_particles", C.c_double * 3),
+                ("p_field_z", C.c_double), ("collisions", C.c_int64),
+                ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64)]
+
+    def as_dict(self, ns: int) -> dict:
+        return dict(step=int(self.step), time=float(self.time), W=np.array(self.W[:]),
+                    kinetic=np.array(self.kinetic[:ns]), p_particles=np.array(self.p_particles[:]),
+                    p_field_z=float(self.p_field_z), collisions=int(self.collisions),
+                    n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins))
+
+
+class PicError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} -> {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_profiled", "pic_sync", "pic_diagnostics",
+           "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
+           "pic_status_string", "pic_last_error"]
+
+
+def lib():
+    """The loaded libpic.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0808_4078_amd.build` "
+                               "(there is no fallback path)")
+        # libpic.so needs libamdhip64.so.7.  PyTorch bundles a HIP runtime with
+        # that soname; bringing torch's runtime up first makes the library bind
+        # to it, so the process holds one HIP runtime and torch's buffers and
+        # streams are valid in the library.
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.pic_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(Sizes)]
+        L.pic_init.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(Buffers), vp, P(vp)]
+        L.pic_load_particles.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int64]
+        L.pic_step.argtypes = [vp, C.c_int32]
+        L.pic_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
+        L.pic_sync.argtypes = [vp]
+        L.pic_diagnostics.argtypes = [vp, P(Diag)]
+        L.pic_diag_history.argtypes = [vp, P(Diag), C.c_int64, P(C.c_int64)]
+        L.pic_read_fields.argtypes = [vp, vp, vp, vp]
+        L.pic_write_fields.argtypes = [vp, vp, vp]
+        L.pic_read_particles.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int64, P(C.c_int64)]
+        L.pic_destroy.argtypes = [vp]
+        L.pic_status_string.argtypes = [C.c_int]
+        L.pic_status_string.restype = C.c_char_p
+        L.pic_last_error.argtypes = [vp, C.c_char_p, C.c_size_t]
+        _lib = L
+    return _lib
+
+
+def _last_error(handle) -> str:
+    buf = C.create_string_buffer(1024)
+    lib().pic_last_error(handle, buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(rc: int, what: str, handle=None):
+    if rc != PIC_OK:
+        raise PicError(rc, what, _last_error(handle))
+
+
+def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0, tile=0,
+               diag_every=0, flags=0):
+    """Descriptors from plain values.  species: list of dicts with keys
+    charge, mass, density, ppc, drift_u, u_th, cancel_current_of, nu_coll."""
+    g = GridDesc()
+    g.ndim = ndim
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < len(n) else 1
+        g.d[a] = float(d[a]) if a < len(d) else 1.0
+        g.tile[a] = int(tile) if a < ndim else 0
+    g.dt = float(dt)
+    g.precision = int(precision)
+    g.seed = int(seed)
+    g.run = int(run)
+    g.diag_every = int(diag_every)
+    g.flags = int(flags)
+    arr = (SpeciesDesc * len(species))()
+    for i, s in enumerate(species):
+        arr[i].charge = float(s.get("charge", -1.0))
+        arr[i].mass = float(s.get("mass", 1.0))
+        arr[i].density = float(s["density"])
+        arr[i].ppc = int(s["ppc"])
+        du = s.get("drift_u", (0.0, 0.0, 0.0))
+        for c in range(3):
+            arr[i].drift_u[c] = float(du[c])
+        arr[i].u_th = float(s.get("u_th", 0.0))
+        arr[i].cancel_current_of = int(s.get("cancel_current_of", -1))
+        arr[i].nu_coll = float(s.get("nu_coll", 0.0))
+    return g, arr
+
+
+def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0):
+    """Descriptors of a synthetic workload object (attributes ndim, n, d, dt,
+    seed, species[name, q, m, density, ppc, drift_u, u_th, nu, cancel_current_of])."""
+    sp = [dict(charge=s.q, mass=s.m, density=s.density, ppc=s.ppc, drift_u=s.drift_u, u_th=s.u_th,
+               cancel_current_of=s.cancel_current_of, nu_coll=s.nu) for s in wl.species]
+    if getattr(wl, "lattice", False):
+        flags |= PIC_FLAG_LATTICE_LOAD
+    return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags)
+
+
+def query(grid: GridDesc, species) -> Sizes:
+    out = Sizes()
+    _check(lib().pic_query(C.byref(grid), species, len(species), C.byref(out)), "pic_query")
+    return out
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Run:
+    """A PIC run on the current CUDA (HIP) device.  Buffers are torch
+    tensors owned by this object; the stream is torch's current stream."""
+
+    def __init__(self, grid: GridDesc, species, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required for the PIC library")
+        self.torch = torch
+        self.grid = grid
+        self.species = species
+        self.ns = len(species)
+        self.ndim = int(grid.ndim)
+        self.n = tuple(int(grid.n[a]) for a in range(self.ndim))
+        self.cells = int(np.prod(self.n))
+        self.device = torch.device(device if device is not None else "cuda")
+        sz = query(grid, species)
+        self.sizes = sz
+
+        def alloc(nbytes):
+            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+        self._bufs = [alloc(sz.particle_bytes[s]) for s in range(self.ns)]
+        self._fields = alloc(sz.field_bytes)
+        self._scratch = alloc(sz.scratch_bytes)
+        self._diag = alloc(sz.diag_bytes)
+        b = Buffers()
+        for s in range(self.ns):
+            b.particles[s] = self._bufs[s].data_ptr()
+        b.fields = self._fields.data_ptr()
+        b.scratch = self._scratch.data_ptr()
+        b.diag = self._diag.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().pic_init(C.byref(grid), species, self.ns, C.byref(b), C.c_void_p(self.stream.cuda_stream),
+                              C.byref(h)), "pic_init")
+        self.h = h
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def device_bytes(self) -> int:
+        return sum(int(t.numel()) for t in self._bufs) + int(self._fields.numel() + self._scratch.numel()
+                                                             + self._diag.numel())
+
+    def load_particles(self, s: int, x: np.ndarray, u: np.ndarray, ids: np.ndarray):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        n = u.shape[1]
+        assert x.shape == (self.ndim, n) and u.shape == (3, n) and ids.shape == (n,)
+        _check(lib().pic_load_particles(self.h, s, _ptr(x), _ptr(u), _ptr(ids), n), "pic_load_particles", self.h)
+
+    def step(self, n: int = 1):
+        _check(lib().pic_step(self.h, int(n)), "pic_step", self.h)
+
+    GROUPS = ("field_diag", "particle", "relayout", "reduce_j", "yee", "advance")
+
+    def step_profiled(self, n: int) -> dict:
+        """n steps with HIP events around each kernel group; returns the
+        summed milliseconds per group (synchronising)."""
+        ms = (C.c_double * 6)()
+        _check(lib().pic_step_profiled(self.h, int(n), ms), "pic_step_profiled", self.h)
+        return dict(zip(self.GROUPS, list(ms)))
+
+    def sync(self):
+        _check(lib().pic_sync(self.h), "pic_sync", self.h)
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        _check(lib().pic_diagnostics(self.h, C.byref(d)), "pic_diagnostics", self.h)
+        return d.as_dict(self.ns)
+
+    def history(self, max_records: int = 4096) -> list:
+        arr = (Diag * max_records)()
+        n = C.c_int64()
+        _check(lib().pic_diag_history(self.h, arr, max_records, C.byref(n)), "pic_diag_history", self.h)
+        return [arr[i].as_dict(self.ns) for i in range(n.value)]
+
+    @property
+    def field_shape(self):
+        """(3, nz, ny, nx), nz = 1 in 2D."""
+        n3 = tuple(self.n) + (1,) * (3 - len(self.n))
+        return (3, n3[2], n3[1], n3[0])
+
+    def read_fields(self):
+        shp = self.field_shape
+        E = np.zeros(shp)
+        B = np.zeros(shp)
+        J = np.zeros(shp)
+        _check(lib().pic_read_fields(self.h, _ptr(E), _ptr(B), _ptr(J)), "pic_read_fields", self.h)
+        return E, B, J
+
+    def write_fields(self, E=None, B=None):
+        shp = self.field_shape
+        Ep = np.ascontiguousarray(E, dtype=np.float64) if E is not None else None
+        Bp = np.ascontiguousarray(B, dtype=np.float64) if B is not None else None
+        for a in (Ep, Bp):
+            if a is not None and a.shape != shp:
+                raise ValueError(f"field array shape {a.shape}, expected {shp}")
+        _check(lib().pic_write_fields(self.h, _ptr(Ep) if Ep is not None else None,
+                                      _ptr(Bp) if Bp is not None else None), "pic_write_fields", self.h)
+
+    def read_particles(self, s: int):
+        cnt = C.c_int64()
+        rc = lib().pic_read_particles(self.h, s, None, None, None, 0, C.byref(cnt))
+        if rc not in (PIC_OK, -4):
+            _check(rc, "pic_read_particles", self.h)
+        n = cnt.value
+        x = np.zeros((self.ndim, max(n, 1)))
+        u = np.zeros((3, max(n, 1)))
+        ids = np.zeros(max(n, 1), dtype=np.uint32)
+        _check(lib().pic_read_particles(self.h, s, _ptr(x), _ptr(u), _ptr(ids), max(n, 1), C.byref(cnt)),
+               "pic_read_particles", self.h)
+        return x[:, :n], u[:, :n], ids[:n]

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point declared in include/pic.h, its ctypes mirrors match the C
+struct sizes, and pic_query validates descriptors."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import synth
+from paper_0808_4078_amd import pic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(pic_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_entry_point():
+    names = declared_functions()
+    assert len(names) >= 13
+    L = pic.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(pic.EXPORTS) == set(names)
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include "pic.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc), sizeof(pic_species_desc),'
+                    'sizeof(pic_sizes), sizeof(pic_buffers), sizeof(pic_diag), offsetof(pic_grid_desc, flags),'
+                    'offsetof(pic_diag, rebins)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    import ctypes as C
+    want = [C.sizeof(pic.GridDesc), C.sizeof(pic.SpeciesDesc), C.sizeof(pic.Sizes), C.sizeof(pic.Buffers),
+            C.sizeof(pic.Diag), pic.GridDesc.flags.offset, pic.Diag.rebins.offset]
+    assert got == want
+
+
+def test_status_strings():
+    L = pic.lib()
+    for code in range(-7, 1):
+        assert L.pic_status_string(code)
+
+
+def _descs(**kw):
+    wl = synth.C1
+    return pic.workload_descs(wl, **kw)
+
+
+def test_query_sizes_c1_and_c3():
+    g, sp = _descs(precision=pic.PIC_PREC_FP64)
+    s64 = pic.query(g, sp)
+    g, sp = _descs(precision=pic.PIC_PREC_MIXED)
+    s32 = pic.query(g, sp)
+    assert s64.field_bytes > s32.field_bytes > 0
+    assert s64.particle_bytes[0] > s32.particle_bytes[0] > 0
+    # C3: 1024^2, 64 ppc, 2 species -> each species store holds >= 64 M slots per set
+    g, sp = pic.workload_descs(synth.C3, precision=pic.PIC_PREC_MIXED)
+    s = pic.query(g, sp)
+    assert s.particle_bytes[0] >= 2 * 64 * 1024 * 1024 * 28
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dt", 0.2, -3),            # more than half a cell per step
+    ("tile", 12, -2),           # not a supported tile
+    ("tile", 32, 0),
+])
+def test_query_validation(field, value, code):
+    wl = synth.C1
+    if field == "dt":
+        g, sp = pic.make_descs(2, wl.n, wl.d, value, [dict(density=1.0, ppc=4)])
+    else:
+        g, sp = pic.make_descs(2, wl.n, wl.d, wl.dt, [dict(density=1.0, ppc=4)], tile=value)
+    out = pic.Sizes()
+    import ctypes as C
+    rc = pic.lib().pic_query(C.byref(g), sp, 1, C.byref(out))
+    assert rc == code
+
+
+def test_query_rejects_bad_species_and_grid():
+    import ctypes as C
+    out = pic.Sizes()
+    g, sp = pic.make_descs(2, (64, 48), (0.2, 0.2), 0.1, [dict(density=1.0, ppc=0)])
+    assert pic.lib().pic_query(C.byref(g), sp, 1, C.byref(out)) == -1
+    g, sp = pic.make_descs(2, (64, 36), (0.2, 0.2), 0.1, [dict(density=1.0, ppc=4)])
+    assert pic.lib().pic_query(C.byref(g), sp, 1, C.byref(out)) == -1      # 36 is not a multiple of 8
+    g, sp = pic.make_descs(2, (64, 40), (0.2, 0.2), 0.1, [dict(density=1.0, ppc=4)])
+    assert pic.lib().pic_query(C.byref(g), sp, 1, C.byref(out)) == 0       # common tile 8
+    g, sp = pic.make_descs(2, (64, 64), (0.2, 0.2), 0.1, [dict(density=1.0, ppc=4)])
+    assert pic.lib().pic_query(C.byref(g), sp, 0, C.byref(out)) == -1
+    assert pic.lib().pic_query(C.byref(g), sp, 9, C.byref(out)) == -1
