@@ -46,6 +46,10 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     return total
 
 
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int):
     import torch
     from paper_0808_4078_amd import pic
@@ -56,6 +60,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     run = pic.Run(g, sp)
     run.sync()
     init_s = time.time() - t0
+    progress(f"{wl.name} {precision}: initialised {wl.particles} particles in {init_s:.2f} s")
     run.step(warmup)
     run.sync()
     stream = run.stream
@@ -78,6 +83,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     p1.record(stream)
     torch.cuda.synchronize()
     prof_ms = p0.elapsed_time(p1)
+    progress(f"{wl.name} {precision}: {steps} steps {graph_ms / steps:.3f} ms/step (graph), "
+             f"{prof_ms / steps:.3f} ms/step (profiled)")
     diag = run.diagnostics()
     n = int(sum(wl.cells * s.ppc for s in wl.species))
     out = dict(particles=n, init_s=init_s, graph_ms=graph_ms, profiled_ms=prof_ms, groups_ms=groups,
@@ -100,6 +107,7 @@ def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
     parts = synth.load(sample)
     sp = [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x, p.u, p.id) for sc, p in zip(sample.species, parts)]
     run = oracle.OracleRun(sample.ndim, sample.n, sample.d, sample.dt, sp, sample.seed)
+    progress(f"cpu baseline: {sample.particles} particles loaded, {oracle.num_threads()} threads")
     run.step(1)
     n = sample.particles
     steps = 0

@@ -28,6 +28,13 @@
 
 namespace pic {
 
+// Pointers read from the parameter block are generic to the compiler; the
+// particle and field arrays are in global memory, and saying so gives global
+// (not flat) loads, stores and atomics.
+#define GLB __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GLB T *gbl(T *p) { return (GLB T *)p; }
+template <typename T> __device__ __forceinline__ const GLB T *gbl(const T *p) { return (const GLB T *)p; }
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
@@ -54,10 +61,12 @@ template <typename R> struct Arith;
 template <> struct Arith<float> {
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ void sc(float a, float *s, float *c) { sincosf(a, s, c); }
 };
 template <> struct Arith<double> {
     static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ void sc(double a, double *s, double *c) { sincos(a, s, c); }
 };
 
 __device__ __forceinline__ bool diag_step(const KParams *kp, int64_t step)
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
     DevState *state = kp->state;
 
     {
-        const R *F = (const R *)kp->F;
+        const GLB R *F = gbl((const R *)kp->F);
         const int64_t plane = kp->g.cells;
         for (int i = threadIdx.x; i < 6 * NF * NF; i += kBlock) {
             const int c = i / (NF * NF), r = i - c * (NF * NF);
@@ -196,18 +205,18 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
         const bool collide = S.collide != 0;
         const bool track = S.track_id != 0;
         const uint32_t thr = S.coll_thr;
-        const uint32_t *__restrict__ icell = S.cell[src];
-        const R *__restrict__ ip0 = (const R *)S.pos[src][0];
-        const R *__restrict__ ip1 = (const R *)S.pos[src][1];
-        const R *__restrict__ iu0 = (const R *)S.u[src][0];
-        const R *__restrict__ iu1 = (const R *)S.u[src][1];
-        const R *__restrict__ iu2 = (const R *)S.u[src][2];
-        const uint32_t *__restrict__ iid = S.id[src];
-        const int32_t *__restrict__ tstart = S.start;
-        const int32_t *__restrict__ tcap = S.cap;
-        const uint32_t *__restrict__ cf_src = S.cnt_front + src * ntiles;
-        const uint32_t *__restrict__ cb_src = S.cnt_back + src * ntiles;
-        uint32_t *cb_dst = S.cnt_back + dst * ntiles;
+        const GLB uint32_t *__restrict__ icell = gbl(S.cell[src]);
+        const GLB R *__restrict__ ip0 = gbl((const R *)S.pos[src][0]);
+        const GLB R *__restrict__ ip1 = gbl((const R *)S.pos[src][1]);
+        const GLB R *__restrict__ iu0 = gbl((const R *)S.u[src][0]);
+        const GLB R *__restrict__ iu1 = gbl((const R *)S.u[src][1]);
+        const GLB R *__restrict__ iu2 = gbl((const R *)S.u[src][2]);
+        const GLB uint32_t *__restrict__ iid = gbl(S.id[src]);
+        const GLB int32_t *__restrict__ tstart = gbl(S.start);
+        const GLB int32_t *__restrict__ tcap = gbl(S.cap);
+        const GLB uint32_t *__restrict__ cf_src = gbl(S.cnt_front + src * ntiles);
+        const GLB uint32_t *__restrict__ cb_src = gbl(S.cnt_back + src * ntiles);
+        GLB uint32_t *cb_dst = gbl(S.cnt_back + dst * ntiles);
 
         if (threadIdx.x == 0) s_front = 0;
         __syncthreads();
@@ -328,14 +337,14 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 if (collide) {
                     const uint4 r = philox10(make_uint4(pid, (uint32_t)step, kPurposeCollide, runid), seed0, seed1);
                     if (r.x < thr) {
-                        const double um = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
-                        const double ct = 1.0 - 2.0 * u01d(r.y);
-                        const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
-                        double sn, cs;
-                        sincos(6.283185307179586 * u01d(r.z), &sn, &cs);
-                        ux = R(um * st * cs);
-                        uy = R(um * st * sn);
-                        uz = R(um * ct);
+                        const R um = sqrt(ux * ux + uy * uy + uz * uz);
+                        const R ct = R(1) - R(2) * R(u01d(r.y));
+                        const R st = sqrt(fmax(R(0), R(1) - ct * ct));
+                        R sn, cs;
+                        Arith<R>::sc(R(6.283185307179586) * R(u01d(r.z)), &sn, &cs);
+                        ux = um * st * cs;
+                        uy = um * st * sn;
+                        uz = um * ct;
                         if (diag) acc[5] += 1.0;
                     }
                 }
@@ -377,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
             }
             bool to_ovf = false;
             if (active && !stay) {
-                const uint32_t b = atomicAdd(&cb_dst[t1], 1u);
+                const uint32_t b = __hip_atomic_fetch_add(cb_dst + t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int64_t room = (int64_t)tcap[t1] - (int64_t)cf_src[t1] - (int64_t)cb_src[t1];
                 if ((int64_t)b < room) opos = (int64_t)tstart[t1] + tcap[t1] - 1 - b;
                 else to_ovf = true;
@@ -390,10 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 else atomicOr(&state->fatal, 1);
             }
             if (opos >= 0) {
-                R *op0 = (R *)S.pos[set][0], *op1 = (R *)S.pos[set][1];
-                R *ou0 = (R *)S.u[set][0], *ou1 = (R *)S.u[set][1], *ou2 = (R *)S.u[set][2];
+                GLB R *op0 = gbl((R *)S.pos[set][0]), *op1 = gbl((R *)S.pos[set][1]);
+                GLB R *ou0 = gbl((R *)S.u[set][0]), *ou1 = gbl((R *)S.u[set][1]), *ou2 = gbl((R *)S.u[set][2]);
                 if constexpr (sizeof(R) == 4) {
-                    S.cell[set][opos] = (uint32_t)ix1 | ((uint32_t)iy1 << csh1);
+                    gbl(S.cell[set])[opos] = (uint32_t)ix1 | ((uint32_t)iy1 << csh1);
                     op0[opos] = ox1;
                     op1[opos] = oy1;
                 } else {
@@ -403,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 ou0[opos] = ux;
                 ou1[opos] = uy;
                 ou2[opos] = uz;
-                if (track) S.id[set][opos] = pid;
+                if (track) gbl(S.id[set])[opos] = pid;
             }
         }
         __syncthreads();
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
         }
     }
     __syncthreads();
-    R *Jt = (R *)kp->Jtile + (int64_t)tile * 3 * NJ * NJ;
+    GLB R *Jt = gbl((R *)kp->Jtile) + (int64_t)tile * 3 * NJ * NJ;
     for (int i = threadIdx.x; i < 3 * NJ * NJ; i += kBlock) Jt[i] = sJ[i];
 }
 
@@ -751,9 +760,11 @@ __global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
 
 // ---------------------------------------------------------------------------
 // Device loader (2D): exactly ppc particles per cell, bins laid out
-// tile-major with the cells of a tile in row order; uniform in-cell
-// positions (or a regular sub-lattice) and Gaussian momenta from Philox
-// draws keyed by the particle id.
+// tile-major; inside a tile the k-th particle of every cell comes before the
+// (k+1)-th of any cell, so the 64 lanes of a wave sit in 64 different cells
+// and their current atomics hit different LDS words.  Uniform in-cell
+// positions (or a regular sub-lattice) and Gaussian momenta come from
+// Philox draws keyed by the particle id.
 template <typename R>
 __global__ __launch_bounds__(256) void k_load_2d(const KParams *__restrict__ kp, int s)
 {
@@ -764,7 +775,7 @@ __global__ __launch_bounds__(256) void k_load_2d(const KParams *__restrict__ kp,
     if (p >= per_tile * kp->g.ntiles) return;
     const int tile = (int)(p / per_tile);
     const int64_t q = p - tile * per_tile;
-    const int cl = (int)(q / S.ppc), slot = (int)(q - (int64_t)cl * S.ppc);
+    const int slot = (int)(q / (T * T)), cl = (int)(q - (int64_t)slot * T * T);
     const int ix = (tile % kp->g.nt[0]) * T + cl % T;
     const int iy = (tile / kp->g.nt[0]) * T + cl / T;
     const uint32_t id = (uint32_t)(S.id_base + ((int64_t)iy * kp->g.n[0] + ix) * S.ppc + slot);

@@ -564,6 +564,30 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
         front[t] = (uint32_t)count[t];
         o += cap[t];
     }
+    // Inside each tile, order by (rank of the particle within its cell, cell):
+    // consecutive slots then hold particles of different cells, which keeps
+    // the lanes of a wave off each other's LDS current words.
+    const int64_t tile_cells = (int64_t)G.tile[0] * G.tile[1] * G.tile[2];
+    std::vector<int64_t> key((size_t)n);
+    {
+        std::vector<int32_t> rank_in_cell((size_t)G.cells, 0);
+        for (int64_t p = 0; p < n; ++p) {
+            int64_t cell = 0, local = 0, mul = 1, lmul = 1;
+            for (int a = 0; a < nd; ++a) {
+                const int ic = cellc[(size_t)p * nd + a];
+                cell += ic * mul;
+                mul *= G.n[a];
+                local += (ic & (G.tile[a] - 1)) * lmul;
+                lmul *= G.tile[a];
+            }
+            key[p] = (int64_t)rank_in_cell[cell]++ * tile_cells + local;
+        }
+    }
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t p = 0; p < n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return tile[a] != tile[b] ? tile[a] < tile[b] : key[a] < key[b];
+    });
     std::vector<int64_t> fill(start.begin(), start.end());
     const size_t R = L.real;
     const size_t ncap = (size_t)P.ncap;
@@ -571,7 +595,8 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
     std::vector<char> hpos[3], hu[3];
     for (int a = 0; a < nd; ++a) hpos[a].assign(ncap * R, 0);
     for (int c = 0; c < 3; ++c) hu[c].assign(ncap * R, 0);
-    for (int64_t p = 0; p < n; ++p) {
+    for (int64_t o = 0; o < n; ++o) {
+        const int64_t p = order[o];
         const int64_t slot = fill[tile[p]]++;
         if (R == 4) {
             uint32_t c = 0;
