@@ -77,8 +77,9 @@ enum {
  *             momenta, FP32 push and per-tile FP32 current, FP64 grid-level
  *             current reduction and diagnostics, FP32 E and B.
  *   seed, run counter-based random stream (Philox4x32-10) key and run index.
- *   tile[3]   particle tile edge in cells (0 = library default); n must be a
- *             multiple of the tile.
+ *   tile[3]   particle tile edge in cells, the same on every resolved axis
+ *             (0 = library default: 16 or 8 in 2D, 8 in 3D); 2D supports 8, 16
+ *             and 32, 3D supports 8; n must be a multiple of the tile.
  *   diag_every record diagnostics every diag_every steps (0 = never).
  *   flags     PIC_FLAG_* bits. */
 typedef struct {
@@ -177,9 +178,10 @@ int pic_load_particles(pic_run *run, int species, const double *x, const double 
 /* Enqueues nsteps full steps on the bound stream (asynchronous). */
 int pic_step(pic_run *run, int32_t nsteps);
 
-/* Measurement path: enqueues nsteps full steps exactly as pic_step but with
- * individual launches bracketed by HIP events on the bound stream, waits for
- * them, and adds each kernel group's elapsed milliseconds into group_ms[6]:
+/* Measurement path: enqueues nsteps full steps exactly as pic_step but as
+ * individual launches, each carrying start/stop HIP events that record the
+ * dispatch's own execution interval on the bound stream; waits for them and
+ * adds each kernel group's summed kernel milliseconds into group_ms[6]:
  * [0] field diagnostics, [1] particle kernel (gather, push, move, deposit,
  * scattering, binning), [2] store re-layout, [3] current reduction,
  * [4] Yee update, [5] end-of-step bookkeeping.  Synchronising. */

@@ -105,7 +105,12 @@ struct KParams {
 };
 
 // Host-callable launchers (defined in the .hip translation units).
-constexpr int kNumGroups = 6;        // field-diag, particle, re-layout, reduction, Yee, advance
+// Kernels of one step and the group each belongs to: field-diag (0),
+// particle (1), re-layout (2), current reduction (3), Yee (4), advance (5).
+constexpr int kNumGroups = 6;
+constexpr int kStepKernels = 13;
+constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
+// ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
 hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);

@@ -3,13 +3,13 @@
 // One step (gather -> Boris push -> move -> Esirkepov deposit -> scattering ->
 // current reduction -> Yee update) is a fixed sequence of launches:
 //   k_field_diag     FP64 field energies of E^n, B^n on diagnostic steps
-//   k_particle_2d    one workgroup per particle tile: E/B staged in LDS,
+//   k_particle       one workgroup per particle tile: E/B staged in LDS,
 //                    per-particle gather, push, move, charge-conserving
 //                    deposit into an LDS current tile, scattering, and
 //                    binning of the particle into the next step's store
 //   k_rebin_*        re-layout of the particle store (early exit unless an
 //                    incoming-mover reserve overflowed during the step)
-//   k_reduce_j_2d    fixed-order FP64 sum of the overlapping tile currents
+//   k_reduce_j       fixed-order FP64 sum of the overlapping tile currents
 //   k_yee_b/k_yee_e  B half step, E full step with -J, B half step
 //   k_advance        diagnostic record, counter reset, step/parity update
 //
@@ -22,6 +22,7 @@
 // particle is scattered isotropically off the immobile ions with
 // probability 1 - exp(-nu dt), |u| kept.  Units: t in 1/w_p, x in c/w_p,
 // u = gamma v/c, fields e F/(m c w_p).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "pic_internal.hpp"
@@ -134,35 +135,67 @@ __global__ __launch_bounds__(256) void k_field_diag(const KParams *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// The particle kernel (2D3V).  One workgroup per T x T tile.
+// The particle kernel.  One workgroup per tile of T^D cells (D = 2: the
+// 2D3V transverse plane, z ignorable; D = 3: 3D3V).
 //
-// LDS: E,B on nodes [tx0-1, tx0+T] x [ty0-1, ty0+T] ((T+2)^2 per component)
-// and the tile current on nodes [tx0-1, tx0+T+1]^2 ((T+3)^2 per component).
-// A particle in cell ix of the tile has local cell lc = ix - tx0 + 1 in both
-// arrays.  Its 3-node deposit window per axis is anchored at the nearest
-// node (ix or ix+1), which holds the form factor before and after a move
-// of less than half a cell.
-template <typename R, int T>
-__global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restrict__ kp)
+// LDS: E, B on the nodes [t0-1, t0+T] of every resolved axis ((T+2)^D per
+// component) and the tile current on [t0-1, t0+T+1] ((T+3)^D per component),
+// accumulated in type A.  A particle in cell i of the tile has local cell
+// lc = i - t0 + 1 in both arrays.  Its 3-node deposit window per axis is
+// anchored at the nearest node (i or i+1), which holds the form factor
+// before and after a move of less than half a cell.
+//
+// Per particle: gather -> Boris -> move -> Esirkepov deposit -> scattering
+// -> binning into the next step's store (stayers at the bin front through a
+// wave-aggregated LDS counter; movers at the back of their new tile's bin,
+// above the particles that tile held at the step start; overflow list when
+// that room is used up).
+
+// Field at local cell (b[0], b[1], b[2]) with per-axis weights (w0, w1):
+// bilinear over 4 nodes (D = 2) or trilinear over 8 (D = 3).
+template <typename R, int D, int NF>
+__device__ __forceinline__ R interp(const R *F, int bx, int by, int bz, R x0, R x1, R y0, R y1, R z0, R z1)
+{
+    const int o = (D == 3 ? bz * NF * NF : 0) + by * NF + bx;
+    R v = y0 * (x0 * F[o] + x1 * F[o + 1]) + y1 * (x0 * F[o + NF] + x1 * F[o + NF + 1]);
+    if constexpr (D == 3) {
+        const int q = o + NF * NF;
+        v = z0 * v + z1 * (y0 * (x0 * F[q] + x1 * F[q + 1]) + y1 * (x0 * F[q + NF] + x1 * F[q + NF + 1]));
+    }
+    return v;
+}
+
+template <typename R, typename A, int D, int T>
+__global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
 {
     constexpr int NF = T + 2;
     constexpr int NJ = T + 3;
-    __shared__ R sF[6 * NF * NF];
-    __shared__ R sJ[3 * NJ * NJ];
+    constexpr int NF_D = D == 3 ? NF * NF * NF : NF * NF;
+    constexpr int NJ_D = D == 3 ? NJ * NJ * NJ : NJ * NJ;
+    constexpr int SJ_Y = NJ, SJ_Z = NJ * NJ;        // LDS strides of the current tile
+    __shared__ R sF[6 * NF_D];
+    __shared__ A sJ[3 * NJ_D];
     __shared__ uint32_t s_front;
     __shared__ double sred[kBlock / 64][kTileDiag];
 
     const int tile = blockIdx.x;
-    const int ntx = kp->g.nt[0];
-    const int nx = kp->g.n[0], ny = kp->g.n[1];
+    const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
+    const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
     const int ntiles = kp->g.ntiles;
-    const int tx0 = (tile % ntx) * T, ty0 = (tile / ntx) * T;
+    int t0[3];
+    t0[0] = (tile % ntx) * T;
+    t0[1] = ((tile / ntx) % nty) * T;
+    t0[2] = (tile / (ntx * nty)) * T;
     const int64_t step = kp->state->step;
     const int src = kp->state->par, dst = src ^ 1;
     const bool diag = diag_step(kp, step);
     const int lane = threadIdx.x & 63;
-    const uint32_t csh1 = (uint32_t)kp->g.csh[1];
-    const uint32_t cmask0 = kp->g.cmask[0];
+    const int tsh = kp->g.tshift[0];
+    uint32_t csh[3], cmask[3];
+    for (int a = 0; a < 3; ++a) {
+        csh[a] = (uint32_t)kp->g.csh[a];
+        cmask[a] = kp->g.cmask[a];
+    }
     const uint32_t seed0 = (uint32_t)kp->seed, seed1 = (uint32_t)(kp->seed >> 32);
     const uint32_t runid = kp->run;
     DevState *state = kp->state;
@@ -170,26 +203,30 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
     {
         const GLB R *F = gbl((const R *)kp->F);
         const int64_t plane = kp->g.cells;
-        for (int i = threadIdx.x; i < 6 * NF * NF; i += kBlock) {
-            const int c = i / (NF * NF), r = i - c * (NF * NF);
-            const int ly = r / NF, lx = r - ly * NF;
-            int gx = tx0 - 1 + lx, gy = ty0 - 1 + ly;
-            gx += gx < 0 ? nx : 0;
-            gx -= gx >= nx ? nx : 0;
-            gy += gy < 0 ? ny : 0;
-            gy -= gy >= ny ? ny : 0;
-            sF[i] = F[c * plane + (int64_t)gy * nx + gx];
+        for (int i = threadIdx.x; i < 6 * NF_D; i += kBlock) {
+            const int c = i / NF_D, r = i - c * NF_D;
+            const int lx = r % NF, ly = (r / NF) % NF, lz = D == 3 ? r / (NF * NF) : 0;
+            int gx = t0[0] - 1 + lx, gy = t0[1] - 1 + ly, gz = D == 3 ? t0[2] - 1 + lz : 0;
+            gx += gx < 0 ? n[0] : 0;
+            gx -= gx >= n[0] ? n[0] : 0;
+            gy += gy < 0 ? n[1] : 0;
+            gy -= gy >= n[1] ? n[1] : 0;
+            if constexpr (D == 3) {
+                gz += gz < 0 ? n[2] : 0;
+                gz -= gz >= n[2] ? n[2] : 0;
+            }
+            sF[i] = F[c * plane + ((int64_t)gz * n[1] + gy) * n[0] + gx];
         }
-        for (int i = threadIdx.x; i < 3 * NJ * NJ; i += kBlock) sJ[i] = R(0);
+        for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) sJ[i] = A(0);
     }
     __syncthreads();
 
-    const R *sEx = sF, *sEy = sF + NF * NF, *sEz = sF + 2 * NF * NF;
-    const R *sBx = sF + 3 * NF * NF, *sBy = sF + 4 * NF * NF, *sBz = sF + 5 * NF * NF;
-    R *sJx = sJ, *sJy = sJ + NJ * NJ, *sJz = sJ + 2 * NJ * NJ;
+    const R *sEx = sF, *sEy = sF + NF_D, *sEz = sF + 2 * NF_D;
+    const R *sBx = sF + 3 * NF_D, *sBy = sF + 4 * NF_D, *sBz = sF + 5 * NF_D;
+    A *sJx = sJ, *sJy = sJ + NJ_D, *sJz = sJ + 2 * NJ_D;
 
-    const R dtdx = R(kp->g.dt / kp->g.d[0]);
-    const R dtdy = R(kp->g.dt / kp->g.d[1]);
+    R dtd[3];
+    for (int a = 0; a < 3; ++a) dtd[a] = R(kp->g.dt / kp->g.d[a]);
 
     for (int s = 0; s < kp->nspecies; ++s) {
         const SpeciesDev &S = kp->sp[s];
@@ -198,16 +235,16 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
         const uint32_t nb = S.cnt_back[src * ntiles + tile];
         const uint32_t total = nf + nb;
         const R qm = R(S.qmdt2);
-        const R kx = R(S.qw * kp->g.d[0] / kp->g.dt);   // q w dx/dt
-        const R ky = R(S.qw * kp->g.d[1] / kp->g.dt);
+        R kd[3];                                            // q w d_a/dt
+        for (int a = 0; a < 3; ++a) kd[a] = R(S.qw * kp->g.d[a] / kp->g.dt);
         const R qw = R(S.qw);
         const double wgt = S.w;
         const bool collide = S.collide != 0;
         const bool track = S.track_id != 0;
         const uint32_t thr = S.coll_thr;
         const GLB uint32_t *__restrict__ icell = gbl(S.cell[src]);
-        const GLB R *__restrict__ ip0 = gbl((const R *)S.pos[src][0]);
-        const GLB R *__restrict__ ip1 = gbl((const R *)S.pos[src][1]);
+        const GLB R *__restrict__ ipos[3] = {gbl((const R *)S.pos[src][0]), gbl((const R *)S.pos[src][1]),
+                                             gbl((const R *)S.pos[src][2])};
         const GLB R *__restrict__ iu0 = gbl((const R *)S.u[src][0]);
         const GLB R *__restrict__ iu1 = gbl((const R *)S.u[src][1]);
         const GLB R *__restrict__ iu2 = gbl((const R *)S.u[src][2]);
@@ -225,25 +262,30 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
         for (uint32_t base = 0; base < total; base += kBlock) {
             const uint32_t k = base + threadIdx.x;
             const bool active = k < total;
-            int ix1 = 0, iy1 = 0, t1 = -1;
-            R ox1 = R(0), oy1 = R(0), ux = R(0), uy = R(0), uz = R(0);
+            int ic1[D];
+            R off1[D];
+            int t1 = -1;
+            R ux = R(0), uy = R(0), uz = R(0);
             uint32_t pid = 0;
+            for (int a = 0; a < D; ++a) { ic1[a] = 0; off1[a] = R(0); }
             if (active) {
                 const int64_t slot = k < nf ? (int64_t)bstart + k : (int64_t)bstart + bcap - nb + (k - nf);
-                int ix, iy;
-                R ox, oy;
+                int ic[3] = {0, 0, 0};
+                R off[3] = {R(0), R(0), R(0)};
                 if constexpr (sizeof(R) == 4) {
                     const uint32_t c = icell[slot];
-                    ix = (int)(c & cmask0);
-                    iy = (int)(c >> csh1);
-                    ox = ip0[slot];
-                    oy = ip1[slot];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        ic[a] = (int)((c >> csh[a]) & cmask[a]);
+                        off[a] = ipos[a][slot];
+                    }
                 } else {
-                    const double X = ip0[slot], Y = ip1[slot];
-                    ix = (int)floor(X);
-                    iy = (int)floor(Y);
-                    ox = X - ix;
-                    oy = Y - iy;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const double X = ipos[a][slot];
+                        ic[a] = (int)floor(X);
+                        off[a] = X - ic[a];
+                    }
                 }
                 ux = iu0[slot];
                 uy = iu1[slot];
@@ -252,27 +294,24 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 const R uox = ux, uoy = uy, uoz = uz;
 
                 // ---- gather: linear weights at each component's stagger
-                const int lcx = ix - tx0 + 1, lcy = iy - ty0 + 1;
-                const int hx = ox < R(0.5) ? 1 : 0, hy = oy < R(0.5) ? 1 : 0;
-                const R ax1 = ox, ax0 = R(1) - ox;                     // integer x
-                const R bx1 = ox - R(0.5) + R(hx), bx0 = R(1) - bx1;   // half x
-                const R ay1 = oy, ay0 = R(1) - oy;
-                const R by1 = oy - R(0.5) + R(hy), by0 = R(1) - by1;
-                const int lhx = lcx - hx, lhy = lcy - hy;
-                // (half x, int y): Ex, By
-                const int o_hi = lcy * NF + lhx;
-                // (int x, half y): Ey, Bx
-                const int o_ih = lhy * NF + lcx;
-                // (int, int): Ez
-                const int o_ii = lcy * NF + lcx;
-                // (half, half): Bz
-                const int o_hh = lhy * NF + lhx;
-                const R Ex = ay0 * (bx0 * sEx[o_hi] + bx1 * sEx[o_hi + 1]) + ay1 * (bx0 * sEx[o_hi + NF] + bx1 * sEx[o_hi + NF + 1]);
-                const R By = ay0 * (bx0 * sBy[o_hi] + bx1 * sBy[o_hi + 1]) + ay1 * (bx0 * sBy[o_hi + NF] + bx1 * sBy[o_hi + NF + 1]);
-                const R Ey = by0 * (ax0 * sEy[o_ih] + ax1 * sEy[o_ih + 1]) + by1 * (ax0 * sEy[o_ih + NF] + ax1 * sEy[o_ih + NF + 1]);
-                const R Bx = by0 * (ax0 * sBx[o_ih] + ax1 * sBx[o_ih + 1]) + by1 * (ax0 * sBx[o_ih + NF] + ax1 * sBx[o_ih + NF + 1]);
-                const R Ez = ay0 * (ax0 * sEz[o_ii] + ax1 * sEz[o_ii + 1]) + ay1 * (ax0 * sEz[o_ii + NF] + ax1 * sEz[o_ii + NF + 1]);
-                const R Bz = by0 * (bx0 * sBz[o_hh] + bx1 * sBz[o_hh + 1]) + by1 * (bx0 * sBz[o_hh + NF] + bx1 * sBz[o_hh + NF + 1]);
+                int lc[3], lh[3];
+                R a0[3], a1[3], b0[3], b1[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lc[a] = ic[a] - t0[a] + 1;
+                    const int h = off[a] < R(0.5) ? 1 : 0;
+                    lh[a] = lc[a] - h;
+                    a1[a] = off[a];                             // integer stagger
+                    a0[a] = R(1) - off[a];
+                    b1[a] = off[a] - R(0.5) + R(h);             // half stagger
+                    b0[a] = R(1) - b1[a];
+                }
+                const R Ex = interp<R, D, NF>(sEx, lh[0], lc[1], lc[2], b0[0], b1[0], a0[1], a1[1], a0[2], a1[2]);
+                const R Ey = interp<R, D, NF>(sEy, lc[0], lh[1], lc[2], a0[0], a1[0], b0[1], b1[1], a0[2], a1[2]);
+                const R Ez = interp<R, D, NF>(sEz, lc[0], lc[1], lh[2], a0[0], a1[0], a0[1], a1[1], b0[2], b1[2]);
+                const R Bx = interp<R, D, NF>(sBx, lc[0], lh[1], lh[2], a0[0], a1[0], b0[1], b1[1], b0[2], b1[2]);
+                const R By = interp<R, D, NF>(sBy, lh[0], lc[1], lh[2], b0[0], b1[0], a0[1], a1[1], b0[2], b1[2]);
+                const R Bz = interp<R, D, NF>(sBz, lh[0], lh[1], lc[2], b0[0], b1[0], b0[1], b1[1], a0[2], a1[2]);
 
                 // ---- relativistic Boris push
                 const R umx = ux + qm * Ex, umy = uy + qm * Ey, umz = uz + qm * Ez;
@@ -287,40 +326,91 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 uy = umy + (wz * sx - wx * sz) + qm * Ey;
                 uz = umz + (wx * sy - wy * sx) + qm * Ez;
                 const R ig1 = Arith<R>::rsq(R(1) + ux * ux + uy * uy + uz * uz);
-                const R vz = uz * ig1;
+                const R v[3] = {ux * ig1, uy * ig1, uz * ig1};
 
-                // ---- move in cell units, relative to the particle's cell
-                const R x1 = ox + ux * ig1 * dtdx;
-                const R y1 = oy + uy * ig1 * dtdy;
-
-                // ---- Esirkepov deposit on the 3x3 window around the nearest node
-                const int cxa = ox >= R(0.5) ? 1 : 0, cya = oy >= R(0.5) ? 1 : 0;
-                const R d0x = ox - R(cxa), d1x = x1 - R(cxa);
-                const R d0y = oy - R(cya), d1y = y1 - R(cya);
-                const R S0x[3] = {fmax(R(0), -d0x), R(1) - fabs(d0x), fmax(R(0), d0x)};
-                const R S0y[3] = {fmax(R(0), -d0y), R(1) - fabs(d0y), fmax(R(0), d0y)};
-                const R DSx[3] = {fmax(R(0), -d1x) - S0x[0], R(1) - fabs(d1x) - S0x[1], fmax(R(0), d1x) - S0x[2]};
-                const R DSy[3] = {fmax(R(0), -d1y) - S0y[0], R(1) - fabs(d1y) - S0y[1], fmax(R(0), d1y) - S0y[2]};
-                const int w0 = (lcy + cya - 1) * NJ + (lcx + cxa - 1);
-                const R kzv = qw * vz;
+                // ---- move in cell units, relative to the particle's cell;
+                // form factors on the 3-node window around the nearest node
+                R x1[3], S0[3][3], DS[3][3];
+                int w0 = 0;
 #pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const R ry = S0y[b] + R(0.5) * DSy[b];
-                    const R qy = R(0.5) * S0y[b] + R(1.0 / 3.0) * DSy[b];
-                    const R j0 = -kx * (DSx[0] * ry);
-                    const R j1 = j0 - kx * (DSx[1] * ry);
-                    atomicAdd(&sJx[w0 + b * NJ], j0);
-                    atomicAdd(&sJx[w0 + b * NJ + 1], j1);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) atomicAdd(&sJz[w0 + b * NJ + a], kzv * (S0x[a] * ry + DSx[a] * qy));
+                for (int a = 0; a < D; ++a) {
+                    x1[a] = off[a] + v[a] * dtd[a];
+                    const int ca = off[a] >= R(0.5) ? 1 : 0;
+                    const R d0 = off[a] - R(ca), d1 = x1[a] - R(ca);
+                    S0[a][0] = fmax(R(0), -d0);
+                    S0[a][1] = R(1) - fabs(d0);
+                    S0[a][2] = fmax(R(0), d0);
+                    DS[a][0] = fmax(R(0), -d1) - S0[a][0];
+                    DS[a][1] = R(1) - fabs(d1) - S0[a][1];
+                    DS[a][2] = fmax(R(0), d1) - S0[a][2];
+                    w0 += (lc[a] + ca - 1) * (a == 0 ? 1 : a == 1 ? SJ_Y : SJ_Z);
                 }
+
+                // ---- Esirkepov deposit
+                // Pxy = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3 (likewise for
+                // the other pairs); W_x = DSx Pyz, W_y = DSy Pxz, W_z = DSz Pxy and
+                // each current is the running sum of -q w (d/dt) W along its axis.
+                if constexpr (D == 2) {
+                    const R kzv = qw * v[2];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const R rx = S0x[a] + R(0.5) * DSx[a];
-                    const R j0 = -ky * (DSy[0] * rx);
-                    const R j1 = j0 - ky * (DSy[1] * rx);
-                    atomicAdd(&sJy[w0 + a], j0);
-                    atomicAdd(&sJy[w0 + NJ + a], j1);
+                    for (int b = 0; b < 3; ++b) {
+                        const R ry = S0[1][b] + R(0.5) * DS[1][b];
+                        const R qy = R(0.5) * S0[1][b] + R(1.0 / 3.0) * DS[1][b];
+                        const R j0 = -kd[0] * (DS[0][0] * ry);
+                        const R j1 = j0 - kd[0] * (DS[0][1] * ry);
+                        atomicAdd(&sJx[w0 + b * SJ_Y], A(j0));
+                        atomicAdd(&sJx[w0 + b * SJ_Y + 1], A(j1));
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            atomicAdd(&sJz[w0 + b * SJ_Y + a], A(kzv * (S0[0][a] * ry + DS[0][a] * qy)));
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const R rx = S0[0][a] + R(0.5) * DS[0][a];
+                        const R j0 = -kd[1] * (DS[1][0] * rx);
+                        const R j1 = j0 - kd[1] * (DS[1][1] * rx);
+                        atomicAdd(&sJy[w0 + a], A(j0));
+                        atomicAdd(&sJy[w0 + SJ_Y + a], A(j1));
+                    }
+                } else {
+                    // pair factors P_pq[m][l] = S0p S0q + DSp S0q/2 + S0p DSq/2 + DSp DSq/3
+                    auto P = [&](int p, int q, int m, int l) {
+                        return S0[p][m] * (S0[q][l] + R(0.5) * DS[q][l]) +
+                               DS[p][m] * (R(0.5) * S0[q][l] + R(1.0 / 3.0) * DS[q][l]);
+                    };
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const R pyz = P(1, 2, b, c);
+                            const R j0 = -kd[0] * (DS[0][0] * pyz);
+                            const R j1 = j0 - kd[0] * (DS[0][1] * pyz);
+                            const int o = w0 + c * SJ_Z + b * SJ_Y;
+                            atomicAdd(&sJx[o], A(j0));
+                            atomicAdd(&sJx[o + 1], A(j1));
+                        }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const R pxz = P(0, 2, a, c);
+                            const R j0 = -kd[1] * (DS[1][0] * pxz);
+                            const R j1 = j0 - kd[1] * (DS[1][1] * pxz);
+                            const int o = w0 + c * SJ_Z + a;
+                            atomicAdd(&sJy[o], A(j0));
+                            atomicAdd(&sJy[o + SJ_Y], A(j1));
+                        }
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const R pxy = P(0, 1, a, b);
+                            const R j0 = -kd[2] * (DS[2][0] * pxy);
+                            const R j1 = j0 - kd[2] * (DS[2][1] * pxy);
+                            const int o = w0 + b * SJ_Y + a;
+                            atomicAdd(&sJz[o], A(j0));
+                            atomicAdd(&sJz[o + SJ_Z], A(j1));
+                        }
                 }
 
                 if (diag) {
@@ -349,40 +439,37 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                     }
                 }
 
-                // ---- new cell and offset
-                int kx1 = (int)floor(x1), ky1 = (int)floor(y1);
-                ox1 = x1 - R(kx1);
-                oy1 = y1 - R(ky1);
-                if (ox1 >= R(1)) { ox1 = R(0); kx1 += 1; }
-                if (oy1 >= R(1)) { oy1 = R(0); ky1 += 1; }
-                ix1 = ix + kx1;
-                iy1 = iy + ky1;
-                ix1 += ix1 < 0 ? nx : 0;
-                ix1 -= ix1 >= nx ? nx : 0;
-                iy1 += iy1 < 0 ? ny : 0;
-                iy1 -= iy1 >= ny ? ny : 0;
-                if ((unsigned)ix1 >= (unsigned)nx || (unsigned)iy1 >= (unsigned)ny) {
-                    atomicOr(&state->fatal, 2);
-                    ix1 = 0;
-                    iy1 = 0;
+                // ---- new cell and offset, destination tile
+                bool bad = false;
+                t1 = 0;
+#pragma unroll
+                for (int a = D - 1; a >= 0; --a) {
+                    int kk = (int)floor(x1[a]);
+                    R o1 = x1[a] - R(kk);
+                    if (o1 >= R(1)) { o1 = R(0); kk += 1; }
+                    int i1 = ic[a] + kk;
+                    i1 += i1 < 0 ? n[a] : 0;
+                    i1 -= i1 >= n[a] ? n[a] : 0;
+                    if ((unsigned)i1 >= (unsigned)n[a]) { bad = true; i1 = 0; }
+                    ic1[a] = i1;
+                    off1[a] = o1;
+                    t1 = t1 * kp->g.nt[a] + (i1 >> tsh);
                 }
-                t1 = (iy1 >> kp->g.tshift[1]) * ntx + (ix1 >> kp->g.tshift[0]);
+                if (bad) atomicOr(&state->fatal, 2);
             }
 
-            // ---- binning: stayers fill the bin front (wave-aggregated LDS
-            // counter), movers take slots from the back of their new tile's
-            // bin, above the particles that tile held at the step start.
+            // ---- binning
             const bool stay = active && t1 == tile;
             const uint64_t smask = __ballot(stay);
             int64_t opos = -1;
             if (smask) {
                 const int leader = __ffsll((unsigned long long)smask) - 1;
-                uint32_t b0 = 0;
-                if (lane == leader) b0 = atomicAdd(&s_front, (uint32_t)__popcll(smask));
-                b0 = __shfl(b0, leader, 64);
+                uint32_t bfront = 0;
+                if (lane == leader) bfront = atomicAdd(&s_front, (uint32_t)__popcll(smask));
+                bfront = __shfl(bfront, leader, 64);
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(smask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)smask, 0u));
-                if (stay) opos = (int64_t)bstart + b0 + rank;
+                if (stay) opos = (int64_t)bstart + bfront + rank;
             }
             bool to_ovf = false;
             if (active && !stay) {
@@ -399,19 +486,20 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
                 else atomicOr(&state->fatal, 1);
             }
             if (opos >= 0) {
-                GLB R *op0 = gbl((R *)S.pos[set][0]), *op1 = gbl((R *)S.pos[set][1]);
-                GLB R *ou0 = gbl((R *)S.u[set][0]), *ou1 = gbl((R *)S.u[set][1]), *ou2 = gbl((R *)S.u[set][2]);
                 if constexpr (sizeof(R) == 4) {
-                    gbl(S.cell[set])[opos] = (uint32_t)ix1 | ((uint32_t)iy1 << csh1);
-                    op0[opos] = ox1;
-                    op1[opos] = oy1;
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) c |= (uint32_t)ic1[a] << csh[a];
+                    gbl(S.cell[set])[opos] = c;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[set][a])[opos] = off1[a];
                 } else {
-                    op0[opos] = (double)ix1 + ox1;
-                    op1[opos] = (double)iy1 + oy1;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[set][a])[opos] = (double)ic1[a] + off1[a];
                 }
-                ou0[opos] = ux;
-                ou1[opos] = uy;
-                ou2[opos] = uz;
+                gbl((R *)S.u[set][0])[opos] = ux;
+                gbl((R *)S.u[set][1])[opos] = uy;
+                gbl((R *)S.u[set][2])[opos] = uz;
                 if (track) gbl(S.id[set])[opos] = pid;
             }
         }
@@ -425,8 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_2d(const KParams *__restric
         }
     }
     __syncthreads();
-    GLB R *Jt = gbl((R *)kp->Jtile) + (int64_t)tile * 3 * NJ * NJ;
-    for (int i = threadIdx.x; i < 3 * NJ * NJ; i += kBlock) Jt[i] = sJ[i];
+    GLB R *Jt = gbl((R *)kp->Jtile) + (int64_t)tile * 3 * NJ_D;
+    for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) Jt[i] = R(sJ[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -454,18 +542,15 @@ __global__ void k_rebin_count(const KParams *__restrict__ kp)
 template <typename R>
 __device__ __forceinline__ int tile_of(const KParams *kp, const SpeciesDev &S, int set, int64_t p)
 {
-    int ix, iy;
-    if constexpr (sizeof(R) == 4) {
-        const uint32_t c = S.cell[set][p];
-        ix = (int)(c & kp->g.cmask[0]);
-        iy = (int)(c >> kp->g.csh[1]);
-    } else {
-        ix = (int)floor(((const double *)S.pos[set][0])[p]);
-        iy = (int)floor(((const double *)S.pos[set][1])[p]);
+    int t = 0;
+    for (int a = kp->g.ndim - 1; a >= 0; --a) {
+        int i;
+        if constexpr (sizeof(R) == 4) i = (int)((S.cell[set][p] >> kp->g.csh[a]) & kp->g.cmask[a]);
+        else i = (int)floor(((const double *)S.pos[set][a])[p]);
+        i = min(max(i, 0), kp->g.n[a] - 1);
+        t = t * kp->g.nt[a] + (i >> kp->g.tshift[a]);
     }
-    ix = min(max(ix, 0), kp->g.n[0] - 1);
-    iy = min(max(iy, 0), kp->g.n[1] - 1);
-    return (iy >> kp->g.tshift[1]) * kp->g.nt[0] + (ix >> kp->g.tshift[0]);
+    return t;
 }
 
 template <typename R>
@@ -521,7 +606,7 @@ __device__ __forceinline__ void copy_particle(const KParams *kp, const SpeciesDe
                                               int to, int64_t b)
 {
     if constexpr (sizeof(R) == 4) S.cell[to][b] = S.cell[from][a];
-    for (int c = 0; c < 2; ++c) ((R *)S.pos[to][c])[b] = ((const R *)S.pos[from][c])[a];
+    for (int c = 0; c < kp->g.ndim; ++c) ((R *)S.pos[to][c])[b] = ((const R *)S.pos[from][c])[a];
     for (int c = 0; c < 3; ++c) ((R *)S.u[to][c])[b] = ((const R *)S.u[from][c])[a];
     if (S.track_id) S.id[to][b] = S.id[from][a];
 }
@@ -586,38 +671,53 @@ __global__ void k_rebin_finalize(const KParams *__restrict__ kp)
 
 // ---------------------------------------------------------------------------
 // Grid current: fixed-order FP64 sum of the tile partials covering each node.
-template <typename R>
-__global__ __launch_bounds__(256) void k_reduce_j_2d(const KParams *__restrict__ kp)
+// Along an axis, node i = a0*T + r is held by tile a0 (local r+1), by tile
+// a0-1 when r <= 1 (local r+T+1) and by tile a0+1 when r = T-1 (local 0).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_reduce_j(const KParams *__restrict__ kp)
 {
-    const int nx = kp->g.n[0], ny = kp->g.n[1];
+    const int64_t cells = kp->g.cells;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (int64_t)nx * ny) return;
-    const int i = (int)(o % nx), j = (int)(o / nx);
+    if (o >= cells) return;
+    const int nx = kp->g.n[0], ny = kp->g.n[1];
+    const int idx[3] = {(int)(o % nx), (int)((o / nx) % ny), (int)(o / ((int64_t)nx * ny))};
     const int T = kp->g.tile[0];
     const int NJ = kp->nj;
-    const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
-    const int a0 = i / T, b0 = j / T, ri = i - a0 * T, rj = j - b0 * T;
-    const R *Jt = (const R *)kp->Jtile;
+    const int64_t NJ_D = D == 3 ? (int64_t)NJ * NJ * NJ : (int64_t)NJ * NJ;
+    int tb[3], r[3];
+    for (int a = 0; a < 3; ++a) {
+        tb[a] = idx[a] / T;
+        r[a] = idx[a] - tb[a] * T;
+    }
+    const GLB R *Jt = gbl((const R *)kp->Jtile);
     double jx = 0.0, jy = 0.0, jz = 0.0;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int ly = rj + 1 - dy * T;
-        if (ly < 0 || ly >= NJ) continue;
-        int tb = b0 + dy;
-        tb += tb < 0 ? nty : 0;
-        tb -= tb >= nty ? nty : 0;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int lx = ri + 1 - dx * T;
-            if (lx < 0 || lx >= NJ) continue;
-            int ta = a0 + dx;
-            ta += ta < 0 ? ntx : 0;
-            ta -= ta >= ntx ? ntx : 0;
-            const R *p = Jt + (int64_t)(tb * ntx + ta) * 3 * NJ * NJ + ly * NJ + lx;
-            jx += (double)p[0];
-            jy += (double)p[NJ * NJ];
-            jz += (double)p[2 * NJ * NJ];
+    const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        const int lz = D == 3 ? r[2] + 1 - dz * T : 0;
+        if (lz < 0 || lz >= NJ) continue;
+        int tz = tb[2] + dz;
+        tz += tz < 0 ? kp->g.nt[2] : 0;
+        tz -= tz >= kp->g.nt[2] ? kp->g.nt[2] : 0;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int ly = r[1] + 1 - dy * T;
+            if (ly < 0 || ly >= NJ) continue;
+            int ty = tb[1] + dy;
+            ty += ty < 0 ? kp->g.nt[1] : 0;
+            ty -= ty >= kp->g.nt[1] ? kp->g.nt[1] : 0;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int lx = r[0] + 1 - dx * T;
+                if (lx < 0 || lx >= NJ) continue;
+                int tx = tb[0] + dx;
+                tx += tx < 0 ? kp->g.nt[0] : 0;
+                tx -= tx >= kp->g.nt[0] ? kp->g.nt[0] : 0;
+                const int64_t t = ((int64_t)tz * kp->g.nt[1] + ty) * kp->g.nt[0] + tx;
+                const GLB R *p = Jt + t * 3 * NJ_D + ((int64_t)lz * NJ + ly) * NJ + lx;
+                jx += (double)p[0];
+                jy += (double)p[NJ_D];
+                jz += (double)p[2 * NJ_D];
+            }
         }
     }
-    const int64_t cells = kp->g.cells;
     kp->J[o] = jx;
     kp->J[cells + o] = jy;
     kp->J[2 * cells + o] = jz;
@@ -628,6 +728,7 @@ __global__ __launch_bounds__(256) void k_reduce_j_2d(const KParams *__restrict__
 template <typename R, int NDIM>
 __global__ __launch_bounds__(256) void k_yee_b(const KParams *__restrict__ kp, double h)
 {
+    if (h == 0.0) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1], nz = NDIM == 3 ? kp->g.n[2] : 1;
     const int64_t cells = kp->g.cells;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -661,6 +762,7 @@ __global__ __launch_bounds__(256) void k_yee_b(const KParams *__restrict__ kp, d
 template <typename R, int NDIM>
 __global__ __launch_bounds__(256) void k_yee_e(const KParams *__restrict__ kp)
 {
+    if (kp->flags & PIC_FLAG_FREEZE_FIELDS) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1];
     const int64_t cells = kp->g.cells;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -759,37 +861,45 @@ __global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
 }
 
 // ---------------------------------------------------------------------------
-// Device loader (2D): exactly ppc particles per cell, bins laid out
-// tile-major; inside a tile the k-th particle of every cell comes before the
-// (k+1)-th of any cell, so the 64 lanes of a wave sit in 64 different cells
-// and their current atomics hit different LDS words.  Uniform in-cell
-// positions (or a regular sub-lattice) and Gaussian momenta come from
-// Philox draws keyed by the particle id.
-template <typename R>
-__global__ __launch_bounds__(256) void k_load_2d(const KParams *__restrict__ kp, int s)
+// Device loader: exactly ppc particles per cell, bins laid out tile-major;
+// inside a tile the k-th particle of every cell comes before the (k+1)-th of
+// any cell, so the 64 lanes of a wave sit in 64 different cells and their
+// current atomics hit different LDS words.  Uniform in-cell positions (or a
+// regular sub-lattice) and Gaussian momenta come from Philox draws keyed by
+// the particle id.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_load(const KParams *__restrict__ kp, int s)
 {
     const SpeciesDev &S = kp->sp[s];
     const int T = kp->g.tile[0];
-    const int64_t per_tile = (int64_t)S.ppc * T * T;
+    const int TD = D == 3 ? T * T * T : T * T;
+    const int64_t per_tile = (int64_t)S.ppc * TD;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= per_tile * kp->g.ntiles) return;
     const int tile = (int)(p / per_tile);
     const int64_t q = p - tile * per_tile;
-    const int slot = (int)(q / (T * T)), cl = (int)(q - (int64_t)slot * T * T);
-    const int ix = (tile % kp->g.nt[0]) * T + cl % T;
-    const int iy = (tile / kp->g.nt[0]) * T + cl / T;
-    const uint32_t id = (uint32_t)(S.id_base + ((int64_t)iy * kp->g.n[0] + ix) * S.ppc + slot);
+    const int slot = (int)(q / TD), cl = (int)(q - (int64_t)slot * TD);
+    const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
+    int ic[3];
+    ic[0] = (tile % ntx) * T + cl % T;
+    ic[1] = ((tile / ntx) % nty) * T + (cl / T) % T;
+    ic[2] = D == 3 ? (tile / (ntx * nty)) * T + cl / (T * T) : 0;
+    const int64_t cell = ((int64_t)ic[2] * kp->g.n[1] + ic[1]) * kp->g.n[0] + ic[0];
+    const uint32_t id = (uint32_t)(S.id_base + cell * S.ppc + slot);
     const uint32_t k0 = (uint32_t)kp->seed, k1 = (uint32_t)(kp->seed >> 32);
     const uint4 r0 = philox10(make_uint4(id, 0u, kPurposeLoad, kp->run), k0, k1);
     const uint4 r1 = philox10(make_uint4(id, 1u, kPurposeLoad, kp->run), k0, k1);
-    double ox, oy;
+    const uint32_t rw[3] = {r0.x, r0.y, r0.z};
+    double off[3];
     if (kp->flags & PIC_FLAG_LATTICE_LOAD) {
-        int m = (int)rint(sqrt((double)S.ppc));
-        ox = (slot % m + 0.5) / m;
-        oy = (slot / m + 0.5) / m;
+        const int m = (int)rint(pow((double)S.ppc, 1.0 / D));
+        int rem = slot;
+        for (int a = 0; a < D; ++a) {
+            off[a] = (rem % m + 0.5) / m;
+            rem /= m;
+        }
     } else {
-        ox = sizeof(R) == 4 ? (double)u01f(r0.x) : u01d(r0.x);
-        oy = sizeof(R) == 4 ? (double)u01f(r0.y) : u01d(r0.y);
+        for (int a = 0; a < D; ++a) off[a] = sizeof(R) == 4 ? (double)u01f(rw[a]) : u01d(rw[a]);
     }
     // Box-Muller on two pairs of uniforms
     const double ra = sqrt(-2.0 * log(u01d(r1.x))), pa = 6.283185307179586 * u01d(r1.y);
@@ -797,12 +907,14 @@ __global__ __launch_bounds__(256) void k_load_2d(const KParams *__restrict__ kp,
     const double z[3] = {ra * cos(pa), ra * sin(pa), rb * cos(pb)};
     const int64_t pos = (int64_t)S.start[tile] + q;
     if constexpr (sizeof(R) == 4) {
-        S.cell[0][pos] = (uint32_t)ix | ((uint32_t)iy << kp->g.csh[1]);
-        ((float *)S.pos[0][0])[pos] = (float)ox;
-        ((float *)S.pos[0][1])[pos] = (float)oy;
+        uint32_t c = 0;
+        for (int a = 0; a < D; ++a) {
+            c |= (uint32_t)ic[a] << kp->g.csh[a];
+            ((float *)S.pos[0][a])[pos] = (float)off[a];
+        }
+        S.cell[0][pos] = c;
     } else {
-        ((double *)S.pos[0][0])[pos] = (double)ix + ox;
-        ((double *)S.pos[0][1])[pos] = (double)iy + oy;
+        for (int a = 0; a < D; ++a) ((double *)S.pos[0][a])[pos] = (double)ic[a] + off[a];
     }
     for (int c = 0; c < 3; ++c) ((R *)S.u[0][c])[pos] = R(S.drift[c] + S.uth * z[c]);
     if (S.track_id) S.id[0][pos] = id;
@@ -867,67 +979,87 @@ __global__ __launch_bounds__(256) void k_shift_u(const KParams *__restrict__ kp,
 }
 
 // ---------------------------------------------------------------------------
-// ev (optional): kNumGroups + 1 events recorded at the group boundaries
-// field-diag | particle | re-layout | current reduction | Yee | advance.
-template <typename R, int T>
-static hipError_t step_2d(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
+// Launches one kernel; with `ev` it is a hipExtLaunchKernelGGL whose start
+// and stop events carry the dispatch's own timestamps (ev[2k], ev[2k+1] for
+// the k-th kernel of the step).
+struct Launcher {
+    hipStream_t st;
+    hipEvent_t *ev;
+    int k = 0;
+    template <typename... KArgs, typename... A>
+    void operator()(void (*kern)(KArgs...), dim3 g, dim3 b, A... args)
+    {
+        if (ev) hipExtLaunchKernelGGL(kern, g, b, 0, st, ev[2 * k], ev[2 * k + 1], 0, args...);
+        else hipLaunchKernelGGL(kern, g, b, 0, st, args...);
+        ++k;
+    }
+};
+
+// Kernel order of a step (kStepKernels entries; kernel -> group map in
+// kKernelGroup): field diag | particle | 6 x re-layout | J reduction |
+// 3 x Yee | advance.
+template <typename R, typename A, int D, int T>
+static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
     const int ntiles = hp.g.ntiles;
     const int64_t cells = hp.g.cells;
     const unsigned cb = (unsigned)((cells + 255) / 256);
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
-    if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_field_diag<R>, dim3(kFieldDiagBlocks), dim3(256), 0, st, dp);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL((k_particle_2d<R, T>), dim3(ntiles), dim3(kBlock), 0, st, dp);
-    if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL(k_rebin_count, dim3(nst), dim3(256), 0, st, dp);
-    hipLaunchKernelGGL(k_rebin_count_ovf<R>, dim3(256), dim3(256), 0, st, dp);
-    hipLaunchKernelGGL(k_rebin_scan, dim3(hp.nspecies), dim3(256), 0, st, dp);
-    hipLaunchKernelGGL(k_rebin_scatter<R>, dim3(1024), dim3(256), 0, st, dp);
-    hipLaunchKernelGGL(k_rebin_scatter_ovf<R>, dim3(256), dim3(256), 0, st, dp);
-    hipLaunchKernelGGL(k_rebin_finalize, dim3(nst), dim3(256), 0, st, dp);
-    if (ev) (void)hipEventRecord(ev[3], st);
-    hipLaunchKernelGGL(k_reduce_j_2d<R>, dim3(cb), dim3(256), 0, st, dp);
-    if (ev) (void)hipEventRecord(ev[4], st);
-    if (!(hp.flags & PIC_FLAG_FREEZE_FIELDS)) {
-        hipLaunchKernelGGL((k_yee_b<R, 2>), dim3(cb), dim3(256), 0, st, dp, 0.5);
-        hipLaunchKernelGGL((k_yee_e<R, 2>), dim3(cb), dim3(256), 0, st, dp);
-        hipLaunchKernelGGL((k_yee_b<R, 2>), dim3(cb), dim3(256), 0, st, dp, 0.5);
-    }
-    if (ev) (void)hipEventRecord(ev[5], st);
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, st, dp);
-    if (ev) (void)hipEventRecord(ev[6], st);
+    Launcher L{st, ev};
+    L(k_field_diag<R>, dim3(kFieldDiagBlocks), dim3(256), dp);
+    L(k_particle<R, A, D, T>, dim3(ntiles), dim3(kBlock), dp);
+    L(k_rebin_count, dim3(nst), dim3(256), dp);
+    L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
+    L(k_rebin_scan, dim3(hp.nspecies), dim3(256), dp);
+    L(k_rebin_scatter<R>, dim3(1024), dim3(256), dp);
+    L(k_rebin_scatter_ovf<R>, dim3(256), dim3(256), dp);
+    L(k_rebin_finalize, dim3(nst), dim3(256), dp);
+    L(k_reduce_j<R, D>, dim3(cb), dim3(256), dp);
+    // frozen fields: the Yee kernels still run (fixed launch shape) but exit
+    const double h = (hp.flags & PIC_FLAG_FREEZE_FIELDS) ? 0.0 : 0.5;
+    L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
+    L(k_yee_e<R, D>, dim3(cb), dim3(256), dp);
+    L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
+    L(k_advance, dim3(1), dim3(256), dp);
     return hipGetLastError();
 }
 
+// Mixed mode accumulates the tile current in FP32 (the current partials are
+// FP32), FP64 mode in FP64.
 template <typename R>
-static hipError_t step_2d_tile(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
+static hipError_t step_prec(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
+    using A = R;
+    if (hp.g.ndim == 3) {
+        if (hp.g.tile[0] == 8) return step_kernels<R, A, 3, 8>(hp, dp, st, ev);
+        return hipErrorInvalidValue;
+    }
     switch (hp.g.tile[0]) {
-    case 8: return step_2d<R, 8>(hp, dp, st, ev);
-    case 16: return step_2d<R, 16>(hp, dp, st, ev);
-    case 32: return step_2d<R, 32>(hp, dp, st, ev);
+    case 8: return step_kernels<R, A, 2, 8>(hp, dp, st, ev);
+    case 16: return step_kernels<R, A, 2, 16>(hp, dp, st, ev);
+    case 32: return step_kernels<R, A, 2, 32>(hp, dp, st, ev);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
-    if (hp.g.ndim != 2) return hipErrorInvalidValue;
-    return hp.precision == PIC_PREC_MIXED ? step_2d_tile<float>(hp, dp, st, ev)
-                                          : step_2d_tile<double>(hp, dp, st, ev);
+    return hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, dp, st, ev) : step_prec<double>(hp, dp, st, ev);
 }
 
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st)
 {
     const int T = hp.g.tile[0];
-    const int64_t n = (int64_t)hp.sp[s].ppc * T * T * hp.g.ntiles;
+    const int64_t TD = hp.g.ndim == 3 ? (int64_t)T * T * T : (int64_t)T * T;
+    const int64_t n = (int64_t)hp.sp[s].ppc * TD * hp.g.ntiles;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    if (hp.precision == PIC_PREC_MIXED)
-        hipLaunchKernelGGL(k_load_2d<float>, dim3(blocks), dim3(256), 0, st, dp, s);
-    else
-        hipLaunchKernelGGL(k_load_2d<double>, dim3(blocks), dim3(256), 0, st, dp, s);
+    if (hp.precision == PIC_PREC_MIXED) {
+        if (hp.g.ndim == 3) hipLaunchKernelGGL((k_load<float, 3>), dim3(blocks), dim3(256), 0, st, dp, s);
+        else hipLaunchKernelGGL((k_load<float, 2>), dim3(blocks), dim3(256), 0, st, dp, s);
+    } else {
+        if (hp.g.ndim == 3) hipLaunchKernelGGL((k_load<double, 3>), dim3(blocks), dim3(256), 0, st, dp, s);
+        else hipLaunchKernelGGL((k_load<double, 2>), dim3(blocks), dim3(256), 0, st, dp, s);
+    }
     return hipGetLastError();
 }
 

@@ -77,7 +77,6 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
     if (!g || !sp) return fail(err, PIC_E_INVALID_ARG, "null descriptor");
     if (ns < 1 || ns > kMaxSpecies) return fail(err, PIC_E_INVALID_ARG, "nspecies %d out of 1..%d", ns, kMaxSpecies);
     if (g->ndim != 2 && g->ndim != 3) return fail(err, PIC_E_INVALID_ARG, "ndim %d", g->ndim);
-    if (g->ndim == 3) return fail(err, PIC_E_UNSUPPORTED, "3D runs are not built in this library version");
     if (g->precision != PIC_PREC_FP64 && g->precision != PIC_PREC_MIXED)
         return fail(err, PIC_E_INVALID_ARG, "precision %d", g->precision);
     if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(err, PIC_E_INVALID_ARG, "dt must be positive");
@@ -103,11 +102,12 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
                         g->dt, a, 0.5 * g->d[a]);
         int t = g->tile[a];
         if (t == 0) {
-            // largest of 16, 8 that divides every resolved axis (tiles are cubes)
-            t = 16;
+            // 3D: 8^3; 2D: the largest of 16, 8 that divides both axes
+            t = g->ndim == 3 ? 8 : 16;
             for (int b = 0; b < g->ndim; ++b)
-                if (g->n[b] > 0 && g->n[b] % 16) t = 8;
+                if (g->n[b] > 0 && g->n[b] % t) t = 8;
         }
+        if (g->ndim == 3 && t != 8) return fail(err, PIC_E_UNSUPPORTED, "3D tiles must be 8^3 (got %d)", t);
         if (t != 8 && t != 16 && t != 32) return fail(err, PIC_E_UNSUPPORTED, "tile %d not in {8,16,32}", t);
         if (g->n[a] % t) return fail(err, PIC_E_INVALID_ARG, "n[%d] = %d is not a multiple of the tile %d", a, g->n[a], t);
         G.n[a] = g->n[a];
@@ -118,7 +118,8 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         G.ntiles *= G.nt[a];
         G.cells *= g->n[a];
     }
-    if (g->ndim == 2 && G.tile[0] != G.tile[1]) return fail(err, PIC_E_UNSUPPORTED, "tiles must be square");
+    for (int a = 1; a < g->ndim; ++a)
+        if (G.tile[a] != G.tile[0]) return fail(err, PIC_E_UNSUPPORTED, "tiles must be square / cubic");
     // packed cell index of the mixed mode
     int used = 0;
     for (int a = 0; a < g->ndim; ++a) {
@@ -640,7 +641,7 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
     if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
     for (int g = 0; g < kNumGroups; ++g) group_ms[g] = 0.0;
     if (nsteps == 0) return PIC_OK;
-    const int ne = kNumGroups + 1;
+    const int ne = 2 * kStepKernels;
     std::vector<hipEvent_t> ev((size_t)nsteps * ne, nullptr);
     int rc = PIC_OK;
     for (auto &e : ev) {
@@ -657,11 +658,11 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
         if (he != hipSuccess) rc = hip_fail(r, he, "hipStreamSynchronize");
     }
     for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i)
-        for (int g = 0; g < kNumGroups; ++g) {
+        for (int k = 0; k < kStepKernels; ++k) {
             float ms = 0.f;
-            hipError_t he = hipEventElapsedTime(&ms, ev[(size_t)i * ne + g], ev[(size_t)i * ne + g + 1]);
+            hipError_t he = hipEventElapsedTime(&ms, ev[(size_t)i * ne + 2 * k], ev[(size_t)i * ne + 2 * k + 1]);
             if (he != hipSuccess) { rc = hip_fail(r, he, "hipEventElapsedTime"); break; }
-            group_ms[g] += ms;
+            group_ms[kKernelGroup[k]] += ms;
         }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);

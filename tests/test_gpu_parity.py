@@ -238,3 +238,61 @@ def test_cold_beam_weibel_rate_gpu(pic, prec):
     log(f"  rates gpu {gg:.5f} oracle {go:.5f} theory {want:.5f} window {win}")
     assert abs(gg / go - 1) < 0.02
     assert abs(gg / want - 1) < 0.03
+
+
+# --------------------------------------------------------------------------- 3D
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-5), ("mixed", 1e-3)])
+def test_3d_fields_and_particles(pic, prec, bar):
+    """3D3V (beam along z, collisionless, 8^3 tiles) on a 16x16x32 box:
+    fields within the bar every 10 steps over 60 steps and particles by id
+    at the end."""
+    log(f"case 3d {prec}")
+    wl = synth.beam_plasma((16, 16, 32), ppc=4, u_th_beam=0.1, u_th_plasma=0.02, steps=60)
+    parts = synth.load(wl)
+    orc = oracle_run(wl, parts)
+    g = gpu_run(wl, parts, PRECS[prec], diag_every=10)
+    worst = 0.0
+    for _ in range(wl.steps // 10):
+        orc.step(10)
+        g.step(10)
+        E, B, J = g.read_fields()
+        worst = max(worst, rel_err(stack(E, B), stack(orc.f.E, orc.f.B)))
+    log(f"  worst stacked field error {worst:.3e}")
+    assert worst < bar
+    assert rel_err(J, orc.f.J) < 10 * bar
+    L = np.array([n * 0.2 for n in wl.n])[:, None]
+    for s in range(2):
+        x, u, ids = by_id(*g.read_particles(s))
+        sp = orc.species[s]
+        xo, uo, io = by_id(sp.x, sp.u, sp.id)
+        assert np.array_equal(ids, io)
+        tol = 1e-9 if prec == "fp64" else 1e-4
+        assert np.max(np.abs(periodic_diff(x, xo, L))) < tol
+        assert np.max(np.abs(u - uo)) < tol * 10
+
+
+def test_3d_device_loader_and_continuity(pic):
+    """3D device load: exactly ppc per cell; after one step the current
+    satisfies rho^1 - rho^0 + dt div J = 0 on every node (rho from the
+    particles read back, by the oracle's CIC deposit)."""
+    log("case 3d loader + continuity")
+    import oracle
+    wl = synth.beam_plasma((16, 16, 16), ppc=8, u_th_beam=0.3, u_th_plasma=0.05)
+    g, sp = pic.workload_descs(wl, precision=PRECS["fp64"], flags=pic.PIC_FLAG_TRACK_IDS)
+    r = pic.Run(g, sp)
+    before = [r.read_particles(s) for s in range(2)]
+    for (x, u, ids), sc in zip(before, wl.species):
+        idx = [np.floor(x[a] / wl.d[a]).astype(int) for a in range(3)]
+        flat = (idx[2] * wl.n[1] + idx[1]) * wl.n[0] + idx[0]
+        assert np.all(np.bincount(flat, minlength=wl.cells) == sc.ppc)
+    r.step(1)
+    after = [r.read_particles(s) for s in range(2)]
+    _, _, J = r.read_fields()
+
+    def rho(parts):
+        sps = [oracle.SpeciesState(sc.q, sc.m, sc.weight, 0.0, np.ascontiguousarray(x), np.ascontiguousarray(u),
+                                   ids) for (x, u, ids), sc in zip(parts, wl.species)]
+        return oracle.OracleRun(3, wl.n, wl.d, wl.dt, sps, 1).rho()
+    o = oracle.OracleRun(3, wl.n, wl.d, wl.dt, [], 1)
+    res = rho(after) - rho(before) + wl.dt * o.divergence(J)
+    assert np.max(np.abs(res)) < 1e-12
