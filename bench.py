@@ -30,19 +30,24 @@ HBM_PEAK_GBS = 8000.0
 
 
 def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
-    """Algorithmic HBM bytes of one particle-kernel launch: every particle's
-    state read once and written once (mixed: int32 cell, 2 FP32 offsets,
-    3 FP32 momenta = 24 B; FP64: 2 FP64 positions, 3 FP64 momenta = 40 B),
-    the 4-byte id read for collisional particles (it keys their draw), plus
-    each tile's E/B halo stage and its partial-current write."""
+    """Algorithmic HBM bytes of one particle-kernel launch.
+
+    Every particle's state is read once and written once:
+      mixed: int32 cell + one FP32 offset per resolved axis + 3 FP32 momenta
+             (2D: 24 B, 3D: 28 B);
+      FP64:  one FP64 position per resolved axis + 3 FP64 momenta (2D: 40 B).
+    Collisional particles also read their 4-byte id, which keys their draw.
+    Each tile stages E and B on (T+2)^D nodes and writes its partial current on
+    (T+3)^D nodes."""
     r = 4 if precision == "mixed" else 8
-    state = (3 * r + 4 * 3) if precision == "mixed" else 5 * 8
+    d = wl.ndim
+    state = (4 + d * 4 + 3 * 4) if precision == "mixed" else (d * 8 + 3 * 8)
     total = 0.0
     for sc in wl.species:
         n = wl.cells * sc.ppc
         total += n * 2 * state + (n * 4 if sc.nu > 0 else 0)
-    tiles = wl.cells // (tile * tile)
-    total += tiles * (6 * (tile + 2) ** 2 * r + 3 * (tile + 3) ** 2 * r)
+    tiles = wl.cells // tile ** d
+    total += tiles * (6 * (tile + 2) ** d * r + 3 * (tile + 3) ** d * r)
     return total
 
 
@@ -50,7 +55,7 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int):
+def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, graph_steps=None):
     import torch
     from paper_0808_4078_amd import pic
 
@@ -75,14 +80,17 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     torch.cuda.synchronize()
     prof_ms = p0.elapsed_time(p1)
     # the next K steps as graph replays (reported beside the timed region)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    run.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    run.sync()
-    graph_ms = e0.elapsed_time(e1)
+    gsteps = steps if graph_steps is None else graph_steps
+    graph_ms = float("nan")
+    if gsteps > 0:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run.step(gsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        run.sync()
+        graph_ms = e0.elapsed_time(e1) * steps / gsteps
     progress(f"{wl.name} {precision}: {steps} steps {prof_ms / steps:.3f} ms/step (timed, per-kernel events), "
              f"{graph_ms / steps:.3f} ms/step (graph replay of the next {steps}); particle kernel "
              f"{groups['particle'] / steps:.3f} ms")
@@ -132,6 +140,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="256^2 grid instead of 1024^2 (for profiling)")
+    ap.add_argument("--c4", type=int, default=0, metavar="K",
+                    help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} refused: this PIC build runs on a single GPU "
@@ -191,6 +201,17 @@ def main():
                        "particle_kernel_GBs": f_bytes / (f_pk * 1e-3) / 1e9,
                        "step_breakdown_ms": {k: v / a.steps for k, v in fp64["groups_ms"].items()}}
         rec["mixed_over_fp64"] = rec["value"] / rec["fp64"]["value"]
+    if a.c4 > 0:
+        c4 = run_gpu(synth.C4, "mixed", a.c4, min(a.warmup, 5), 8, a.diag_every, graph_steps=0)
+        c4_pk = c4["groups_ms"]["particle"] / a.c4
+        c4_bytes = particle_kernel_bytes(synth.C4, "mixed", 8)
+        rec["c4"] = {"workload": "C4: 3D3V periodic 256x256x512, dx=0.2, dt=0.1, 8 ppc per species, beam "
+                                 "gamma=3 u_th=0.1 + collisionless return-current plasma, mixed precision",
+                     "particles": c4["particles"], "steps": a.c4,
+                     "value": c4["particles"] / (c4["profiled_ms"] / a.c4 * 1e-3),
+                     "ms_per_step": c4["profiled_ms"] / a.c4, "particle_kernel_ms": c4_pk,
+                     "particle_kernel_GBs": c4_bytes / (c4_pk * 1e-3) / 1e9,
+                     "step_breakdown_ms": {k: v / a.c4 for k, v in c4["groups_ms"].items()}}
     if not a.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

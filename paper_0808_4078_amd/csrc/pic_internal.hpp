@@ -102,7 +102,24 @@ struct KParams {
     int32_t *rb_start;   // [nspecies][tiles]
     int32_t *rb_cap;     // [nspecies][tiles]
     int32_t *rb_fill;    // [nspecies][tiles]
+    int fd_blocks;       // blocks (and partial records) of the field-diagnostic reduction
 };
+
+// An ensemble of runs stepped together: every launch of a step covers all
+// runs.  Runs share precision, dimension and tile edge.
+struct BatchTable {
+    int nruns;
+    int n_items;          // particle-kernel work items
+    int n_cell_blocks;    // 256-cell blocks over all runs
+    int nst_blocks;       // max over runs of ceil(nspecies * tiles / 256)
+    int max_species;
+    const KParams *const *kp;   // [nruns] device parameter blocks
+    const int2 *items;          // [n_items] (run, tile), heaviest tiles first
+    const int2 *cell_blocks;    // [n_cell_blocks] (run, block of that run)
+    int *queue;                 // work counter of the persistent particle kernel
+};
+constexpr int kBatchFieldDiagBlocks = 32;
+constexpr int kBatchRebinBlocks = 64;
 
 // Host-callable launchers (defined in the .hip translation units).
 // Kernels of one step and the group each belongs to: field-diag (0),
@@ -112,6 +129,8 @@ constexpr int kStepKernels = 13;
 constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
 // ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
+hipError_t launch_batch_step(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int persistent_blocks,
+                             hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
 hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);
 hipError_t launch_shift_u(const KParams &hp, const KParams *dp, int s, double dux, double duy,

@@ -35,6 +35,26 @@ namespace pic {
 #define GLB __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ GLB T *gbl(T *p) { return (GLB T *)p; }
 template <typename T> __device__ __forceinline__ const GLB T *gbl(const T *p) { return (const GLB T *)p; }
+// Element access with a 32-bit byte offset from a scalar base (every
+// particle array is smaller than 4 GiB; pic_query checks it), which maps to
+// the base-register + 32-bit-offset form of global loads and stores.
+template <typename T> __device__ __forceinline__ T ld(const GLB T *base, uint32_t i)
+{
+    return *(const GLB T *)((const GLB char *)base + i * (uint32_t)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ void st(GLB T *base, uint32_t i, T v)
+{
+    *(GLB T *)((GLB char *)base + i * (uint32_t)sizeof(T)) = v;
+}
+
+// LDS current deposit.  Most particles do not cross a node line in a step, so
+// many window weights are exactly zero; skipping them keeps those lanes off
+// the LDS atomic unit.
+template <typename A, typename R>
+__device__ __forceinline__ void lds_add(A *p, R v)
+{
+    if (v != R(0)) atomicAdd(p, A(v));
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
@@ -69,6 +89,21 @@ template <> struct Arith<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ void sc(double a, double *s, double *c) { sincos(a, s, c); }
 };
+
+// The step counter and particle-set parity live in memory that kernels also
+// update; reading them through readfirstlane tells the compiler they are
+// uniform, so everything indexed by them stays in scalar registers.
+__device__ __forceinline__ int64_t uniform_step(const KParams *kp)
+{
+    const int64_t v = kp->state->step;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform_par(const KParams *kp)
+{
+    return __builtin_amdgcn_readfirstlane(kp->state->par);
+}
 
 __device__ __forceinline__ bool diag_step(const KParams *kp, int64_t step)
 {
@@ -107,16 +142,16 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*sred)[N])
 // ---------------------------------------------------------------------------
 // Field energies W_i = sum F_i^2 dV and z field momentum of E^n, B^n.
 template <typename R>
-__global__ __launch_bounds__(256) void k_field_diag(const KParams *__restrict__ kp)
+__device__ __forceinline__ void field_diag_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     __shared__ double sred[4][7];
-    const int64_t step = kp->state->step;
+    const int64_t step = uniform_step(kp);
     if (!diag_step(kp, step)) return;
     const R *F = (const R *)kp->F;
     const int64_t cells = kp->g.cells;
     const int64_t nxy = (int64_t)kp->g.n[0] * kp->g.n[1];
     double a[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < cells; o += (int64_t)gridDim.x * 256) {
+    for (int64_t o = (int64_t)bid * 256 + threadIdx.x; o < cells; o += (int64_t)nb * 256) {
         double v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -131,7 +166,7 @@ __global__ __launch_bounds__(256) void k_field_diag(const KParams *__restrict__ 
     }
     block_sum<7>(a, sred);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 7; ++c) kp->field_diag[blockIdx.x * kFieldDiag + c] = a[c];
+        for (int c = 0; c < 7; ++c) kp->field_diag[bid * kFieldDiag + c] = a[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -165,8 +200,10 @@ __device__ __forceinline__ R interp(const R *F, int bx, int by, int bz, R x0, R 
     return v;
 }
 
+constexpr int kBatch = 2;   // particles fetched per lane before processing
+
 template <typename R, typename A, int D, int T>
-__global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
+__device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     constexpr int NF = T + 2;
     constexpr int NJ = T + 3;
@@ -178,7 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
     __shared__ uint32_t s_front;
     __shared__ double sred[kBlock / 64][kTileDiag];
 
-    const int tile = blockIdx.x;
+    const int tile = bid;
+    (void)nb;
     const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
     const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
     const int ntiles = kp->g.ntiles;
@@ -186,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
     t0[0] = (tile % ntx) * T;
     t0[1] = ((tile / ntx) % nty) * T;
     t0[2] = (tile / (ntx * nty)) * T;
-    const int64_t step = kp->state->step;
-    const int src = kp->state->par, dst = src ^ 1;
+    const int64_t step = uniform_step(kp);
+    const int src = uniform_par(kp), dst = src ^ 1;
     const bool diag = diag_step(kp, step);
     const int lane = threadIdx.x & 63;
     const int tsh = kp->g.tshift[0];
@@ -255,13 +293,50 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
         const GLB uint32_t *__restrict__ cb_src = gbl(S.cnt_back + src * ntiles);
         GLB uint32_t *cb_dst = gbl(S.cnt_back + dst * ntiles);
 
+        GLB uint32_t *__restrict__ ocell = gbl(S.cell[dst]);
+        GLB R *__restrict__ opos_a[3] = {gbl((R *)S.pos[dst][0]), gbl((R *)S.pos[dst][1]), gbl((R *)S.pos[dst][2])};
+        GLB R *__restrict__ ou0 = gbl((R *)S.u[dst][0]);
+        GLB R *__restrict__ ou1 = gbl((R *)S.u[dst][1]);
+        GLB R *__restrict__ ou2 = gbl((R *)S.u[dst][2]);
+        GLB uint32_t *__restrict__ oid = gbl(S.id[dst]);
+
         if (threadIdx.x == 0) s_front = 0;
         __syncthreads();
 
+        // Raw fields of one particle as stored.  Each lane fetches kBatch
+        // particles (k, k+256, ...) before processing them, so a wave keeps
+        // kBatch particles' loads in flight.
+        struct Raw {
+            uint32_t c;
+            R p[D];
+            R u[3];
+            uint32_t id;
+        };
+        auto fetch = [&](uint32_t k, Raw &r) {
+            const uint32_t slot = k < nf ? (uint32_t)bstart + k : (uint32_t)(bstart + bcap) - nb + (k - nf);
+            if constexpr (sizeof(R) == 4) r.c = ld(icell, slot);
+#pragma unroll
+            for (int a = 0; a < D; ++a) r.p[a] = ld(ipos[a], slot);
+            r.u[0] = ld(iu0, slot);
+            r.u[1] = ld(iu1, slot);
+            r.u[2] = ld(iu2, slot);
+            r.id = track ? ld(iid, slot) : 0u;
+        };
         double acc[kTileDiag] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t base = 0; base < total; base += kBlock) {
-            const uint32_t k = base + threadIdx.x;
+        for (uint32_t base = 0; base < total; base += kBatch * kBlock) {
+            Raw q[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const uint32_t kk = base + u * kBlock + threadIdx.x;
+                if (kk < total) fetch(kk, q[u]);
+            }
+#pragma unroll 1
+            for (int u = 0; u < kBatch; ++u) {
+            const uint32_t k = base + u * kBlock + threadIdx.x;
             const bool active = k < total;
+            const Raw cur = q[0];
+#pragma unroll
+            for (int v = 0; v + 1 < kBatch; ++v) q[v] = q[v + 1];
             int ic1[D];
             R off1[D];
             int t1 = -1;
@@ -269,28 +344,26 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
             uint32_t pid = 0;
             for (int a = 0; a < D; ++a) { ic1[a] = 0; off1[a] = R(0); }
             if (active) {
-                const int64_t slot = k < nf ? (int64_t)bstart + k : (int64_t)bstart + bcap - nb + (k - nf);
                 int ic[3] = {0, 0, 0};
                 R off[3] = {R(0), R(0), R(0)};
                 if constexpr (sizeof(R) == 4) {
-                    const uint32_t c = icell[slot];
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        ic[a] = (int)((c >> csh[a]) & cmask[a]);
-                        off[a] = ipos[a][slot];
+                        ic[a] = (int)((cur.c >> csh[a]) & cmask[a]);
+                        off[a] = cur.p[a];
                     }
                 } else {
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        const double X = ipos[a][slot];
+                        const double X = cur.p[a];
                         ic[a] = (int)floor(X);
                         off[a] = X - ic[a];
                     }
                 }
-                ux = iu0[slot];
-                uy = iu1[slot];
-                uz = iu2[slot];
-                if (track) pid = iid[slot];
+                ux = cur.u[0];
+                uy = cur.u[1];
+                uz = cur.u[2];
+                pid = cur.id;
                 const R uox = ux, uoy = uy, uoz = uz;
 
                 // ---- gather: linear weights at each component's stagger
@@ -358,19 +431,19 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
                         const R qy = R(0.5) * S0[1][b] + R(1.0 / 3.0) * DS[1][b];
                         const R j0 = -kd[0] * (DS[0][0] * ry);
                         const R j1 = j0 - kd[0] * (DS[0][1] * ry);
-                        atomicAdd(&sJx[w0 + b * SJ_Y], A(j0));
-                        atomicAdd(&sJx[w0 + b * SJ_Y + 1], A(j1));
+                        lds_add(&sJx[w0 + b * SJ_Y], j0);
+                        lds_add(&sJx[w0 + b * SJ_Y + 1], j1);
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
-                            atomicAdd(&sJz[w0 + b * SJ_Y + a], A(kzv * (S0[0][a] * ry + DS[0][a] * qy)));
+                            lds_add(&sJz[w0 + b * SJ_Y + a], kzv * (S0[0][a] * ry + DS[0][a] * qy));
                     }
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const R rx = S0[0][a] + R(0.5) * DS[0][a];
                         const R j0 = -kd[1] * (DS[1][0] * rx);
                         const R j1 = j0 - kd[1] * (DS[1][1] * rx);
-                        atomicAdd(&sJy[w0 + a], A(j0));
-                        atomicAdd(&sJy[w0 + SJ_Y + a], A(j1));
+                        lds_add(&sJy[w0 + a], j0);
+                        lds_add(&sJy[w0 + SJ_Y + a], j1);
                     }
                 } else {
                     // pair factors P_pq[m][l] = S0p S0q + DSp S0q/2 + S0p DSq/2 + DSp DSq/3
@@ -386,8 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
                             const R j0 = -kd[0] * (DS[0][0] * pyz);
                             const R j1 = j0 - kd[0] * (DS[0][1] * pyz);
                             const int o = w0 + c * SJ_Z + b * SJ_Y;
-                            atomicAdd(&sJx[o], A(j0));
-                            atomicAdd(&sJx[o + 1], A(j1));
+                            lds_add(&sJx[o], j0);
+                            lds_add(&sJx[o + 1], j1);
                         }
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
@@ -397,8 +470,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
                             const R j0 = -kd[1] * (DS[1][0] * pxz);
                             const R j1 = j0 - kd[1] * (DS[1][1] * pxz);
                             const int o = w0 + c * SJ_Z + a;
-                            atomicAdd(&sJy[o], A(j0));
-                            atomicAdd(&sJy[o + SJ_Y], A(j1));
+                            lds_add(&sJy[o], j0);
+                            lds_add(&sJy[o + SJ_Y], j1);
                         }
 #pragma unroll
                     for (int b = 0; b < 3; ++b)
@@ -408,8 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
                             const R j0 = -kd[2] * (DS[2][0] * pxy);
                             const R j1 = j0 - kd[2] * (DS[2][1] * pxy);
                             const int o = w0 + b * SJ_Y + a;
-                            atomicAdd(&sJz[o], A(j0));
-                            atomicAdd(&sJz[o + SJ_Z], A(j1));
+                            lds_add(&sJz[o], j0);
+                            lds_add(&sJz[o + SJ_Z], j1);
                         }
                 }
 
@@ -461,46 +534,70 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
             // ---- binning
             const bool stay = active && t1 == tile;
             const uint64_t smask = __ballot(stay);
-            int64_t opos = -1;
+            uint32_t opos = 0;
+            bool wr = false;
             if (smask) {
                 const int leader = __ffsll((unsigned long long)smask) - 1;
                 uint32_t bfront = 0;
                 if (lane == leader) bfront = atomicAdd(&s_front, (uint32_t)__popcll(smask));
-                bfront = __shfl(bfront, leader, 64);
+                bfront = __builtin_amdgcn_readlane(bfront, leader);
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(smask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)smask, 0u));
-                if (stay) opos = (int64_t)bstart + bfront + rank;
+                if (stay) {
+                    opos = (uint32_t)bstart + bfront + rank;
+                    wr = true;
+                }
             }
             bool to_ovf = false;
             if (active && !stay) {
                 const uint32_t b = __hip_atomic_fetch_add(cb_dst + t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int64_t room = (int64_t)tcap[t1] - (int64_t)cf_src[t1] - (int64_t)cb_src[t1];
-                if ((int64_t)b < room) opos = (int64_t)tstart[t1] + tcap[t1] - 1 - b;
-                else to_ovf = true;
+                if ((int64_t)b < room) {
+                    opos = (uint32_t)(tstart[t1] + tcap[t1] - 1) - b;
+                    wr = true;
+                } else {
+                    to_ovf = true;
+                }
             }
-            int set = dst;
-            if (to_ovf) {
-                const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
-                state->rebin = 1;
-                if (oi < S.ovf_cap) { opos = oi; set = 2; }
-                else atomicOr(&state->fatal, 1);
+            uint32_t cpack = 0;
+            if constexpr (sizeof(R) == 4) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) cpack |= (uint32_t)ic1[a] << csh[a];
             }
-            if (opos >= 0) {
+            if (wr) {
                 if constexpr (sizeof(R) == 4) {
-                    uint32_t c = 0;
+                    st(ocell, opos, cpack);
 #pragma unroll
-                    for (int a = 0; a < D; ++a) c |= (uint32_t)ic1[a] << csh[a];
-                    gbl(S.cell[set])[opos] = c;
-#pragma unroll
-                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[set][a])[opos] = off1[a];
+                    for (int a = 0; a < D; ++a) st(opos_a[a], opos, off1[a]);
                 } else {
 #pragma unroll
-                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[set][a])[opos] = (double)ic1[a] + off1[a];
+                    for (int a = 0; a < D; ++a) st(opos_a[a], opos, R((double)ic1[a] + off1[a]));
                 }
-                gbl((R *)S.u[set][0])[opos] = ux;
-                gbl((R *)S.u[set][1])[opos] = uy;
-                gbl((R *)S.u[set][2])[opos] = uz;
-                if (track) gbl(S.id[set])[opos] = pid;
+                st(ou0, opos, ux);
+                st(ou1, opos, uy);
+                st(ou2, opos, uz);
+                if (track) st(oid, opos, pid);
+            }
+            if (to_ovf) {
+                // no room left in the new tile's bin: overflow list (set 2),
+                // re-laid out at the end of the step
+                const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
+                state->rebin = 1;
+                if (oi < S.ovf_cap) {
+                    if constexpr (sizeof(R) == 4) {
+                        gbl(S.cell[2])[oi] = cpack;
+                        for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = off1[a];
+                    } else {
+                        for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = (double)ic1[a] + off1[a];
+                    }
+                    gbl((R *)S.u[2][0])[oi] = ux;
+                    gbl((R *)S.u[2][1])[oi] = uy;
+                    gbl((R *)S.u[2][2])[oi] = uz;
+                    if (track) gbl(S.id[2])[oi] = pid;
+                } else {
+                    atomicOr(&state->fatal, 1);
+                }
+            }
             }
         }
         __syncthreads();
@@ -522,12 +619,12 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
 // Data of the step sits in set dst (bins) and set 2 (overflow list); it is
 // rewritten into set src with capacities count + a uniform reserve, and the
 // parity is kept so that the next step reads set src.
-__global__ void k_rebin_count(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_count_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const DevState *st = kp->state;
     if (!st->rebin) return;
     const int ntiles = kp->g.ntiles;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
     if (i >= (int64_t)kp->nspecies * ntiles) return;
     const int s = (int)(i / ntiles), t = (int)(i % ntiles);
     const SpeciesDev &S = kp->sp[s];
@@ -554,50 +651,72 @@ __device__ __forceinline__ int tile_of(const KParams *kp, const SpeciesDev &S, i
 }
 
 template <typename R>
-__global__ void k_rebin_count_ovf(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_count_ovf_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const DevState *st = kp->state;
     if (!st->rebin) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
     for (int s = 0; s < kp->nspecies; ++s) {
         const SpeciesDev &S = kp->sp[s];
         const int64_t n = min((int64_t)st->ovf_count[s], (int64_t)S.ovf_cap);
-        for (int64_t p = i; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t p = i; p < n; p += (int64_t)nb * blockDim.x)
             atomicAdd(&kp->rb_count[(int64_t)s * kp->g.ntiles + tile_of<R>(kp, S, 2, p)], 1);
     }
 }
 
 // one block per species: capacities = count + uniform reserve, exclusive scan
-__global__ __launch_bounds__(256) void k_rebin_scan(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_scan_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     __shared__ int64_t spart[256];
+    __shared__ int64_t s_total;
     DevState *st = kp->state;
     if (!st->rebin) return;
-    const int s = blockIdx.x;
+    const int s = bid;
+    if (s >= kp->nspecies) return;
     const SpeciesDev &S = kp->sp[s];
     const int ntiles = kp->g.ntiles;
     const int32_t *cnt = kp->rb_count + (int64_t)s * ntiles;
     const int chunk = (ntiles + 255) / 256;
     const int t0 = threadIdx.x * chunk, t1 = min(t0 + chunk, ntiles);
+    // pass 1: particle total
     int64_t local = 0;
     for (int t = t0; t < t1; ++t) local += cnt[t];
     spart[threadIdx.x] = local;
     __syncthreads();
-    __shared__ int64_t s_total;
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int i = 0; i < 256; ++i) tot += spart[i];
+        s_total = tot;
+    }
+    __syncthreads();
+    // reserve of tile t: m + floor(rest * count_t / total), which sums to at
+    // most the free slots; busy tiles get proportionally more room
+    const int64_t total = s_total;
+    const int64_t slack = S.ncap - total;
+    if (slack < 0) {
+        if (threadIdx.x == 0) atomicOr(&st->fatal, 4);
+        return;
+    }
+    const int64_t m = min((int64_t)64, slack / (2 * (int64_t)ntiles));
+    const int64_t rest = slack - m * ntiles;
+    auto reserve = [&](int64_t c) { return m + (total > 0 ? (rest * c) / total : rest / ntiles); };
+    // pass 2: exclusive scan of count + reserve
+    local = 0;
+    for (int t = t0; t < t1; ++t) local += cnt[t] + reserve(cnt[t]);
+    __syncthreads();
+    spart[threadIdx.x] = local;
+    __syncthreads();
     if (threadIdx.x == 0) {
         int64_t run = 0;
         for (int i = 0; i < 256; ++i) { const int64_t v = spart[i]; spart[i] = run; run += v; }
-        s_total = run;
     }
     __syncthreads();
-    const int64_t reserve = (S.ncap - s_total) / ntiles;
-    if (reserve < 0 && threadIdx.x == 0) atomicOr(&st->fatal, 4);
-    const int64_t rv = reserve < 0 ? 0 : reserve;
-    int64_t off = spart[threadIdx.x] + rv * t0;
+    int64_t off = spart[threadIdx.x];
     for (int t = t0; t < t1; ++t) {
+        const int64_t c = cnt[t] + reserve(cnt[t]);
         kp->rb_start[(int64_t)s * ntiles + t] = (int32_t)off;
-        kp->rb_cap[(int64_t)s * ntiles + t] = (int32_t)(cnt[t] + rv);
-        off += cnt[t] + rv;
+        kp->rb_cap[(int64_t)s * ntiles + t] = (int32_t)c;
+        off += c;
     }
 }
 
@@ -613,13 +732,13 @@ __device__ __forceinline__ void copy_particle(const KParams *kp, const SpeciesDe
 
 // copy each tile's valid bin contents dst -> src (blocks stride over (tile, species))
 template <typename R>
-__global__ __launch_bounds__(256) void k_rebin_scatter(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_scatter_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const DevState *st = kp->state;
     if (!st->rebin || (st->fatal & 4)) return;
     const int ntiles = kp->g.ntiles;
     const int src = st->par, dst = src ^ 1;
-    for (int pair = blockIdx.x; pair < ntiles * kp->nspecies; pair += gridDim.x) {
+    for (int pair = bid; pair < ntiles * kp->nspecies; pair += nb) {
         const int s = pair / ntiles, t = pair - s * ntiles;
         const SpeciesDev &S = kp->sp[s];
         const int64_t room = (int64_t)S.cap[t] - S.cnt_front[src * ntiles + t] - S.cnt_back[src * ntiles + t];
@@ -635,16 +754,16 @@ __global__ __launch_bounds__(256) void k_rebin_scatter(const KParams *__restrict
 }
 
 template <typename R>
-__global__ void k_rebin_scatter_ovf(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_scatter_ovf_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const DevState *st = kp->state;
     if (!st->rebin || (st->fatal & 4)) return;
     const int src = st->par;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
     for (int s = 0; s < kp->nspecies; ++s) {
         const SpeciesDev &S = kp->sp[s];
         const int64_t n = min((int64_t)st->ovf_count[s], (int64_t)S.ovf_cap);
-        for (int64_t p = i; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t p = i; p < n; p += (int64_t)nb * blockDim.x) {
             const int64_t idx = (int64_t)s * kp->g.ntiles + tile_of<R>(kp, S, 2, p);
             const int32_t slot = atomicAdd(&kp->rb_fill[idx], 1);
             copy_particle<R>(kp, S, 2, p, src, (int64_t)kp->rb_start[idx] + slot);
@@ -652,12 +771,12 @@ __global__ void k_rebin_scatter_ovf(const KParams *__restrict__ kp)
     }
 }
 
-__global__ void k_rebin_finalize(const KParams *__restrict__ kp)
+__device__ __forceinline__ void rebin_finalize_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const DevState *st = kp->state;
     if (!st->rebin || (st->fatal & 4)) return;
     const int ntiles = kp->g.ntiles;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
     if (i >= (int64_t)kp->nspecies * ntiles) return;
     const int s = (int)(i / ntiles), t = (int)(i % ntiles);
     const SpeciesDev &S = kp->sp[s];
@@ -674,10 +793,10 @@ __global__ void k_rebin_finalize(const KParams *__restrict__ kp)
 // Along an axis, node i = a0*T + r is held by tile a0 (local r+1), by tile
 // a0-1 when r <= 1 (local r+T+1) and by tile a0+1 when r = T-1 (local 0).
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_reduce_j(const KParams *__restrict__ kp)
+__device__ __forceinline__ void reduce_j_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const int64_t cells = kp->g.cells;
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = (int64_t)bid * blockDim.x + threadIdx.x;
     if (o >= cells) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1];
     const int idx[3] = {(int)(o % nx), (int)((o / nx) % ny), (int)(o / ((int64_t)nx * ny))};
@@ -726,12 +845,12 @@ __global__ __launch_bounds__(256) void k_reduce_j(const KParams *__restrict__ kp
 // ---------------------------------------------------------------------------
 // Yee updates (2D: n[2] == 1 and every z difference vanishes).
 template <typename R, int NDIM>
-__global__ __launch_bounds__(256) void k_yee_b(const KParams *__restrict__ kp, double h)
+__device__ __forceinline__ void yee_b_body(const KParams *__restrict__ kp, int bid, int nb, double h)
 {
     if (h == 0.0) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1], nz = NDIM == 3 ? kp->g.n[2] : 1;
     const int64_t cells = kp->g.cells;
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = (int64_t)bid * blockDim.x + threadIdx.x;
     if (o >= cells) return;
     const int i = (int)(o % nx);
     const int j = (int)((o / nx) % ny);
@@ -760,12 +879,12 @@ __global__ __launch_bounds__(256) void k_yee_b(const KParams *__restrict__ kp, d
 }
 
 template <typename R, int NDIM>
-__global__ __launch_bounds__(256) void k_yee_e(const KParams *__restrict__ kp)
+__device__ __forceinline__ void yee_e_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     if (kp->flags & PIC_FLAG_FREEZE_FIELDS) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1];
     const int64_t cells = kp->g.cells;
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = (int64_t)bid * blockDim.x + threadIdx.x;
     if (o >= cells) return;
     const int i = (int)(o % nx);
     const int j = (int)((o / nx) % ny);
@@ -796,7 +915,7 @@ __global__ __launch_bounds__(256) void k_yee_e(const KParams *__restrict__ kp)
 // ---------------------------------------------------------------------------
 // End of step: diagnostic record, reset of the next destination's mover
 // counters, step and parity update.  One workgroup.
-__global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
+__device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     __shared__ double sred[4][8];
     DevState *st = kp->state;
@@ -808,7 +927,7 @@ __global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
     if (diag_step(kp, step)) {
         const double dv = kp->g.d[0] * kp->g.d[1] * (kp->g.ndim == 3 ? kp->g.d[2] : 1.0);
         double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int b = threadIdx.x; b < kFieldDiagBlocks; b += blockDim.x)
+        for (int b = threadIdx.x; b < kp->fd_blocks; b += blockDim.x)
             for (int c = 0; c < 7; ++c) f[c] += kp->field_diag[b * kFieldDiag + c];
         block_sum<8>(f, sred);
         pic_diag rec;
@@ -858,6 +977,132 @@ __global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
             st->par = par ^ 1;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel entry points.  k_*: one run, the grid covers that run's blocks.
+// kb_*: an ensemble; blockIdx.y picks the run, or a table maps each block to
+// (run, block of that run), or (particle kernel) persistent workgroups take
+// (run, tile) items from a queue, heaviest first.
+template <typename R>
+__global__ __launch_bounds__(256) void k_field_diag(const KParams *__restrict__ kp)
+{
+    field_diag_body<R>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void kb_field_diag(const BatchTable *__restrict__ bt)
+{
+    field_diag_body<R>(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+template <typename R, typename A, int D, int T>
+__global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
+{
+    particle_body<R, A, D, T>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R, typename A, int D, int T>
+__global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restrict__ bt)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(bt->queue, 1);
+        __syncthreads();
+        const int i = s_item;
+        __syncthreads();
+        if (i >= bt->n_items) break;
+        const int2 it = bt->items[i];
+        particle_body<R, A, D, T>(bt->kp[it.x], it.y, 0);
+    }
+}
+
+#define PIC_RUN_KERNELS(NAME, BODY)                                                     \
+    __global__ __launch_bounds__(256) void k_##NAME(const KParams *__restrict__ kp)    \
+    {                                                                                   \
+        BODY(kp, blockIdx.x, gridDim.x);                                                \
+    }                                                                                   \
+    __global__ __launch_bounds__(256) void kb_##NAME(const BatchTable *__restrict__ bt) \
+    {                                                                                   \
+        BODY(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);                                \
+    }
+PIC_RUN_KERNELS(rebin_count, rebin_count_body)
+PIC_RUN_KERNELS(rebin_scan, rebin_scan_body)
+PIC_RUN_KERNELS(rebin_finalize, rebin_finalize_body)
+#undef PIC_RUN_KERNELS
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_rebin_count_ovf(const KParams *__restrict__ kp)
+{
+    rebin_count_ovf_body<R>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void kb_rebin_count_ovf(const BatchTable *__restrict__ bt)
+{
+    rebin_count_ovf_body<R>(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_rebin_scatter(const KParams *__restrict__ kp)
+{
+    rebin_scatter_body<R>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void kb_rebin_scatter(const BatchTable *__restrict__ bt)
+{
+    rebin_scatter_body<R>(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_rebin_scatter_ovf(const KParams *__restrict__ kp)
+{
+    rebin_scatter_ovf_body<R>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void kb_rebin_scatter_ovf(const BatchTable *__restrict__ bt)
+{
+    rebin_scatter_ovf_body<R>(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_reduce_j(const KParams *__restrict__ kp)
+{
+    reduce_j_body<R, D>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R, int D>
+__global__ __launch_bounds__(256) void kb_reduce_j(const BatchTable *__restrict__ bt)
+{
+    const int2 cb = bt->cell_blocks[blockIdx.x];
+    reduce_j_body<R, D>(bt->kp[cb.x], cb.y, 0);
+}
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_yee_b(const KParams *__restrict__ kp, double h)
+{
+    yee_b_body<R, D>(kp, blockIdx.x, gridDim.x, h);
+}
+template <typename R, int D>
+__global__ __launch_bounds__(256) void kb_yee_b(const BatchTable *__restrict__ bt, double h)
+{
+    const int2 cb = bt->cell_blocks[blockIdx.x];
+    yee_b_body<R, D>(bt->kp[cb.x], cb.y, 0, h);
+}
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_yee_e(const KParams *__restrict__ kp)
+{
+    yee_e_body<R, D>(kp, blockIdx.x, gridDim.x);
+}
+template <typename R, int D>
+__global__ __launch_bounds__(256) void kb_yee_e(const BatchTable *__restrict__ bt)
+{
+    const int2 cb = bt->cell_blocks[blockIdx.x];
+    yee_e_body<R, D>(bt->kp[cb.x], cb.y, 0);
+}
+
+__global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
+{
+    advance_body(kp, blockIdx.x, gridDim.x);
+}
+// one workgroup per run; the first also rewinds the particle-kernel queue
+__global__ __launch_bounds__(256) void kb_advance(const BatchTable *__restrict__ bt)
+{
+    advance_body(bt->kp[blockIdx.x], 0, 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *bt->queue = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,7 +1251,7 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     const unsigned cb = (unsigned)((cells + 255) / 256);
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
     Launcher L{st, ev};
-    L(k_field_diag<R>, dim3(kFieldDiagBlocks), dim3(256), dp);
+    L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
     L(k_particle<R, A, D, T>, dim3(ntiles), dim3(kBlock), dp);
     L(k_rebin_count, dim3(nst), dim3(256), dp);
     L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
@@ -1024,12 +1269,14 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     return hipGetLastError();
 }
 
-// Mixed mode accumulates the tile current in FP32 (the current partials are
-// FP32), FP64 mode in FP64.
+// The tile current is accumulated in FP64 in LDS in both modes: on gfx950 an
+// FP32 LDS atomic add (ds_add_f32) measured 5.4x slower than the FP64 one
+// (ds_add_f64) in this kernel (C3, 14.7 ms against 2.7 ms per launch).  The
+// partial written to HBM is in the run's precision (FP32 in mixed mode).
 template <typename R>
 static hipError_t step_prec(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
-    using A = R;
+    using A = double;
     if (hp.g.ndim == 3) {
         if (hp.g.tile[0] == 8) return step_kernels<R, A, 3, 8>(hp, dp, st, ev);
         return hipErrorInvalidValue;
@@ -1045,6 +1292,53 @@ static hipError_t step_prec(const KParams &hp, const KParams *dp, hipStream_t st
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
     return hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, dp, st, ev) : step_prec<double>(hp, dp, st, ev);
+}
+
+// The same kernel sequence over a whole ensemble (kStepKernels launches).
+template <typename R, typename A, int D, int T>
+static hipError_t batch_kernels(const BatchTable &ht, const BatchTable *dt, int pblocks, hipStream_t st,
+                                hipEvent_t *ev)
+{
+    const unsigned nr = (unsigned)ht.nruns;
+    Launcher L{st, ev};
+    L(kb_field_diag<R>, dim3(kBatchFieldDiagBlocks, nr), dim3(256), dt);
+    L(kb_particle<R, A, D, T>, dim3(pblocks), dim3(kBlock), dt);
+    L(kb_rebin_count, dim3(ht.nst_blocks, nr), dim3(256), dt);
+    L(kb_rebin_count_ovf<R>, dim3(kBatchRebinBlocks, nr), dim3(256), dt);
+    L(kb_rebin_scan, dim3(ht.max_species, nr), dim3(256), dt);
+    L(kb_rebin_scatter<R>, dim3(kBatchRebinBlocks, nr), dim3(256), dt);
+    L(kb_rebin_scatter_ovf<R>, dim3(kBatchRebinBlocks, nr), dim3(256), dt);
+    L(kb_rebin_finalize, dim3(ht.nst_blocks, nr), dim3(256), dt);
+    L(kb_reduce_j<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt);
+    L(kb_yee_b<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt, 0.5);
+    L(kb_yee_e<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt);
+    L(kb_yee_b<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt, 0.5);
+    L(kb_advance, dim3(nr), dim3(256), dt);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t batch_prec(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int pb, hipStream_t st,
+                             hipEvent_t *ev)
+{
+    using A = double;
+    if (hp0.g.ndim == 3) {
+        if (hp0.g.tile[0] == 8) return batch_kernels<R, A, 3, 8>(ht, dt, pb, st, ev);
+        return hipErrorInvalidValue;
+    }
+    switch (hp0.g.tile[0]) {
+    case 8: return batch_kernels<R, A, 2, 8>(ht, dt, pb, st, ev);
+    case 16: return batch_kernels<R, A, 2, 16>(ht, dt, pb, st, ev);
+    case 32: return batch_kernels<R, A, 2, 32>(ht, dt, pb, st, ev);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_step(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int pblocks,
+                             hipStream_t st, hipEvent_t *ev)
+{
+    return hp0.precision == PIC_PREC_MIXED ? batch_prec<float>(hp0, ht, dt, pblocks, st, ev)
+                                           : batch_prec<double>(hp0, ht, dt, pblocks, st, ev);
 }
 
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st)

@@ -143,9 +143,10 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         Layout::Sp &P = L->sp[s];
         P.tile_nominal = (int64_t)S.ppc * tile_cells;
         P.nominal = P.tile_nominal * G.ntiles;
-        P.reserve = std::max<int64_t>(64, (P.tile_nominal + 3) / 4);
+        P.reserve = std::max<int64_t>(64, (P.tile_nominal + 1) / 2);
         P.ncap = (P.tile_nominal + P.reserve) * G.ntiles;
-        if (P.ncap >= ((int64_t)1 << 31)) return fail(err, PIC_E_UNSUPPORTED, "species %d: store exceeds 2^31 slots", s);
+        if (P.ncap * (g->precision == PIC_PREC_MIXED ? 4 : 8) >= ((int64_t)1 << 32))
+            return fail(err, PIC_E_UNSUPPORTED, "species %d: a particle array would exceed 4 GiB", s);
         P.ovf_cap = (uint32_t)std::max<int64_t>(4096, P.ncap / 8);
         id_total += P.nominal;
     }
@@ -478,6 +479,7 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     K.rb_cap = (int32_t *)at(buffers->scratch, L.rb[2]);
     K.rb_fill = (int32_t *)at(buffers->scratch, L.rb[3]);
     r->dp = (KParams *)at(buffers->scratch, L.kparams);
+    K.fd_blocks = kFieldDiagBlocks;
 
 #define INIT_CHK(expr)                                          \
     do {                                                        \
@@ -555,13 +557,16 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
         tile[p] = t;
         count[t] += 1;
     }
-    const int64_t reserve = (P.ncap - n) / nt;
+    // reserve of tile t: m + floor(rest * count_t / n), the device re-layout's rule
+    const int64_t slack = P.ncap - n;
+    const int64_t m = std::min<int64_t>(64, slack / (2 * (int64_t)nt));
+    const int64_t rest = slack - m * nt;
     std::vector<int32_t> start(nt), cap(nt);
     std::vector<uint32_t> front(nt);
     int64_t o = 0;
     for (int t = 0; t < nt; ++t) {
         start[t] = (int32_t)o;
-        cap[t] = (int32_t)(count[t] + reserve);
+        cap[t] = (int32_t)(count[t] + m + (n > 0 ? rest * count[t] / n : rest / nt));
         front[t] = (uint32_t)count[t];
         o += cap[t];
     }
