@@ -79,29 +79,37 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     p1.record(stream)
     torch.cuda.synchronize()
     prof_ms = p0.elapsed_time(p1)
-    # the next K steps as graph replays (reported beside the timed region)
-    gsteps = steps if graph_steps is None else graph_steps
-    graph_ms = float("nan")
-    if gsteps > 0:
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        run.step(gsteps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        run.sync()
-        graph_ms = e0.elapsed_time(e1) * steps / gsteps
-    progress(f"{wl.name} {precision}: {steps} steps {prof_ms / steps:.3f} ms/step (timed, per-kernel events), "
-             f"{graph_ms / steps:.3f} ms/step (graph replay of the next {steps}); particle kernel "
-             f"{groups['particle'] / steps:.3f} ms")
     diag = run.diagnostics()
     n = int(sum(wl.cells * s.ppc for s in wl.species))
-    out = dict(particles=n, init_s=init_s, graph_ms=graph_ms, profiled_ms=prof_ms, groups_ms=groups,
-               diag=diag, device_bytes=run.device_bytes)
+    device_bytes = run.device_bytes
     run.close()
     del run
     torch.cuda.empty_cache()
-    return out
+    # the same steps replayed as captured graphs, from a fresh start (reported
+    # beside the timed region)
+    gsteps = steps if graph_steps is None else graph_steps
+    graph_ms = float("nan")
+    if gsteps > 0:
+        run = pic.Run(g, sp)
+        run.step(warmup)
+        run.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(run.stream)
+        run.step(gsteps)
+        e1.record(run.stream)
+        torch.cuda.synchronize()
+        run.sync()
+        graph_ms = e0.elapsed_time(e1) * steps / gsteps
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+    progress(f"{wl.name} {precision}: {steps} steps {prof_ms / steps:.3f} ms/step (timed, per-kernel events), "
+             f"{graph_ms / steps:.3f} ms/step (graph replay, fresh run); particle kernel "
+             f"{groups['particle'] / steps:.3f} ms; re-layouts {diag['rebins']}")
+    return dict(particles=n, init_s=init_s, graph_ms=graph_ms, profiled_ms=prof_ms, groups_ms=groups,
+                diag=diag, device_bytes=device_bytes)
 
 
 def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
@@ -188,6 +196,7 @@ def main():
         "particle_kernel": {"ms": pk_ms, "particle_steps_per_s": n / (pk_ms * 1e-3),
                             "algorithmic_bytes": pk_bytes},
         "step_breakdown_ms": {k: v / a.steps for k, v in mixed["groups_ms"].items()},
+        "relayouts": mixed["diag"]["rebins"],
         "graph_replay_ms_per_step": mixed["graph_ms"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},

@@ -200,6 +200,152 @@ __device__ __forceinline__ R interp(const R *F, int bx, int by, int bz, R x0, R 
     return v;
 }
 
+// Esirkepov deposit of one move into the LDS current tile.  Positions are
+// in cell units relative to the particle's cell (local cell lc, whose lower
+// node has local index lc): x0 at t^n (in [0,1)), x1 at t^{n+1}.  kd = q w
+// d_a/dt per axis; kzv = q w v_z (2D out-of-plane current).
+//
+// Pair factors P_pq[m][l] = S0p S0q + DSp S0q/2 + S0p DSq/2 + DSp DSq/3 with
+// DS = S1 - S0; W_x = DSx Pyz, W_y = DSy Pxz, W_z = DSz Pxy (3D) and each
+// current is the running sum of -q w (d/dt) W along its own axis.  In 2D,
+// J_z = q w v_z Pxy.
+
+// General case: 3-node window per axis around the node nearest to x0, which
+// holds the form factor before and after any move shorter than half a cell.
+template <typename R, typename A, int D, int NJ>
+__device__ __forceinline__ void deposit_window(A *sJx, A *sJy, A *sJz, const int (&lc)[3], const R (&x0)[3],
+                                               const R (&x1)[3], const R (&kd)[3], R kzv)
+{
+    constexpr int SY = NJ, SZ = NJ * NJ;
+    R S0[3][3], DS[3][3];
+    int w0 = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int ca = x0[a] >= R(0.5) ? 1 : 0;
+        const R d0 = x0[a] - R(ca), d1 = x1[a] - R(ca);
+        S0[a][0] = fmax(R(0), -d0);
+        S0[a][1] = R(1) - fabs(d0);
+        S0[a][2] = fmax(R(0), d0);
+        DS[a][0] = fmax(R(0), -d1) - S0[a][0];
+        DS[a][1] = R(1) - fabs(d1) - S0[a][1];
+        DS[a][2] = fmax(R(0), d1) - S0[a][2];
+        w0 += (lc[a] + ca - 1) * (a == 0 ? 1 : a == 1 ? SY : SZ);
+    }
+    if constexpr (D == 2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const R ry = S0[1][b] + R(0.5) * DS[1][b];
+            const R qy = R(0.5) * S0[1][b] + R(1.0 / 3.0) * DS[1][b];
+            const R j0 = -kd[0] * (DS[0][0] * ry);
+            const R j1 = j0 - kd[0] * (DS[0][1] * ry);
+            lds_add(&sJx[w0 + b * SY], j0);
+            lds_add(&sJx[w0 + b * SY + 1], j1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lds_add(&sJz[w0 + b * SY + a], kzv * (S0[0][a] * ry + DS[0][a] * qy));
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R rx = S0[0][a] + R(0.5) * DS[0][a];
+            const R j0 = -kd[1] * (DS[1][0] * rx);
+            const R j1 = j0 - kd[1] * (DS[1][1] * rx);
+            lds_add(&sJy[w0 + a], j0);
+            lds_add(&sJy[w0 + SY + a], j1);
+        }
+    } else {
+        auto P = [&](int p, int q, int m, int l) {
+            return S0[p][m] * (S0[q][l] + R(0.5) * DS[q][l]) + DS[p][m] * (R(0.5) * S0[q][l] + R(1.0 / 3.0) * DS[q][l]);
+        };
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const R pyz = P(1, 2, b, c);
+                const R j0 = -kd[0] * (DS[0][0] * pyz);
+                const R j1 = j0 - kd[0] * (DS[0][1] * pyz);
+                const int o = w0 + c * SZ + b * SY;
+                lds_add(&sJx[o], j0);
+                lds_add(&sJx[o + 1], j1);
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R pxz = P(0, 2, a, c);
+                const R j0 = -kd[1] * (DS[1][0] * pxz);
+                const R j1 = j0 - kd[1] * (DS[1][1] * pxz);
+                const int o = w0 + c * SZ + a;
+                lds_add(&sJy[o], j0);
+                lds_add(&sJy[o + SY], j1);
+            }
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R pxy = P(0, 1, a, b);
+                const R j0 = -kd[2] * (DS[2][0] * pxy);
+                const R j1 = j0 - kd[2] * (DS[2][1] * pxy);
+                const int o = w0 + b * SY + a;
+                lds_add(&sJz[o], j0);
+                lds_add(&sJz[o + SZ], j1);
+            }
+    }
+}
+
+// A particle that stays in its cell (x1 in [0,1) on every axis): the form
+// factors live on the cell's two nodes per axis, S0 = (1-x0, x0) and
+// DS = (-dx, dx), and the window's nonzero entries reduce to
+//   J_x(i+1/2, j+b) = kd_x dx (S0y + DSy/2)[b]  (the y average over the move)
+// and likewise for y (and z); in 2D J_z(i+a, j+b) = kzv (S0x[a] ry[b] + DSx[a] qy[b]).
+template <typename R, typename A, int D, int NJ>
+__device__ __forceinline__ void deposit_cell(A *sJx, A *sJy, A *sJz, const int (&lc)[3], const R (&x0)[3],
+                                             const R (&x1)[3], const R (&kd)[3], R kzv)
+{
+    constexpr int SY = NJ, SZ = NJ * NJ;
+    R dd[3], m[3], s0[3][2], ds[3][2], h[3][2], q[3][2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dd[a] = x1[a] - x0[a];
+        m[a] = x0[a] + R(0.5) * dd[a];
+        s0[a][0] = R(1) - x0[a];
+        s0[a][1] = x0[a];
+        ds[a][0] = -dd[a];
+        ds[a][1] = dd[a];
+        h[a][0] = R(1) - m[a];                                   // S0 + DS/2
+        h[a][1] = m[a];
+        q[a][0] = R(0.5) * s0[a][0] - R(1.0 / 3.0) * dd[a];     // S0/2 + DS/3
+        q[a][1] = R(0.5) * s0[a][1] + R(1.0 / 3.0) * dd[a];
+    }
+    int o = lc[0] + lc[1] * SY;
+    if constexpr (D == 3) o += lc[2] * SZ;
+    if constexpr (D == 2) {
+        const R jx = kd[0] * dd[0], jy = kd[1] * dd[1];
+        atomicAdd(&sJx[o], A(jx * h[1][0]));
+        atomicAdd(&sJx[o + SY], A(jx * h[1][1]));
+        atomicAdd(&sJy[o], A(jy * h[0][0]));
+        atomicAdd(&sJy[o + 1], A(jy * h[0][1]));
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                atomicAdd(&sJz[o + b * SY + a], A(kzv * (s0[0][a] * h[1][b] + ds[0][a] * q[1][b])));
+    } else {
+        auto P = [&](int p, int r, int i, int l) { return s0[p][i] * h[r][l] + ds[p][i] * q[r][l]; };
+        const R jx = kd[0] * dd[0], jy = kd[1] * dd[1], jz = kd[2] * dd[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                atomicAdd(&sJx[o + c * SZ + b * SY], A(jx * P(1, 2, b, c)));
+                atomicAdd(&sJy[o + c * SZ + b], A(jy * P(0, 2, b, c)));
+                atomicAdd(&sJz[o + c * SY + b], A(jz * P(0, 1, b, c)));
+            }
+    }
+}
+
+// Crossing particles wait in a per-wave ring of kQueue entries in LDS and are
+// deposited 64 at a time through deposit_window, with every lane busy.
+constexpr int kQueue = 128;
+
 constexpr int kBatch = 2;   // particles fetched per lane before processing
 
 template <typename R, typename A, int D, int T>
@@ -212,6 +358,8 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
     constexpr int SJ_Y = NJ, SJ_Z = NJ * NJ;        // LDS strides of the current tile
     __shared__ R sF[6 * NF_D];
     __shared__ A sJ[3 * NJ_D];
+    __shared__ int sQc[kBlock / 64][kQueue];             // crossing-particle ring per wave
+    __shared__ R sQv[kBlock / 64][2 * D + 1][kQueue];
     __shared__ uint32_t s_front;
     __shared__ double sred[kBlock / 64][kTileDiag];
 
@@ -228,6 +376,7 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
     const int src = uniform_par(kp), dst = src ^ 1;
     const bool diag = diag_step(kp, step);
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int tsh = kp->g.tshift[0];
     uint32_t csh[3], cmask[3];
     for (int a = 0; a < 3; ++a) {
@@ -323,6 +472,18 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
             r.id = track ? ld(iid, slot) : 0u;
         };
         double acc[kTileDiag] = {0, 0, 0, 0, 0, 0};
+        uint32_t qhead = 0, qtail = 0;                       // wave-uniform ring indices
+        auto drain = [&](uint32_t e) {
+            const int pk = sQc[wave][e];
+            const int qlc[3] = {pk & 0xff, (pk >> 8) & 0xff, (pk >> 16) & 0xff};
+            R qx0[3] = {R(0), R(0), R(0)}, qx1[3] = {R(0), R(0), R(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                qx0[a] = sQv[wave][a][e];
+                qx1[a] = sQv[wave][D + a][e];
+            }
+            deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, sQv[wave][2 * D][e]);
+        };
         for (uint32_t base = 0; base < total; base += kBatch * kBlock) {
             Raw q[kBatch];
 #pragma unroll
@@ -343,6 +504,9 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
             R ux = R(0), uy = R(0), uz = R(0);
             uint32_t pid = 0;
             for (int a = 0; a < D; ++a) { ic1[a] = 0; off1[a] = R(0); }
+            bool cross = false;                               // leaves its cell this step
+            int q_lc = 0;
+            R q_x0[D], q_x1[D], q_kz = R(0);
             if (active) {
                 int ic[3] = {0, 0, 0};
                 R off[3] = {R(0), R(0), R(0)};
@@ -401,89 +565,29 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
                 const R ig1 = Arith<R>::rsq(R(1) + ux * ux + uy * uy + uz * uz);
                 const R v[3] = {ux * ig1, uy * ig1, uz * ig1};
 
-                // ---- move in cell units, relative to the particle's cell;
-                // form factors on the 3-node window around the nearest node
-                R x1[3], S0[3][3], DS[3][3];
-                int w0 = 0;
+                // ---- move in cell units, relative to the particle's cell
+                R x1[3] = {R(0), R(0), R(0)};
+                int kk[3] = {0, 0, 0};
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     x1[a] = off[a] + v[a] * dtd[a];
-                    const int ca = off[a] >= R(0.5) ? 1 : 0;
-                    const R d0 = off[a] - R(ca), d1 = x1[a] - R(ca);
-                    S0[a][0] = fmax(R(0), -d0);
-                    S0[a][1] = R(1) - fabs(d0);
-                    S0[a][2] = fmax(R(0), d0);
-                    DS[a][0] = fmax(R(0), -d1) - S0[a][0];
-                    DS[a][1] = R(1) - fabs(d1) - S0[a][1];
-                    DS[a][2] = fmax(R(0), d1) - S0[a][2];
-                    w0 += (lc[a] + ca - 1) * (a == 0 ? 1 : a == 1 ? SJ_Y : SJ_Z);
+                    kk[a] = (int)floor(x1[a]);
+                    cross = cross || kk[a] != 0;
                 }
 
-                // ---- Esirkepov deposit
-                // Pxy = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3 (likewise for
-                // the other pairs); W_x = DSx Pyz, W_y = DSy Pxz, W_z = DSz Pxy and
-                // each current is the running sum of -q w (d/dt) W along its axis.
-                if constexpr (D == 2) {
-                    const R kzv = qw * v[2];
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const R ry = S0[1][b] + R(0.5) * DS[1][b];
-                        const R qy = R(0.5) * S0[1][b] + R(1.0 / 3.0) * DS[1][b];
-                        const R j0 = -kd[0] * (DS[0][0] * ry);
-                        const R j1 = j0 - kd[0] * (DS[0][1] * ry);
-                        lds_add(&sJx[w0 + b * SJ_Y], j0);
-                        lds_add(&sJx[w0 + b * SJ_Y + 1], j1);
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            lds_add(&sJz[w0 + b * SJ_Y + a], kzv * (S0[0][a] * ry + DS[0][a] * qy));
-                    }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const R rx = S0[0][a] + R(0.5) * DS[0][a];
-                        const R j0 = -kd[1] * (DS[1][0] * rx);
-                        const R j1 = j0 - kd[1] * (DS[1][1] * rx);
-                        lds_add(&sJy[w0 + a], j0);
-                        lds_add(&sJy[w0 + SJ_Y + a], j1);
-                    }
+                // ---- Esirkepov deposit: particles that stay in their cell now,
+                // the others through the per-wave queue below
+                const R kzv = qw * v[2];
+                if (!cross) {
+                    deposit_cell<R, A, D, NJ>(sJx, sJy, sJz, lc, off, x1, kd, kzv);
                 } else {
-                    // pair factors P_pq[m][l] = S0p S0q + DSp S0q/2 + S0p DSq/2 + DSp DSq/3
-                    auto P = [&](int p, int q, int m, int l) {
-                        return S0[p][m] * (S0[q][l] + R(0.5) * DS[q][l]) +
-                               DS[p][m] * (R(0.5) * S0[q][l] + R(1.0 / 3.0) * DS[q][l]);
-                    };
+                    q_lc = lc[0] | (lc[1] << 8) | (D == 3 ? lc[2] << 16 : 0);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            const R pyz = P(1, 2, b, c);
-                            const R j0 = -kd[0] * (DS[0][0] * pyz);
-                            const R j1 = j0 - kd[0] * (DS[0][1] * pyz);
-                            const int o = w0 + c * SJ_Z + b * SJ_Y;
-                            lds_add(&sJx[o], j0);
-                            lds_add(&sJx[o + 1], j1);
-                        }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const R pxz = P(0, 2, a, c);
-                            const R j0 = -kd[1] * (DS[1][0] * pxz);
-                            const R j1 = j0 - kd[1] * (DS[1][1] * pxz);
-                            const int o = w0 + c * SJ_Z + a;
-                            lds_add(&sJy[o], j0);
-                            lds_add(&sJy[o + SJ_Y], j1);
-                        }
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const R pxy = P(0, 1, a, b);
-                            const R j0 = -kd[2] * (DS[2][0] * pxy);
-                            const R j1 = j0 - kd[2] * (DS[2][1] * pxy);
-                            const int o = w0 + b * SJ_Y + a;
-                            lds_add(&sJz[o], j0);
-                            lds_add(&sJz[o + SJ_Z], j1);
-                        }
+                    for (int a = 0; a < D; ++a) {
+                        q_x0[a] = off[a];
+                        q_x1[a] = x1[a];
+                    }
+                    q_kz = kzv;
                 }
 
                 if (diag) {
@@ -517,10 +621,10 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
                 t1 = 0;
 #pragma unroll
                 for (int a = D - 1; a >= 0; --a) {
-                    int kk = (int)floor(x1[a]);
-                    R o1 = x1[a] - R(kk);
-                    if (o1 >= R(1)) { o1 = R(0); kk += 1; }
-                    int i1 = ic[a] + kk;
+                    int k1 = kk[a];
+                    R o1 = x1[a] - R(k1);
+                    if (o1 >= R(1)) { o1 = R(0); k1 += 1; }
+                    int i1 = ic[a] + k1;
                     i1 += i1 < 0 ? n[a] : 0;
                     i1 -= i1 >= n[a] ? n[a] : 0;
                     if ((unsigned)i1 >= (unsigned)n[a]) { bad = true; i1 = 0; }
@@ -529,6 +633,31 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
                     t1 = t1 * kp->g.nt[a] + (i1 >> tsh);
                 }
                 if (bad) atomicOr(&state->fatal, 2);
+            }
+
+            // ---- crossing particles: append to the wave's ring, drain when a
+            // full wave of entries is waiting
+            {
+                const uint64_t cm = __ballot(cross);
+                if (cm) {
+                    if (cross) {
+                        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                        const uint32_t e = (qtail + r) & (kQueue - 1);
+                        sQc[wave][e] = q_lc;
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            sQv[wave][a][e] = q_x0[a];
+                            sQv[wave][D + a][e] = q_x1[a];
+                        }
+                        sQv[wave][2 * D][e] = q_kz;
+                    }
+                    qtail += (uint32_t)__popcll(cm);
+                    if (qtail - qhead >= 64) {
+                        drain((qhead + lane) & (kQueue - 1));
+                        qhead += 64;
+                    }
+                }
             }
 
             // ---- binning
@@ -600,6 +729,7 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
             }
             }
         }
+        if ((uint32_t)lane < qtail - qhead) drain((qhead + lane) & (kQueue - 1));
         __syncthreads();
         if (threadIdx.x == 0) S.cnt_front[dst * ntiles + tile] = s_front;
         if (diag) {
