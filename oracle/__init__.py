@@ -63,6 +63,9 @@ def lib():
         P = C.POINTER
         dp = P(C.c_double)
         L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_philox2x32_10.argtypes = [P(C.c_uint32), C.c_uint32, P(C.c_uint32)]
+        L.orc_collision_key.argtypes = [C.c_uint64, C.c_uint32]
+        L.orc_collision_key.restype = C.c_uint32
         L.orc_gather.argtypes = [P(_Grid), dp, dp, dp]
         L.orc_boris.argtypes = [dp, dp, dp, C.c_double]
         L.orc_deposit.argtypes = [P(_Grid), dp * 3, C.c_double, dp, dp, C.c_double]
@@ -96,6 +99,18 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     o = (C.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return np.array(list(o), dtype=np.uint32)
+
+
+def philox2x32_10(ctr, key) -> np.ndarray:
+    """Philox2x32-10 block for a 2-word counter and 1-word key."""
+    c = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    o = (C.c_uint32 * 2)()
+    lib().orc_philox2x32_10(c, int(key) & 0xFFFFFFFF, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def collision_key(seed: int, run: int) -> int:
+    return int(lib().orc_collision_key(seed, run))
 
 
 def collision_threshold(nu: float, dt: float) -> int:

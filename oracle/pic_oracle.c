@@ -43,8 +43,8 @@
  * particles carry no z position, and J_z comes from v_z and the 2D Esirkepov
  * weight instead of the z running sum.  Boundaries are periodic.
  *
- * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written
- * from its published definition.
+ * Random numbers: Philox2x32-10 and Philox4x32-10 (Salmon, Moraes, Dror,
+ * Shaw, SC'11), written from their published definition.
  */
 #include <math.h>
 #include <stdint.h>
@@ -104,6 +104,23 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
         philox_round(c, k);
     }
     for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+/* Philox2x32-10 (same paper): a 2x32-bit counter and a 32-bit key; each
+ * round multiplies word 0 by a fixed odd constant, xors the high half with
+ * the key and word 1, and the key advances by a Weyl increment.          */
+void orc_philox2x32_10(const uint32_t ctr[2], uint32_t key, uint32_t out[2])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], k = key;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) k += 0x9E3779B9u;
+        uint64_t p = (uint64_t)0xD256D193u * c0;
+        uint32_t hi = (uint32_t)(p >> 32), lo = (uint32_t)p;
+        c0 = hi ^ k ^ c1;
+        c1 = lo;
+    }
+    out[0] = c0;
+    out[1] = c1;
 }
 
 /* uniform in (0,1) from 32 random bits, exact in FP64 */
@@ -258,12 +275,18 @@ void orc_deposit(const orc_grid *g, double *const Jp[3], double qw,
     }
 }
 
-/* Scattering off the immobile ions.  The draw is keyed by the particle's
- * identity and the step: counter (id, step, 1, run), key (seed lo, seed hi).
- * The event happens when word 0 of the draw is below floor(P 2^32),
- * P = 1 - exp(-nu dt), an integer decision.  The new direction is isotropic,
- * cos(theta) = 1 - 2 U1, phi = 2 pi U2, and |u| is kept.  Returns 1 if the
- * particle scattered.                                                     */
+/* Scattering off the immobile ions.  The decision draw is Philox2x32-10 on
+ * counter (id, step) with key  seed_lo ^ (seed_hi * 0x9E3779B9) ^
+ * (run * 0x85EBCA6B); the event happens when its word 0 is below
+ * floor(P 2^32), P = 1 - exp(-nu dt), an integer decision.  A scattered
+ * particle draws its new direction from Philox4x32-10 on counter
+ * (id, step, 1, run), key (seed lo, seed hi): cos(theta) = 1 - 2 U(word 1),
+ * phi = 2 pi U(word 2); the direction is isotropic and |u| is kept.
+ * Returns 1 if the particle scattered.                                    */
+uint32_t orc_collision_key(uint64_t seed, uint32_t run)
+{
+    return (uint32_t)seed ^ ((uint32_t)(seed >> 32) * 0x9E3779B9u) ^ (run * 0x85EBCA6Bu);
+}
 uint32_t orc_collision_threshold(double nu, double dt)
 {
     double P = 1.0 - exp(-nu * dt);
@@ -275,11 +298,13 @@ uint32_t orc_collision_threshold(double nu, double dt)
 
 int orc_collide(double u[3], uint32_t id, int64_t step, uint64_t seed, uint32_t run, uint32_t thr)
 {
+    uint32_t dctr[2] = {id, (uint32_t)step}, d[2];
+    orc_philox2x32_10(dctr, orc_collision_key(seed, run), d);
+    if (!(d[0] < thr)) return 0;
     uint32_t ctr[4] = {id, (uint32_t)step, 1u, run};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t r[4];
     orc_philox4x32_10(ctr, key, r);
-    if (!(r[0] < thr)) return 0;
     double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     double ct = 1.0 - 2.0 * u01(r[1]);
     double st = sqrt(fmax(0.0, 1.0 - ct * ct));

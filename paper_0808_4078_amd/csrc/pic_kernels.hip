@@ -73,6 +73,20 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// Philox2x32-10 (same paper): the per-step scatter decision needs one word.
+__device__ __forceinline__ uint32_t philox2x32_10_w0(uint32_t c0, uint32_t c1, uint32_t k)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi = __umulhi(0xD256D193u, c0);
+        const uint32_t lo = 0xD256D193u * c0;
+        c0 = hi ^ k ^ c1;
+        c1 = lo;
+        k += 0x9E3779B9u;
+    }
+    return c0;
+}
+
 __device__ __forceinline__ double u01d(uint32_t r) { return ((double)r + 0.5) * 2.3283064365386963e-10; }
 
 // uniform in (0,1) in FP32, exactly representable
@@ -385,6 +399,8 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
     }
     const uint32_t seed0 = (uint32_t)kp->seed, seed1 = (uint32_t)(kp->seed >> 32);
     const uint32_t runid = kp->run;
+    // key of the scatter-decision draw (Philox2x32-10 on (id, step))
+    const uint32_t ckey = seed0 ^ (seed1 * 0x9E3779B9u) ^ (runid * 0x85EBCA6Bu);
     DevState *state = kp->state;
 
     {
@@ -602,8 +618,8 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
 
                 // ---- scattering off the ions (collisional species)
                 if (collide) {
-                    const uint4 r = philox10(make_uint4(pid, (uint32_t)step, kPurposeCollide, runid), seed0, seed1);
-                    if (r.x < thr) {
+                    if (philox2x32_10_w0(pid, (uint32_t)step, ckey) < thr) {
+                        const uint4 r = philox10(make_uint4(pid, (uint32_t)step, kPurposeCollide, runid), seed0, seed1);
                         const R um = sqrt(ux * ux + uy * uy + uz * uz);
                         const R ct = R(1) - R(2) * R(u01d(r.y));
                         const R st = sqrt(fmax(R(0), R(1) - ct * ct));

@@ -40,6 +40,28 @@ def test_philox_known_answers(orc):
         assert [int(o) for o in out] == v[6:10]
 
 
+def test_philox2x32_known_answers(orc):
+    """Philox2x32-10 (the collision decision draw) reproduces the published
+    known-answer vectors."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "philox2x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(h, 16) for h in r]
+        assert [int(o) for o in orc.philox2x32_10(v[0:2], v[2])] == v[3:5]
+
+
+def test_collision_decision_uses_the_2x32_draw(orc):
+    """The scatter decision is word 0 of Philox2x32-10 on (id, step) under the
+    collision key, compared with floor(P 2^32)."""
+    seed, run, thr = 0x08084078, 3, orc.collision_threshold(5.0, 0.1)
+    key = orc.collision_key(seed, run)
+    u = np.array([0.1, 0.2, -0.3])
+    for pid in range(200):
+        want = int(orc.philox2x32_10([pid, 7], key)[0]) < thr
+        assert orc.collide(u, pid, 7, seed, run, thr)[1] == want
+
+
 def test_philox_uniformity(orc):
     """Word 0 over consecutive counters is uniform (chi-square, 64 bins)."""
     n = 20000
