@@ -76,7 +76,9 @@ enum {
  *             PIC_PREC_MIXED: int32 cell index + FP32 in-cell offset, FP32
  *             momenta, FP32 push and per-tile FP32 current, FP64 grid-level
  *             current reduction and diagnostics, FP32 E and B.
- *   seed, run counter-based random stream (Philox4x32-10) key and run index.
+ *   seed, run key of the counter-based random streams (Philox2x32-10 for the
+ *             per-step scattering decision, Philox4x32-10 for the loader and
+ *             the scattering direction) and the run index mixed into it.
  *   tile[3]   particle tile edge in cells, the same on every resolved axis
  *             (0 = library default: 16 or 8 in 2D, 8 in 3D); 2D supports 8, 16
  *             and 32, 3D supports 8; n must be a multiple of the tile.
@@ -223,6 +225,73 @@ const char *pic_status_string(int status);
 /* Copies the last error message of the handle (or of the last failed
  * pic_init / pic_query when run is NULL) into buf. */
 int pic_last_error(pic_run *run, char *buf, size_t n);
+
+/* ---- Ensembles -----------------------------------------------------------
+ * Many independent runs (the paper's parameter scans: beam temperature,
+ * collision rate, box size) stepped together.  A batch step is one kernel
+ * sequence over every member: the particle kernel is persistent -- its
+ * workgroups take (run, tile) work items from a device queue, runs with the
+ * most particles per tile first -- and is launched once per tile edge in use;
+ * the re-layout, current-reduction and Yee kernels each cover every member's
+ * cells in one launch.  Unless PIC_FLAG_NO_GRAPH is given, a step is the
+ * replay of one captured graph.  Each member goes through the same kernels'
+ * arithmetic as when stepped alone (tile by tile, the same workgroup code).
+ *
+ * Members are initialised runs (pic_init) sharing precision, ndim and the
+ * bound stream; in 2D their tile edges may differ.  While a batch holds a
+ * run, pic_step / pic_step_profiled / pic_destroy on it return PIC_E_STATE;
+ * the read-out calls (pic_diagnostics, pic_read_fields, ...) work as usual.
+ * Failures are described by pic_last_error(NULL, ...). */
+typedef struct pic_batch pic_batch;
+
+/* Host only.  Size of the device table of a batch of these runs.  Errors:
+ * INVALID_ARG (nruns < 1, NULL or repeated run), UNSUPPORTED (mixed
+ * precision or ndim). */
+int pic_batch_query(int nruns, pic_run *const *runs, size_t *table_bytes);
+
+/* Builds the batch: writes the work-item and block tables into the caller's
+ * device buffer `table` (>= pic_batch_query's size, kept alive until
+ * pic_batch_destroy) and captures the step graph.  persistent_blocks:
+ * workgroups of each particle launch (0 = as many as fit on the device at
+ * once).  flags: PIC_FLAG_NO_GRAPH or 0.  Synchronising.  Errors as
+ * pic_batch_query, plus BUFFER_TOO_SMALL, STATE (a run already in a batch),
+ * INVALID_ARG (members on different streams). */
+int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_bytes,
+                   int32_t persistent_blocks, uint32_t flags, pic_batch **out);
+
+/* Enqueues nsteps steps of every member on the shared stream (asynchronous). */
+int pic_batch_step(pic_batch *batch, int32_t nsteps);
+
+/* As pic_step_profiled, for the batch: group_ms[6] receives the summed
+ * kernel milliseconds per kernel group over all members.  Synchronising. */
+int pic_batch_step_profiled(pic_batch *batch, int32_t nsteps, double *group_ms);
+
+/* Waits for the stream; returns the first member's failure, if any. */
+int pic_batch_sync(pic_batch *batch);
+
+/* Host only.  For tile edges 8, 16, 32 (index 0..2): the particle kernel's
+ * workgroups and work items (0 where no member uses the edge). */
+int pic_batch_info(pic_batch *batch, int32_t persistent_blocks[3], int32_t items[3]);
+
+/* Waits for the stream, releases the members and frees the host state. */
+int pic_batch_destroy(pic_batch *batch);
+
+/* ---- Tile autotuner --------------------------------------------------------
+ * The tile edge sets the particles per workgroup (ppc * edge^ndim) and the
+ * LDS footprint of the particle kernel.  pic_tune builds, inside the caller's
+ * workspace, a fresh device-loaded run of the described configuration for
+ * every edge in {8, 16, 32} that divides each resolved axis (3D: 8 only),
+ * times `nsteps` graph-replayed steps after 2 warm-up steps, and returns the
+ * fastest edge in *best_tile and each candidate's milliseconds per step in
+ * ms[3] (edge 8, 16, 32; -1 where not tried).  grid->tile and
+ * PIC_FLAG_HOST_LOAD are ignored.  Synchronising, on `hip_stream`; the
+ * workspace may be reused once it returns.  pic_tune_query (host only) gives
+ * the workspace size. */
+int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+                   size_t *workspace_bytes);
+int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+             void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps,
+             int32_t *best_tile, double ms[3]);
 
 #ifdef __cplusplus
 }

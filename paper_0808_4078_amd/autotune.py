@@ -1,0 +1,88 @@
+"""Tile-edge choice for ensembles of runs.
+
+The tile edge fixes the particles one workgroup of the particle kernel owns
+(ppc * edge^ndim) and its LDS footprint; the best edge depends on the grid
+size (work items per run) and the particle load.  The timing itself is the
+library's ``pic_tune`` (fresh device-loaded runs, graph-replayed steps); this
+module groups the members of an ensemble into classes of equal grid and
+similar load, tunes one representative per class, and keeps the answers in a
+JSON cache keyed by the class.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import pic
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_0808_4078_amd", "tiles.json")
+
+
+def load_band(ppc_total: int) -> int:
+    """Particle-load band of a run: total particles per cell over species,
+    rounded to bands of 32."""
+    return max(1, (int(ppc_total) + 31) // 32)
+
+
+def class_key(wl, precision: int) -> str:
+    ppc = sum(s.ppc for s in wl.species)
+    return f"d{wl.ndim}-n{'x'.join(str(v) for v in wl.n[:wl.ndim])}-band{load_band(ppc)}-p{precision}"
+
+
+def _read(path):
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _write(path, data):
+    if not path:
+        return
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def choose_tiles(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cache_path=DEFAULT_CACHE,
+                 log=None):
+    """Tile edge for every workload.  Returns (tiles, report) where report
+    maps each class key to {"tile", "ms", "representative", "members",
+    "cached"}."""
+    cache = _read(cache_path)
+    classes = {}
+    for i, wl in enumerate(workloads):
+        classes.setdefault(class_key(wl, precision), []).append(i)
+    report = {}
+    dirty = False
+    for key, idx in sorted(classes.items()):
+        # representative: the member with the median particle load of the class
+        idx_sorted = sorted(idx, key=lambda i: sum(s.ppc for s in workloads[i].species))
+        rep = idx_sorted[len(idx_sorted) // 2]
+        if key in cache and "tile" in cache[key]:
+            ent = dict(cache[key])
+            ent["cached"] = True
+        else:
+            g, sp = pic.workload_descs(workloads[rep], precision=precision)
+            best, ms = pic.tune(g, sp, nsteps=nsteps)
+            ent = {"tile": best, "ms": {str(k): v for k, v in ms.items()}, "cached": False}
+            cache[key] = {"tile": best, "ms": ent["ms"]}
+            dirty = True
+            if log:
+                log(f"autotune {key}: tile {best} ({', '.join(f'{k}: {v:.3f} ms' for k, v in ms.items())})")
+        ent["representative"] = rep
+        ent["members"] = len(idx)
+        report[key] = ent
+    if dirty:
+        _write(cache_path, cache)
+    tiles = [0] * len(workloads)
+    for key, idx in classes.items():
+        for i in idx:
+            tiles[i] = int(report[key]["tile"])
+    return tiles, report

@@ -106,19 +106,25 @@ struct KParams {
 };
 
 // An ensemble of runs stepped together: every launch of a step covers all
-// runs.  Runs share precision, dimension and tile edge.
+// runs.  Runs share precision and dimension; in 2D each run has its own tile
+// edge, and the particle kernel is launched once per edge (group g: edge
+// 8 << g; 3D runs use group 0).
+struct BatchGroup {
+    int n_items;          // particle-kernel work items of the runs with this edge
+    const int2 *items;    // [n_items] (run, tile), heaviest tiles first
+    int *queue;           // work counter of the persistent particle kernel
+};
+constexpr int kBatchGroups = 3;
 struct BatchTable {
     int nruns;
-    int n_items;          // particle-kernel work items
     int n_cell_blocks;    // 256-cell blocks over all runs
     int nst_blocks;       // max over runs of ceil(nspecies * tiles / 256)
     int max_species;
+    int max_fd_blocks;    // max over runs of KParams::fd_blocks
     const KParams *const *kp;   // [nruns] device parameter blocks
-    const int2 *items;          // [n_items] (run, tile), heaviest tiles first
     const int2 *cell_blocks;    // [n_cell_blocks] (run, block of that run)
-    int *queue;                 // work counter of the persistent particle kernel
+    BatchGroup grp[kBatchGroups];
 };
-constexpr int kBatchFieldDiagBlocks = 32;
 constexpr int kBatchRebinBlocks = 64;
 
 // Host-callable launchers (defined in the .hip translation units).
@@ -129,8 +135,17 @@ constexpr int kStepKernels = 13;
 constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
 // ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
-hipError_t launch_batch_step(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int persistent_blocks,
-                             hipStream_t s, hipEvent_t *ev = nullptr);
+// Batch step: the particle kernel is one launch per tile group (empty groups
+// launch one workgroup that exits), so a batch step has kBatchKernels
+// dispatches; kBatchKernelGroup maps them to the groups above.
+// pblocks[g]: persistent workgroups of group g's particle launch.
+constexpr int kBatchKernels = kStepKernels + kBatchGroups - 1;
+constexpr int kBatchKernelGroup[kBatchKernels] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
+hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, const BatchTable *dt,
+                             const int pblocks[kBatchGroups], hipStream_t s, hipEvent_t *ev = nullptr);
+// Workgroups of the batch particle kernel of tile group g that fit on one
+// compute unit at once.
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, int *blocks_per_cu);
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
 hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);
 hipError_t launch_shift_u(const KParams &hp, const KParams *dp, int s, double dux, double duy,

@@ -23,6 +23,7 @@
 // probability 1 - exp(-nu dt), |u| kept.  Units: t in 1/w_p, x in c/w_p,
 // u = gamma v/c, fields e F/(m c w_p).
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include "pic_internal.hpp"
@@ -1135,10 +1136,14 @@ __global__ __launch_bounds__(256) void k_field_diag(const KParams *__restrict__ 
 {
     field_diag_body<R>(kp, blockIdx.x, gridDim.x);
 }
+// each run writes exactly its own fd_blocks partial records
 template <typename R>
 __global__ __launch_bounds__(256) void kb_field_diag(const BatchTable *__restrict__ bt)
 {
-    field_diag_body<R>(bt->kp[blockIdx.y], blockIdx.x, gridDim.x);
+    const KParams *kp = bt->kp[blockIdx.y];
+    const int nb = kp->fd_blocks;
+    if ((int)blockIdx.x >= nb) return;
+    field_diag_body<R>(kp, blockIdx.x, nb);
 }
 
 template <typename R, typename A, int D, int T>
@@ -1146,17 +1151,23 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
 {
     particle_body<R, A, D, T>(kp, blockIdx.x, gridDim.x);
 }
+// Persistent: each workgroup takes (run, tile) items of its tile group until
+// the group's list is exhausted.  The counter only grows, so every workgroup
+// reaches the exit.
 template <typename R, typename A, int D, int T>
 __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restrict__ bt)
 {
+    constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
     __shared__ int s_item;
+    const BatchGroup &G = bt->grp[g];
+    const int n_items = G.n_items;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(bt->queue, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(G.queue, 1);
         __syncthreads();
         const int i = s_item;
         __syncthreads();
-        if (i >= bt->n_items) break;
-        const int2 it = bt->items[i];
+        if (i >= n_items) break;
+        const int2 it = G.items[i];
         particle_body<R, A, D, T>(bt->kp[it.x], it.y, 0);
     }
 }
@@ -1226,7 +1237,8 @@ template <typename R, int D>
 __global__ __launch_bounds__(256) void kb_yee_b(const BatchTable *__restrict__ bt, double h)
 {
     const int2 cb = bt->cell_blocks[blockIdx.x];
-    yee_b_body<R, D>(bt->kp[cb.x], cb.y, 0, h);
+    const KParams *kp = bt->kp[cb.x];
+    yee_b_body<R, D>(kp, cb.y, 0, (kp->flags & PIC_FLAG_FREEZE_FIELDS) ? 0.0 : h);
 }
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_yee_e(const KParams *__restrict__ kp)
@@ -1244,11 +1256,11 @@ __global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
 {
     advance_body(kp, blockIdx.x, gridDim.x);
 }
-// one workgroup per run; the first also rewinds the particle-kernel queue
+// one workgroup per run; the first also rewinds the particle-kernel queues
 __global__ __launch_bounds__(256) void kb_advance(const BatchTable *__restrict__ bt)
 {
     advance_body(bt->kp[blockIdx.x], 0, 1);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *bt->queue = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kBatchGroups) *bt->grp[threadIdx.x].queue = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1440,15 +1452,36 @@ hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t st, hip
     return hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, dp, st, ev) : step_prec<double>(hp, dp, st, ev);
 }
 
-// The same kernel sequence over a whole ensemble (kStepKernels launches).
+// The same kernel sequence over a whole ensemble (kBatchKernels launches):
+// field diag | particle, one per tile group | 6 x re-layout | J reduction |
+// 3 x Yee | advance.
 template <typename R, typename A, int D, int T>
-static hipError_t batch_kernels(const BatchTable &ht, const BatchTable *dt, int pblocks, hipStream_t st,
+static void batch_particle(Launcher &L, const BatchTable &ht, const BatchTable *dt, int pblocks)
+{
+    constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
+    const unsigned nb = ht.grp[g].n_items > 0 ? (unsigned)std::max(1, pblocks) : 1u;
+    L(kb_particle<R, A, D, T>, dim3(nb), dim3(kBlock), dt);
+}
+
+template <typename R, int D>
+static hipError_t batch_kernels(const BatchTable &ht, const BatchTable *dt, const int *pb, hipStream_t st,
                                 hipEvent_t *ev)
 {
+    using A = double;
     const unsigned nr = (unsigned)ht.nruns;
     Launcher L{st, ev};
-    L(kb_field_diag<R>, dim3(kBatchFieldDiagBlocks, nr), dim3(256), dt);
-    L(kb_particle<R, A, D, T>, dim3(pblocks), dim3(kBlock), dt);
+    L(kb_field_diag<R>, dim3(ht.max_fd_blocks, nr), dim3(256), dt);
+    if constexpr (D == 3) {
+        batch_particle<R, A, 3, 8>(L, ht, dt, pb[0]);
+        // fixed dispatch count: two one-workgroup launches that find the
+        // queue of group 0 exhausted and exit (3D has one tile edge)
+        batch_particle<R, A, 3, 8>(L, ht, dt, 0);
+        batch_particle<R, A, 3, 8>(L, ht, dt, 0);
+    } else {
+        batch_particle<R, A, 2, 8>(L, ht, dt, pb[0]);
+        batch_particle<R, A, 2, 16>(L, ht, dt, pb[1]);
+        batch_particle<R, A, 2, 32>(L, ht, dt, pb[2]);
+    }
     L(kb_rebin_count, dim3(ht.nst_blocks, nr), dim3(256), dt);
     L(kb_rebin_count_ovf<R>, dim3(kBatchRebinBlocks, nr), dim3(256), dt);
     L(kb_rebin_scan, dim3(ht.max_species, nr), dim3(256), dt);
@@ -1463,28 +1496,34 @@ static hipError_t batch_kernels(const BatchTable &ht, const BatchTable *dt, int 
     return hipGetLastError();
 }
 
-template <typename R>
-static hipError_t batch_prec(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int pb, hipStream_t st,
-                             hipEvent_t *ev)
+hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, const BatchTable *dt,
+                             const int pblocks[kBatchGroups], hipStream_t st, hipEvent_t *ev)
 {
-    using A = double;
-    if (hp0.g.ndim == 3) {
-        if (hp0.g.tile[0] == 8) return batch_kernels<R, A, 3, 8>(ht, dt, pb, st, ev);
-        return hipErrorInvalidValue;
+    if (ndim == 3) {
+        if (ht.grp[1].n_items || ht.grp[2].n_items) return hipErrorInvalidValue;
+        return precision == PIC_PREC_MIXED ? batch_kernels<float, 3>(ht, dt, pblocks, st, ev)
+                                           : batch_kernels<double, 3>(ht, dt, pblocks, st, ev);
     }
-    switch (hp0.g.tile[0]) {
-    case 8: return batch_kernels<R, A, 2, 8>(ht, dt, pb, st, ev);
-    case 16: return batch_kernels<R, A, 2, 16>(ht, dt, pb, st, ev);
-    case 32: return batch_kernels<R, A, 2, 32>(ht, dt, pb, st, ev);
-    default: return hipErrorInvalidValue;
-    }
+    return precision == PIC_PREC_MIXED ? batch_kernels<float, 2>(ht, dt, pblocks, st, ev)
+                                       : batch_kernels<double, 2>(ht, dt, pblocks, st, ev);
 }
 
-hipError_t launch_batch_step(const KParams &hp0, const BatchTable &ht, const BatchTable *dt, int pblocks,
-                             hipStream_t st, hipEvent_t *ev)
+template <typename R, int D, int T>
+static hipError_t occupancy(int *n)
 {
-    return hp0.precision == PIC_PREC_MIXED ? batch_prec<float>(hp0, ht, dt, pblocks, st, ev)
-                                           : batch_prec<double>(hp0, ht, dt, pblocks, st, ev);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T>, kBlock, 0);
+}
+
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, int *n)
+{
+    const bool mx = precision == PIC_PREC_MIXED;
+    if (ndim == 3) return mx ? occupancy<float, 3, 8>(n) : occupancy<double, 3, 8>(n);
+    switch (g) {
+    case 0: return mx ? occupancy<float, 2, 8>(n) : occupancy<double, 2, 8>(n);
+    case 1: return mx ? occupancy<float, 2, 16>(n) : occupancy<double, 2, 16>(n);
+    case 2: return mx ? occupancy<float, 2, 32>(n) : occupancy<double, 2, 32>(n);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st)

@@ -207,6 +207,19 @@ struct pic_run {
     int64_t steps_enqueued = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    pic_batch *owner = nullptr;  // batch this run is a member of
+    std::string err;
+};
+
+struct pic_batch {
+    std::vector<pic_run *> runs;
+    int precision = 0, ndim = 0;
+    hipStream_t stream = nullptr;
+    BatchTable ht;              // host copy (device pointers inside)
+    BatchTable *dt = nullptr;   // device copy (inside the caller's table buffer)
+    int pblocks[kBatchGroups] = {0, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     std::string err;
 };
 
@@ -358,6 +371,141 @@ int capture_graph(pic_run *r)
     return PIC_OK;
 }
 
+// Device table of a batch: BatchTable | kp[nruns] | cell blocks | work items
+// of each tile group | one queue counter per group.
+struct BatchLayout {
+    size_t table, kp, cell_blocks, items[kBatchGroups], queues, bytes;
+    int n_cell_blocks, n_items[kBatchGroups];
+};
+
+int tile_group(const pic_run *r)
+{
+    return r->L.g.tile[0] == 8 ? 0 : (r->L.g.tile[0] == 16 ? 1 : 2);
+}
+
+int batch_layout(int nruns, pic_run *const *runs, BatchLayout *B, std::string *err)
+{
+    if (nruns < 1 || !runs) return fail(err, PIC_E_INVALID_ARG, "batch needs at least one run");
+    memset(B, 0, sizeof(*B));
+    int64_t ncb = 0, nit[kBatchGroups] = {0, 0, 0};
+    for (int i = 0; i < nruns; ++i) {
+        const pic_run *r = runs[i];
+        if (!r) return fail(err, PIC_E_INVALID_ARG, "run %d is NULL", i);
+        if (r->grid.precision != runs[0]->grid.precision || r->grid.ndim != runs[0]->grid.ndim)
+            return fail(err, PIC_E_UNSUPPORTED, "run %d: members must share precision and ndim", i);
+        for (int j = 0; j < i; ++j)
+            if (runs[j] == r) return fail(err, PIC_E_INVALID_ARG, "run %d listed twice", i);
+        ncb += (r->L.g.cells + 255) / 256;
+        nit[tile_group(r)] += r->L.g.ntiles;
+    }
+    if (ncb > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
+    B->n_cell_blocks = (int)ncb;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (nit[g] > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
+        B->n_items[g] = (int)nit[g];
+    }
+    Carver c;
+    B->table = c.take(sizeof(BatchTable));
+    B->kp = c.take((size_t)nruns * sizeof(void *));
+    B->cell_blocks = c.take((size_t)B->n_cell_blocks * sizeof(int2));
+    for (int g = 0; g < kBatchGroups; ++g) B->items[g] = c.take((size_t)B->n_items[g] * sizeof(int2));
+    B->queues = c.take(kBatchGroups * sizeof(int));
+    B->bytes = c.off;
+    return PIC_OK;
+}
+
+// Run-level or batch-level profiled steps: `launch(ev)` enqueues one step
+// whose nk dispatches record start/stop into ev[2k], ev[2k+1].
+template <typename F>
+int profiled_steps(std::string *err, hipStream_t st, int32_t nsteps, int nk, const int *kgroup, double *group_ms,
+                   F launch)
+{
+    for (int g = 0; g < kNumGroups; ++g) group_ms[g] = 0.0;
+    if (nsteps == 0) return PIC_OK;
+    const int ne = 2 * nk;
+    std::vector<hipEvent_t> ev((size_t)nsteps * ne, nullptr);
+    int rc = PIC_OK;
+    auto hfail = [&](hipError_t e, const char *what) {
+        return fail(err, PIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    for (auto &e : ev) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) { rc = hfail(he, "hipEventCreate"); break; }
+    }
+    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i) {
+        hipError_t he = launch(&ev[(size_t)i * ne]);
+        if (he != hipSuccess) rc = hfail(he, "step launch");
+    }
+    if (rc == PIC_OK) {
+        hipError_t he = hipStreamSynchronize(st);
+        if (he != hipSuccess) rc = hfail(he, "hipStreamSynchronize");
+    }
+    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i)
+        for (int k = 0; k < nk; ++k) {
+            float ms = 0.f;
+            hipError_t he = hipEventElapsedTime(&ms, ev[(size_t)i * ne + 2 * k], ev[(size_t)i * ne + 2 * k + 1]);
+            if (he != hipSuccess) { rc = hfail(he, "hipEventElapsedTime"); break; }
+            group_ms[kgroup[k]] += ms;
+        }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// One step of a batch captured as a graph (kept unset if capture fails:
+// steps are then launched one kernel at a time).
+void capture_batch_graph(pic_batch *b)
+{
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipError_t le = launch_batch_step(b->precision, b->ndim, b->ht, b->dt, b->pblocks, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) b->graph = g;
+            else (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        (void)hipGetLastError();
+    }
+}
+
+int batch_hip_fail(pic_batch *b, hipError_t e, const char *what)
+{
+    return fail(&b->err, PIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define BHIPCHK(b, expr)                                          \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return batch_hip_fail(b, e_, #expr); \
+    } while (0)
+
+// Tile autotuner: where each candidate run sits inside the workspace.
+struct TuneCarve {
+    pic_sizes sz;
+    size_t part[kMaxSpecies], fields, scratch, diag, bytes;
+};
+
+bool tile_fits(const pic_grid_desc *g, int t)
+{
+    if (g->ndim == 3 && t != 8) return false;
+    for (int a = 0; a < g->ndim; ++a)
+        if (g->n[a] % t) return false;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -479,7 +627,7 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     K.rb_cap = (int32_t *)at(buffers->scratch, L.rb[2]);
     K.rb_fill = (int32_t *)at(buffers->scratch, L.rb[3]);
     r->dp = (KParams *)at(buffers->scratch, L.kparams);
-    K.fd_blocks = kFieldDiagBlocks;
+    K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
 
 #define INIT_CHK(expr)                                          \
     do {                                                        \
@@ -629,6 +777,7 @@ int pic_step(pic_run *r, int32_t nsteps)
 {
     if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
     if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
+    if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; step the batch");
     for (int32_t i = 0; i < nsteps; ++i) {
         if (r->gexec) {
             HIPCHK(r, hipGraphLaunch(r->gexec, r->stream));
@@ -644,34 +793,12 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
 {
     if (!r || !group_ms) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
     if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
-    for (int g = 0; g < kNumGroups; ++g) group_ms[g] = 0.0;
-    if (nsteps == 0) return PIC_OK;
-    const int ne = 2 * kStepKernels;
-    std::vector<hipEvent_t> ev((size_t)nsteps * ne, nullptr);
-    int rc = PIC_OK;
-    for (auto &e : ev) {
-        hipError_t he = hipEventCreate(&e);
-        if (he != hipSuccess) { rc = hip_fail(r, he, "hipEventCreate"); break; }
-    }
-    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i) {
-        hipError_t he = launch_step(r->hp, r->dp, r->stream, &ev[(size_t)i * ne]);
-        if (he != hipSuccess) rc = hip_fail(r, he, "launch_step");
-        else r->steps_enqueued += 1;
-    }
-    if (rc == PIC_OK) {
-        hipError_t he = hipStreamSynchronize(r->stream);
-        if (he != hipSuccess) rc = hip_fail(r, he, "hipStreamSynchronize");
-    }
-    for (int32_t i = 0; rc == PIC_OK && i < nsteps; ++i)
-        for (int k = 0; k < kStepKernels; ++k) {
-            float ms = 0.f;
-            hipError_t he = hipEventElapsedTime(&ms, ev[(size_t)i * ne + 2 * k], ev[(size_t)i * ne + 2 * k + 1]);
-            if (he != hipSuccess) { rc = hip_fail(r, he, "hipEventElapsedTime"); break; }
-            group_ms[kKernelGroup[k]] += ms;
-        }
-    for (auto &e : ev)
-        if (e) (void)hipEventDestroy(e);
-    return rc;
+    if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; step the batch");
+    return profiled_steps(&r->err, r->stream, nsteps, kStepKernels, kKernelGroup, group_ms, [&](hipEvent_t *ev) {
+        hipError_t e = launch_step(r->hp, r->dp, r->stream, ev);
+        if (e == hipSuccess) r->steps_enqueued += 1;
+        return e;
+    });
 }
 
 int pic_sync(pic_run *r)
@@ -821,10 +948,291 @@ int pic_read_particles(pic_run *r, int s, double *x, double *u, uint32_t *id, in
 int pic_destroy(pic_run *r)
 {
     if (!r) return PIC_OK;
+    if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; destroy the batch first");
     if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
     if (r->graph) (void)hipGraphDestroy(r->graph);
     delete r;
     return PIC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Ensembles
+
+int pic_batch_query(int nruns, pic_run *const *runs, size_t *table_bytes)
+{
+    if (!table_bytes) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
+    BatchLayout B;
+    int rc = batch_layout(nruns, runs, &B, nullptr);
+    if (rc) return rc;
+    *table_bytes = B.bytes;
+    return PIC_OK;
+}
+
+int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_bytes, int32_t persistent_blocks,
+                   uint32_t flags, pic_batch **out)
+{
+    if (!out || !table) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (persistent_blocks < 0) return fail(nullptr, PIC_E_INVALID_ARG, "persistent_blocks < 0");
+    BatchLayout B;
+    int rc = batch_layout(nruns, runs, &B, nullptr);
+    if (rc) return rc;
+    if (table_bytes < B.bytes)
+        return fail(nullptr, PIC_E_BUFFER_TOO_SMALL, "table buffer %zu bytes, need %zu", table_bytes, B.bytes);
+    for (int i = 0; i < nruns; ++i) {
+        if (runs[i]->owner) return fail(nullptr, PIC_E_STATE, "run %d already belongs to a batch", i);
+        if (runs[i]->stream != runs[0]->stream)
+            return fail(nullptr, PIC_E_INVALID_ARG, "run %d: members must be bound to the same stream", i);
+    }
+    pic_batch *b = new (std::nothrow) pic_batch();
+    if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "host allocation failed");
+    b->runs.assign(runs, runs + nruns);
+    b->precision = runs[0]->grid.precision;
+    b->ndim = runs[0]->grid.ndim;
+    b->stream = runs[0]->stream;
+
+    // host images of the table sections
+    std::vector<const KParams *> kps(nruns);
+    std::vector<int2> cells;
+    cells.reserve(B.n_cell_blocks);
+    int max_species = 0, nst = 0, max_fd = 0;
+    for (int i = 0; i < nruns; ++i) {
+        const pic_run *r = runs[i];
+        kps[i] = r->dp;
+        const int cb = (int)((r->L.g.cells + 255) / 256);
+        for (int k = 0; k < cb; ++k) cells.push_back(make_int2(i, k));
+        max_species = std::max(max_species, r->ns);
+        nst = std::max(nst, (int)((r->ns * (int64_t)r->L.g.ntiles + 255) / 256));
+        max_fd = std::max(max_fd, r->hp.fd_blocks);
+    }
+    // work items: runs in order of decreasing particles per tile (the longest
+    // items are handed out first), all tiles of a run together
+    std::vector<int64_t> load(nruns, 0);
+    for (int i = 0; i < nruns; ++i)
+        for (int sp = 0; sp < runs[i]->ns; ++sp) load[i] += runs[i]->L.sp[sp].tile_nominal;
+    std::vector<int> order(nruns);
+    for (int i = 0; i < nruns; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return load[a] > load[c]; });
+    std::vector<int2> items[kBatchGroups];
+    for (int i : order) {
+        const pic_run *r = runs[i];
+        for (int t = 0; t < r->L.g.ntiles; ++t) items[tile_group(r)].push_back(make_int2(i, t));
+    }
+    char *base = (char *)table;
+    BatchTable &H = b->ht;
+    memset(&H, 0, sizeof(H));
+    H.nruns = nruns;
+    H.n_cell_blocks = B.n_cell_blocks;
+    H.nst_blocks = std::max(1, nst);
+    H.max_species = max_species;
+    H.max_fd_blocks = max_fd;
+    H.kp = (const KParams *const *)(base + B.kp);
+    H.cell_blocks = (const int2 *)(base + B.cell_blocks);
+    for (int g = 0; g < kBatchGroups; ++g) {
+        H.grp[g].n_items = (int)items[g].size();
+        H.grp[g].items = (const int2 *)(base + B.items[g]);
+        H.grp[g].queue = (int *)(base + B.queues) + g;
+    }
+    b->dt = (BatchTable *)(base + B.table);
+    // persistent workgroups: as many as fit on the device at once
+    int devi = 0, cus = 0;
+    hipError_t he = hipGetDevice(&devi);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, devi);
+    for (int g = 0; he == hipSuccess && g < kBatchGroups; ++g) {
+        if (persistent_blocks > 0) {
+            b->pblocks[g] = persistent_blocks;
+            continue;
+        }
+        int per_cu = 0;
+        he = batch_particle_occupancy(b->precision, b->ndim, g, &per_cu);
+        b->pblocks[g] = std::max(1, per_cu) * std::max(1, cus);
+    }
+    const int zeros[kBatchGroups] = {0, 0, 0};
+#define BINIT_CHK(expr)                                  \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            int c_ = batch_hip_fail(b, e_, #expr);       \
+            delete b;                                    \
+            return c_;                                   \
+        }                                                \
+    } while (0)
+    BINIT_CHK(he);
+    BINIT_CHK(hipMemcpyAsync(base + B.table, &H, sizeof(H), hipMemcpyHostToDevice, b->stream));
+    BINIT_CHK(hipMemcpyAsync(base + B.kp, kps.data(), kps.size() * sizeof(void *), hipMemcpyHostToDevice,
+                             b->stream));
+    BINIT_CHK(hipMemcpyAsync(base + B.cell_blocks, cells.data(), cells.size() * sizeof(int2), hipMemcpyHostToDevice,
+                             b->stream));
+    for (int g = 0; g < kBatchGroups; ++g)
+        if (!items[g].empty())
+            BINIT_CHK(hipMemcpyAsync(base + B.items[g], items[g].data(), items[g].size() * sizeof(int2),
+                                     hipMemcpyHostToDevice, b->stream));
+    BINIT_CHK(hipMemcpyAsync(base + B.queues, zeros, sizeof(zeros), hipMemcpyHostToDevice, b->stream));
+    BINIT_CHK(hipStreamSynchronize(b->stream));
+#undef BINIT_CHK
+    for (pic_run *r : b->runs) r->owner = b;
+    if (!(flags & PIC_FLAG_NO_GRAPH)) capture_batch_graph(b);
+    *out = b;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch *b, int32_t nsteps)
+{
+    if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    if (nsteps < 0) return fail(&b->err, PIC_E_INVALID_ARG, "nsteps < 0");
+    for (int32_t i = 0; i < nsteps; ++i) {
+        if (b->gexec) {
+            BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+        } else {
+            BHIPCHK(b, launch_batch_step(b->precision, b->ndim, b->ht, b->dt, b->pblocks, b->stream));
+        }
+        for (pic_run *r : b->runs) r->steps_enqueued += 1;
+    }
+    return PIC_OK;
+}
+
+int pic_batch_step_profiled(pic_batch *b, int32_t nsteps, double *group_ms)
+{
+    if (!b || !group_ms) return fail(b ? &b->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    if (nsteps < 0) return fail(&b->err, PIC_E_INVALID_ARG, "nsteps < 0");
+    return profiled_steps(&b->err, b->stream, nsteps, kBatchKernels, kBatchKernelGroup, group_ms,
+                          [&](hipEvent_t *ev) {
+                              hipError_t e = launch_batch_step(b->precision, b->ndim, b->ht, b->dt, b->pblocks,
+                                                               b->stream, ev);
+                              if (e == hipSuccess)
+                                  for (pic_run *r : b->runs) r->steps_enqueued += 1;
+                              return e;
+                          });
+}
+
+int pic_batch_sync(pic_batch *b)
+{
+    if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+        pic_run *r = b->runs[i];
+        DevState st;
+        int rc = read_state(r, &st);
+        if (!rc) rc = check_fatal(r, st);
+        if (rc) return fail(&b->err, rc, "member %zu: %s", i, r->err.c_str());
+    }
+    return PIC_OK;
+}
+
+int pic_batch_info(pic_batch *b, int32_t *persistent_blocks, int32_t *items)
+{
+    if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (persistent_blocks) persistent_blocks[g] = b->ht.grp[g].n_items ? b->pblocks[g] : 0;
+        if (items) items[g] = b->ht.grp[g].n_items;
+    }
+    return PIC_OK;
+}
+
+int pic_batch_destroy(pic_batch *b)
+{
+    if (!b) return PIC_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (pic_run *r : b->runs) r->owner = nullptr;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner
+
+static int tune_carve(const pic_grid_desc *grid, const pic_species_desc *sp, int ns, int tile, TuneCarve *T)
+{
+    pic_grid_desc g = *grid;
+    for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? tile : 0;
+    int rc = pic_query(&g, sp, ns, &T->sz);
+    if (rc) return rc;
+    Carver c;
+    for (int s = 0; s < ns; ++s) T->part[s] = c.take(T->sz.particle_bytes[s]);
+    T->fields = c.take(T->sz.field_bytes);
+    T->scratch = c.take(T->sz.scratch_bytes);
+    T->diag = c.take(T->sz.diag_bytes);
+    T->bytes = c.off;
+    return PIC_OK;
+}
+
+int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+                   size_t *workspace_bytes)
+{
+    if (!grid || !species || !workspace_bytes) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
+    size_t need = 0;
+    int tried = 0;
+    for (int t = 8; t <= 32; t *= 2) {
+        if (!tile_fits(grid, t)) continue;
+        TuneCarve T;
+        int rc = tune_carve(grid, species, nspecies, t, &T);
+        if (rc) return rc;
+        need = std::max(need, T.bytes);
+        ++tried;
+    }
+    if (!tried) return fail(nullptr, PIC_E_INVALID_ARG, "no tile edge in {8,16,32} divides the grid");
+    *workspace_bytes = need;
+    return PIC_OK;
+}
+
+int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, void *workspace,
+             size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_tile, double *ms)
+{
+    if (!grid || !species || !workspace || !best_tile || !ms || nsteps < 1)
+        return fail(nullptr, PIC_E_INVALID_ARG, "bad argument");
+    size_t need = 0;
+    int rc = pic_tune_query(grid, species, nspecies, &need);
+    if (rc) return rc;
+    if (workspace_bytes < need)
+        return fail(nullptr, PIC_E_BUFFER_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    hipStream_t st = (hipStream_t)hip_stream;
+    *best_tile = 0;
+    double best = 0.0;
+    for (int k = 0, t = 8; t <= 32; ++k, t *= 2) {
+        ms[k] = -1.0;
+        if (!tile_fits(grid, t)) continue;
+        TuneCarve T;
+        rc = tune_carve(grid, species, nspecies, t, &T);
+        if (rc) return rc;
+        pic_grid_desc g = *grid;
+        for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? t : 0;
+        g.flags &= ~(uint32_t)PIC_FLAG_HOST_LOAD;
+        pic_buffers buf;
+        memset(&buf, 0, sizeof(buf));
+        for (int s = 0; s < nspecies; ++s) buf.particles[s] = (char *)workspace + T.part[s];
+        buf.fields = (char *)workspace + T.fields;
+        buf.scratch = (char *)workspace + T.scratch;
+        buf.diag = (char *)workspace + T.diag;
+        pic_run *r = nullptr;
+        rc = pic_init(&g, species, nspecies, &buf, hip_stream, &r);
+        if (rc) return rc;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float el = 0.f;
+        hipError_t he = hipEventCreate(&e0);
+        if (he == hipSuccess) he = hipEventCreate(&e1);
+        if (he == hipSuccess) rc = pic_step(r, 2);
+        if (he == hipSuccess && !rc) he = hipEventRecord(e0, st);
+        if (he == hipSuccess && !rc) rc = pic_step(r, nsteps);
+        if (he == hipSuccess && !rc) he = hipEventRecord(e1, st);
+        if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
+        if (he == hipSuccess && !rc) he = hipEventElapsedTime(&el, e0, e1);
+        if (he == hipSuccess && !rc) rc = pic_sync(r);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(st);
+        pic_destroy(r);
+        if (he != hipSuccess) return fail(nullptr, PIC_E_HIP, "tuner timing: %s", hipGetErrorString(he));
+        if (rc) return rc;
+        ms[k] = (double)el / nsteps;
+        if (*best_tile == 0 || ms[k] < best) {
+            best = ms[k];
+            *best_tile = t;
+        }
+    }
+    return PIC_OK;
+}
+
 }  // extern "C"
+

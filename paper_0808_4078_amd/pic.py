@@ -75,7 +75,9 @@ _lib = None
 
 EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_profiled", "pic_sync", "pic_diagnostics",
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
-           "pic_status_string", "pic_last_error"]
+           "pic_status_string", "pic_last_error", "pic_batch_query", "pic_batch_init", "pic_batch_step",
+           "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_destroy", "pic_tune_query",
+           "pic_tune"]
 
 
 def lib():
@@ -110,6 +112,16 @@ def lib():
         L.pic_status_string.argtypes = [C.c_int]
         L.pic_status_string.restype = C.c_char_p
         L.pic_last_error.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.pic_batch_query.argtypes = [C.c_int, P(vp), P(C.c_size_t)]
+        L.pic_batch_init.argtypes = [C.c_int, P(vp), vp, C.c_size_t, C.c_int32, C.c_uint32, P(vp)]
+        L.pic_batch_step.argtypes = [vp, C.c_int32]
+        L.pic_batch_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
+        L.pic_batch_sync.argtypes = [vp]
+        L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.pic_batch_destroy.argtypes = [vp]
+        L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(C.c_size_t)]
+        L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, vp, C.c_size_t, vp, C.c_int32,
+                               P(C.c_int32), P(C.c_double)]
         _lib = L
     return _lib
 
@@ -217,7 +229,7 @@ class Run:
     # ------------------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
-            lib().pic_destroy(self.h)
+            _check(lib().pic_destroy(self.h), "pic_destroy", self.h)
             self.h = None
 
     def __del__(self):
@@ -307,3 +319,76 @@ class Run:
         _check(lib().pic_read_particles(self.h, s, _ptr(x), _ptr(u), _ptr(ids), max(n, 1), C.byref(cnt)),
                "pic_read_particles", self.h)
         return x[:, :n], u[:, :n], ids[:n]
+
+
+class Batch:
+    """Runs stepped together (pic_batch_*).  The runs must have been created
+    on one stream; the batch keeps them alive and releases them on close()."""
+
+    GROUPS = Run.GROUPS
+
+    def __init__(self, runs, persistent_blocks: int = 0, graph: bool = True):
+        import torch
+        self.runs = list(runs)
+        n = len(self.runs)
+        arr = (C.c_void_p * n)(*[r.h for r in self.runs])
+        self._arr = arr
+        nbytes = C.c_size_t()
+        _check(lib().pic_batch_query(n, arr, C.byref(nbytes)), "pic_batch_query")
+        self._table = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.runs[0].device)
+        h = C.c_void_p()
+        _check(lib().pic_batch_init(n, arr, C.c_void_p(self._table.data_ptr()), int(self._table.numel()),
+                                    int(persistent_blocks), 0 if graph else PIC_FLAG_NO_GRAPH, C.byref(h)),
+               "pic_batch_init")
+        self.h = h
+        self.stream = self.runs[0].stream
+
+    def step(self, n: int = 1):
+        _check(lib().pic_batch_step(self.h, int(n)), "pic_batch_step")
+
+    def step_profiled(self, n: int) -> dict:
+        ms = (C.c_double * 6)()
+        _check(lib().pic_batch_step_profiled(self.h, int(n), ms), "pic_batch_step_profiled")
+        return dict(zip(self.GROUPS, list(ms)))
+
+    def sync(self):
+        _check(lib().pic_batch_sync(self.h), "pic_batch_sync")
+
+    def info(self) -> dict:
+        pb = (C.c_int32 * 3)()
+        it = (C.c_int32 * 3)()
+        _check(lib().pic_batch_info(self.h, pb, it), "pic_batch_info")
+        return {"persistent_blocks": list(pb), "items": list(it)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().pic_batch_destroy(self.h), "pic_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def tune(grid: GridDesc, species, nsteps: int = 10, stream=None):
+    """pic_tune: (best tile edge, {edge: ms per step}) for this configuration,
+    timed on the current device inside a temporary torch workspace."""
+    import torch
+    nbytes = C.c_size_t()
+    _check(lib().pic_tune_query(C.byref(grid), species, len(species), C.byref(nbytes)), "pic_tune_query")
+    ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    best = C.c_int32()
+    ms = (C.c_double * 3)()
+    _check(lib().pic_tune(C.byref(grid), species, len(species), C.c_void_p(ws.data_ptr()), int(ws.numel()),
+                          C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
+    del ws
+    return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}
