@@ -112,6 +112,60 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
                 diag=diag, device_bytes=device_bytes)
 
 
+def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
+    """The ensemble: 256 independent 2D3V runs of uneven size and load, tile
+    edges from the autotuner, stepped as one batch (one graph per step)."""
+    import torch
+    import synth
+    from paper_0808_4078_amd import autotune, pic
+
+    members = synth.c5_members()
+    t0 = time.time()
+    tiles, report = autotune.choose_tiles(members, precision=pic.PIC_PREC_MIXED, nsteps=5, log=progress)
+    tune_s = time.time() - t0
+    t0 = time.time()
+    runs = []
+    for i, (wl, t) in enumerate(zip(members, tiles)):
+        g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=t, diag_every=diag_every)
+        runs.append(pic.Run(g, sp))
+    batch = pic.Batch(runs)
+    init_s = time.time() - t0
+    n = int(sum(wl.particles for wl in members))
+    progress(f"C5: {len(runs)} runs, {n} particles, tiles {dict((e, tiles.count(e)) for e in (8, 16, 32))}, "
+             f"tuned in {tune_s:.1f} s, initialised in {init_s:.1f} s")
+    batch.step(warmup)
+    batch.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    batch.step(steps)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    groups = batch.step_profiled(prof_steps)
+    batch.sync()
+    info = batch.info()
+    rebins = sum(r.diagnostics()["rebins"] for r in runs) if diag_every else None
+    batch.close()
+    for r in runs:
+        r.close()
+    del runs, batch
+    torch.cuda.empty_cache()
+    progress(f"C5: {steps} batch steps {ms / steps:.3f} ms/step, {n * steps / (ms * 1e-3):.3e} particle-steps/s")
+    return {"workload": "C5: 256 independent 2D3V runs, side in {64,128,256,512}, beam u_th ~ U[0.05,0.5], "
+                        "nu ~ U[0,0.1], ppc ~ U{16..64} per species, mixed precision, one batch (persistent "
+                        "particle kernel over a (run, tile) queue, one graph replay per step)",
+            "runs": len(members), "particles": n, "steps": steps,
+            "value": n * steps / (ms * 1e-3), "unit": "particle-steps/s", "ms_per_step": ms / steps,
+            "tiles": {str(e): tiles.count(e) for e in (8, 16, 32)},
+            "autotune": {k: {"tile": v["tile"], "ms": v.get("ms"), "members": v["members"]}
+                         for k, v in report.items()},
+            "persistent_blocks": info["persistent_blocks"], "work_items": info["items"],
+            "step_breakdown_ms": {k: v / prof_steps for k, v in groups.items()},
+            "relayouts_total": rebins, "tune_s": tune_s, "init_s": init_s}
+
+
 def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
     """The FP64 oracle on a bounded sample of the workload: a 256 x 256 box
     with the same per-cell load and physics, timed for whole steps until
@@ -148,8 +202,10 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="256^2 grid instead of 1024^2 (for profiling)")
-    ap.add_argument("--c4", type=int, default=0, metavar="K",
-                    help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed)")
+    ap.add_argument("--c4", type=int, default=500, metavar="K",
+                    help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed; 0 = skip)")
+    ap.add_argument("--c5", type=int, default=300, metavar="K",
+                    help="also time K batch steps of the 256-run 2D ensemble (mixed, autotuned tiles; 0 = skip)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} refused: this PIC build runs on a single GPU "
@@ -221,6 +277,8 @@ def main():
                      "ms_per_step": c4["profiled_ms"] / a.c4, "particle_kernel_ms": c4_pk,
                      "particle_kernel_GBs": c4_bytes / (c4_pk * 1e-3) / 1e9,
                      "step_breakdown_ms": {k: v / a.c4 for k, v in c4["groups_ms"].items()}}
+    if a.c5 > 0:
+        rec["c5"] = run_c5(a.c5, min(a.warmup, 5), a.diag_every)
     if not a.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -83,7 +83,13 @@ enum {
  *             (0 = library default: 16 or 8 in 2D, 8 in 3D); 2D supports 8, 16
  *             and 32, 3D supports 8; n must be a multiple of the tile.
  *   diag_every record diagnostics every diag_every steps (0 = never).
- *   flags     PIC_FLAG_* bits. */
+ *   flags     PIC_FLAG_* bits.
+ *   reserve   spare particle-store capacity per tile, as a fraction of the
+ *             tile's nominal particle count (0 = library default 1.0).  A
+ *             tile whose population outgrows its spare capacity triggers a
+ *             re-layout of the store at the end of the step; spare slots are
+ *             never read, so a larger reserve costs device memory only.
+ *             Must be in [0, 8]. */
 typedef struct {
     int32_t ndim;
     int32_t n[3];
@@ -95,6 +101,7 @@ typedef struct {
     int32_t tile[3];
     int32_t diag_every;
     uint32_t flags;
+    double reserve;
 } pic_grid_desc;
 
 /* One particle species.
@@ -279,19 +286,23 @@ int pic_batch_destroy(pic_batch *batch);
 /* ---- Tile autotuner --------------------------------------------------------
  * The tile edge sets the particles per workgroup (ppc * edge^ndim) and the
  * LDS footprint of the particle kernel.  pic_tune builds, inside the caller's
- * workspace, a fresh device-loaded run of the described configuration for
- * every edge in {8, 16, 32} that divides each resolved axis (3D: 8 only),
- * times `nsteps` graph-replayed steps after 2 warm-up steps, and returns the
- * fastest edge in *best_tile and each candidate's milliseconds per step in
- * ms[3] (edge 8, 16, 32; -1 where not tried).  grid->tile and
- * PIC_FLAG_HOST_LOAD are ignored.  Synchronising, on `hip_stream`; the
- * workspace may be reused once it returns.  pic_tune_query (host only) gives
- * the workspace size. */
+ * workspace, `copies` fresh device-loaded runs of the described configuration
+ * (run indices grid->run + i) for every edge in {8, 16, 32} that divides each
+ * resolved axis (3D: 8 only), times `nsteps` graph-replayed steps after 2
+ * warm-up steps -- of the run alone when copies == 1, of a batch of the
+ * copies otherwise (enough copies fill the device, which is the situation of
+ * a member of a large ensemble) -- and returns the fastest edge in
+ * *best_tile and each candidate's milliseconds per step in ms[3] (edge 8,
+ * 16, 32; -1 where not tried).  grid->tile and PIC_FLAG_HOST_LOAD are
+ * ignored.  Synchronising, on `hip_stream`; the workspace may be reused once
+ * it returns.  pic_tune_query (host only) gives the workspace size.  Errors:
+ * INVALID_ARG (copies out of 1..4096, no edge divides the grid, nsteps < 1),
+ * BUFFER_TOO_SMALL, and those of pic_init. */
 int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
-                   size_t *workspace_bytes);
+                   int32_t copies, size_t *workspace_bytes);
 int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
-             void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps,
-             int32_t *best_tile, double ms[3]);
+             int32_t copies, void *workspace, size_t workspace_bytes, void *hip_stream,
+             int32_t nsteps, int32_t *best_tile, double ms[3]);
 
 #ifdef __cplusplus
 }

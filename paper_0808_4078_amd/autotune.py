@@ -7,6 +7,12 @@ library's ``pic_tune`` (fresh device-loaded runs, graph-replayed steps); this
 module groups the members of an ensemble into classes of equal grid and
 similar load, tunes one representative per class, and keeps the answers in a
 JSON cache keyed by the class.
+
+Inside a large ensemble the device is full whatever one member's tile
+count, so what decides is the cost per particle at saturation, not the
+latency of a member alone (alone, a small grid prefers small tiles only
+because they give more workgroups).  The representative is therefore timed
+as a batch of enough copies to hold about SATURATION particles.
 """
 from __future__ import annotations
 
@@ -16,6 +22,8 @@ import os
 from . import pic
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_0808_4078_amd", "tiles.json")
+SATURATION = 1 << 25          # particles that keep every compute unit busy
+MAX_COPIES = 128
 
 
 def load_band(ppc_total: int) -> int:
@@ -24,9 +32,16 @@ def load_band(ppc_total: int) -> int:
     return max(1, (int(ppc_total) + 31) // 32)
 
 
-def class_key(wl, precision: int) -> str:
+def class_key(wl, precision: int, saturate: bool) -> str:
     ppc = sum(s.ppc for s in wl.species)
-    return f"d{wl.ndim}-n{'x'.join(str(v) for v in wl.n[:wl.ndim])}-band{load_band(ppc)}-p{precision}"
+    mode = "sat" if saturate else "alone"
+    return f"d{wl.ndim}-n{'x'.join(str(v) for v in wl.n[:wl.ndim])}-band{load_band(ppc)}-p{precision}-{mode}"
+
+
+def copies_for(wl, saturate: bool) -> int:
+    if not saturate:
+        return 1
+    return int(min(MAX_COPIES, max(1, -(-SATURATION // wl.particles))))
 
 
 def _read(path):
@@ -51,14 +66,15 @@ def _write(path, data):
 
 
 def choose_tiles(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cache_path=DEFAULT_CACHE,
-                 log=None):
-    """Tile edge for every workload.  Returns (tiles, report) where report
-    maps each class key to {"tile", "ms", "representative", "members",
-    "cached"}."""
+                 log=None, saturate: bool = True):
+    """Tile edge for every workload (saturate=True: for stepping them in one
+    large batch; False: for stepping each alone).  Returns (tiles, report)
+    where report maps each class key to {"tile", "ms", "copies",
+    "representative", "members", "cached"}."""
     cache = _read(cache_path)
     classes = {}
     for i, wl in enumerate(workloads):
-        classes.setdefault(class_key(wl, precision), []).append(i)
+        classes.setdefault(class_key(wl, precision, saturate), []).append(i)
     report = {}
     dirty = False
     for key, idx in sorted(classes.items()):
@@ -70,12 +86,14 @@ def choose_tiles(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cach
             ent["cached"] = True
         else:
             g, sp = pic.workload_descs(workloads[rep], precision=precision)
-            best, ms = pic.tune(g, sp, nsteps=nsteps)
-            ent = {"tile": best, "ms": {str(k): v for k, v in ms.items()}, "cached": False}
-            cache[key] = {"tile": best, "ms": ent["ms"]}
+            copies = copies_for(workloads[rep], saturate)
+            best, ms = pic.tune(g, sp, nsteps=nsteps, copies=copies)
+            ent = {"tile": best, "ms": {str(k): v for k, v in ms.items()}, "copies": copies, "cached": False}
+            cache[key] = {"tile": best, "ms": ent["ms"], "copies": copies}
             dirty = True
             if log:
-                log(f"autotune {key}: tile {best} ({', '.join(f'{k}: {v:.3f} ms' for k, v in ms.items())})")
+                log(f"autotune {key}: tile {best} over {copies} copies "
+                    f"({', '.join(f'{k}: {v:.3f} ms' for k, v in ms.items())})")
         ent["representative"] = rep
         ent["members"] = len(idx)
         report[key] = ent

@@ -125,7 +125,7 @@ struct BatchTable {
     const int2 *cell_blocks;    // [n_cell_blocks] (run, block of that run)
     BatchGroup grp[kBatchGroups];
 };
-constexpr int kBatchRebinBlocks = 64;
+constexpr int kBatchRebinBlocks = 256;
 
 // Host-callable launchers (defined in the .hip translation units).
 // Kernels of one step and the group each belongs to: field-diag (0),

@@ -81,6 +81,8 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         return fail(err, PIC_E_INVALID_ARG, "precision %d", g->precision);
     if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(err, PIC_E_INVALID_ARG, "dt must be positive");
     if (g->diag_every < 0) return fail(err, PIC_E_INVALID_ARG, "diag_every < 0");
+    if (!(g->reserve >= 0.0 && g->reserve <= 8.0)) return fail(err, PIC_E_INVALID_ARG, "reserve out of [0, 8]");
+    const double reserve = g->reserve > 0.0 ? g->reserve : 1.0;
     Geometry &G = L->g;
     memset(&G, 0, sizeof(G));
     G.ndim = g->ndim;
@@ -143,7 +145,7 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         Layout::Sp &P = L->sp[s];
         P.tile_nominal = (int64_t)S.ppc * tile_cells;
         P.nominal = P.tile_nominal * G.ntiles;
-        P.reserve = std::max<int64_t>(64, (P.tile_nominal + 1) / 2);
+        P.reserve = std::max<int64_t>(64, (int64_t)std::ceil(reserve * (double)P.tile_nominal));
         P.ncap = (P.tile_nominal + P.reserve) * G.ntiles;
         if (P.ncap * (g->precision == PIC_PREC_MIXED ? 4 : 8) >= ((int64_t)1 << 32))
             return fail(err, PIC_E_UNSUPPORTED, "species %d: a particle array would exceed 4 GiB", s);
@@ -383,6 +385,24 @@ int tile_group(const pic_run *r)
     return r->L.g.tile[0] == 8 ? 0 : (r->L.g.tile[0] == 16 ? 1 : 2);
 }
 
+int batch_carve(int nruns, int64_t ncb, const int64_t nit[kBatchGroups], BatchLayout *B, std::string *err)
+{
+    if (ncb > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
+    B->n_cell_blocks = (int)ncb;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (nit[g] > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
+        B->n_items[g] = (int)nit[g];
+    }
+    Carver c;
+    B->table = c.take(sizeof(BatchTable));
+    B->kp = c.take((size_t)nruns * sizeof(void *));
+    B->cell_blocks = c.take((size_t)B->n_cell_blocks * sizeof(int2));
+    for (int g = 0; g < kBatchGroups; ++g) B->items[g] = c.take((size_t)B->n_items[g] * sizeof(int2));
+    B->queues = c.take(kBatchGroups * sizeof(int));
+    B->bytes = c.off;
+    return PIC_OK;
+}
+
 int batch_layout(int nruns, pic_run *const *runs, BatchLayout *B, std::string *err)
 {
     if (nruns < 1 || !runs) return fail(err, PIC_E_INVALID_ARG, "batch needs at least one run");
@@ -398,20 +418,7 @@ int batch_layout(int nruns, pic_run *const *runs, BatchLayout *B, std::string *e
         ncb += (r->L.g.cells + 255) / 256;
         nit[tile_group(r)] += r->L.g.ntiles;
     }
-    if (ncb > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
-    B->n_cell_blocks = (int)ncb;
-    for (int g = 0; g < kBatchGroups; ++g) {
-        if (nit[g] > INT32_MAX / 2) return fail(err, PIC_E_UNSUPPORTED, "batch too large");
-        B->n_items[g] = (int)nit[g];
-    }
-    Carver c;
-    B->table = c.take(sizeof(BatchTable));
-    B->kp = c.take((size_t)nruns * sizeof(void *));
-    B->cell_blocks = c.take((size_t)B->n_cell_blocks * sizeof(int2));
-    for (int g = 0; g < kBatchGroups; ++g) B->items[g] = c.take((size_t)B->n_items[g] * sizeof(int2));
-    B->queues = c.take(kBatchGroups * sizeof(int));
-    B->bytes = c.off;
-    return PIC_OK;
+    return batch_carve(nruns, ncb, nit, B, err);
 }
 
 // Run-level or batch-level profiled steps: `launch(ev)` enqueues one step
@@ -492,10 +499,11 @@ int batch_hip_fail(pic_batch *b, hipError_t e, const char *what)
         if (e_ != hipSuccess) return batch_hip_fail(b, e_, #expr); \
     } while (0)
 
-// Tile autotuner: where each candidate run sits inside the workspace.
+// Tile autotuner: where each copy of a candidate run, and the batch table
+// of the copies, sit inside the workspace.
 struct TuneCarve {
     pic_sizes sz;
-    size_t part[kMaxSpecies], fields, scratch, diag, bytes;
+    size_t part[kMaxSpecies], fields, scratch, diag, per_copy, table, table_bytes, bytes;
 };
 
 bool tile_fits(const pic_grid_desc *g, int t)
@@ -1143,7 +1151,8 @@ int pic_batch_destroy(pic_batch *b)
 // ---------------------------------------------------------------------------
 // Tile autotuner
 
-static int tune_carve(const pic_grid_desc *grid, const pic_species_desc *sp, int ns, int tile, TuneCarve *T)
+static int tune_carve(const pic_grid_desc *grid, const pic_species_desc *sp, int ns, int copies, int tile,
+                      TuneCarve *T)
 {
     pic_grid_desc g = *grid;
     for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? tile : 0;
@@ -1154,20 +1163,35 @@ static int tune_carve(const pic_grid_desc *grid, const pic_species_desc *sp, int
     T->fields = c.take(T->sz.field_bytes);
     T->scratch = c.take(T->sz.scratch_bytes);
     T->diag = c.take(T->sz.diag_bytes);
-    T->bytes = c.off;
+    T->per_copy = c.off;
+    // batch table of the copies
+    int64_t cells = 1, tiles = 1;
+    for (int a = 0; a < g.ndim; ++a) {
+        cells *= g.n[a];
+        tiles *= g.n[a] / tile;
+    }
+    int64_t nit[kBatchGroups] = {0, 0, 0};
+    nit[tile == 8 ? 0 : (tile == 16 ? 1 : 2)] = tiles * copies;
+    BatchLayout B;
+    rc = batch_carve(copies, (cells + 255) / 256 * copies, nit, &B, nullptr);
+    if (rc) return rc;
+    T->table = T->per_copy * (size_t)copies;
+    T->table_bytes = B.bytes;
+    T->bytes = T->table + B.bytes;
     return PIC_OK;
 }
 
-int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
                    size_t *workspace_bytes)
 {
     if (!grid || !species || !workspace_bytes) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
+    if (copies < 1 || copies > 4096) return fail(nullptr, PIC_E_INVALID_ARG, "copies %d out of 1..4096", copies);
     size_t need = 0;
     int tried = 0;
     for (int t = 8; t <= 32; t *= 2) {
         if (!tile_fits(grid, t)) continue;
         TuneCarve T;
-        int rc = tune_carve(grid, species, nspecies, t, &T);
+        int rc = tune_carve(grid, species, nspecies, copies, t, &T);
         if (rc) return rc;
         need = std::max(need, T.bytes);
         ++tried;
@@ -1177,13 +1201,14 @@ int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, i
     return PIC_OK;
 }
 
-int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, void *workspace,
-             size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_tile, double *ms)
+int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
+             void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_tile,
+             double *ms)
 {
     if (!grid || !species || !workspace || !best_tile || !ms || nsteps < 1)
         return fail(nullptr, PIC_E_INVALID_ARG, "bad argument");
     size_t need = 0;
-    int rc = pic_tune_query(grid, species, nspecies, &need);
+    int rc = pic_tune_query(grid, species, nspecies, copies, &need);
     if (rc) return rc;
     if (workspace_bytes < need)
         return fail(nullptr, PIC_E_BUFFER_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
@@ -1194,35 +1219,46 @@ int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
         ms[k] = -1.0;
         if (!tile_fits(grid, t)) continue;
         TuneCarve T;
-        rc = tune_carve(grid, species, nspecies, t, &T);
+        rc = tune_carve(grid, species, nspecies, copies, t, &T);
         if (rc) return rc;
-        pic_grid_desc g = *grid;
-        for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? t : 0;
-        g.flags &= ~(uint32_t)PIC_FLAG_HOST_LOAD;
-        pic_buffers buf;
-        memset(&buf, 0, sizeof(buf));
-        for (int s = 0; s < nspecies; ++s) buf.particles[s] = (char *)workspace + T.part[s];
-        buf.fields = (char *)workspace + T.fields;
-        buf.scratch = (char *)workspace + T.scratch;
-        buf.diag = (char *)workspace + T.diag;
-        pic_run *r = nullptr;
-        rc = pic_init(&g, species, nspecies, &buf, hip_stream, &r);
-        if (rc) return rc;
+        std::vector<pic_run *> runs;
+        pic_batch *b = nullptr;
+        for (int i = 0; !rc && i < copies; ++i) {
+            pic_grid_desc g = *grid;
+            for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? t : 0;
+            g.flags &= ~(uint32_t)PIC_FLAG_HOST_LOAD;
+            g.run = grid->run + (uint32_t)i;
+            char *base = (char *)workspace + T.per_copy * (size_t)i;
+            pic_buffers buf;
+            memset(&buf, 0, sizeof(buf));
+            for (int s = 0; s < nspecies; ++s) buf.particles[s] = base + T.part[s];
+            buf.fields = base + T.fields;
+            buf.scratch = base + T.scratch;
+            buf.diag = base + T.diag;
+            pic_run *r = nullptr;
+            rc = pic_init(&g, species, nspecies, &buf, hip_stream, &r);
+            if (!rc) runs.push_back(r);
+        }
+        if (!rc && copies > 1)
+            rc = pic_batch_init(copies, runs.data(), (char *)workspace + T.table, T.table_bytes, 0, 0, &b);
+        auto steps = [&](int32_t n) { return b ? pic_batch_step(b, n) : pic_step(runs[0], n); };
         hipEvent_t e0 = nullptr, e1 = nullptr;
         float el = 0.f;
-        hipError_t he = hipEventCreate(&e0);
-        if (he == hipSuccess) he = hipEventCreate(&e1);
-        if (he == hipSuccess) rc = pic_step(r, 2);
-        if (he == hipSuccess && !rc) he = hipEventRecord(e0, st);
-        if (he == hipSuccess && !rc) rc = pic_step(r, nsteps);
-        if (he == hipSuccess && !rc) he = hipEventRecord(e1, st);
-        if (he == hipSuccess && !rc) he = hipEventSynchronize(e1);
-        if (he == hipSuccess && !rc) he = hipEventElapsedTime(&el, e0, e1);
-        if (he == hipSuccess && !rc) rc = pic_sync(r);
+        hipError_t he = hipSuccess;
+        if (!rc) he = hipEventCreate(&e0);
+        if (!rc && he == hipSuccess) he = hipEventCreate(&e1);
+        if (!rc && he == hipSuccess) rc = steps(2);
+        if (!rc && he == hipSuccess) he = hipEventRecord(e0, st);
+        if (!rc && he == hipSuccess) rc = steps(nsteps);
+        if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
+        if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+        if (!rc && he == hipSuccess) he = hipEventElapsedTime(&el, e0, e1);
+        if (!rc && he == hipSuccess) rc = b ? pic_batch_sync(b) : pic_sync(runs[0]);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         (void)hipStreamSynchronize(st);
-        pic_destroy(r);
+        if (b) pic_batch_destroy(b);
+        for (pic_run *r : runs) pic_destroy(r);
         if (he != hipSuccess) return fail(nullptr, PIC_E_HIP, "tuner timing: %s", hipGetErrorString(he));
         if (rc) return rc;
         ms[k] = (double)el / nsteps;

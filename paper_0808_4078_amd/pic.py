@@ -33,7 +33,8 @@ STATUS = {0: "PIC_OK", -1: "PIC_E_INVALID_ARG", -2: "PIC_E_UNSUPPORTED", -3: "PI
 class GridDesc(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("run", C.c_uint32),
-                ("tile", C.c_int32 * 3), ("diag_every", C.c_int32), ("flags", C.c_uint32)]
+                ("tile", C.c_int32 * 3), ("diag_every", C.c_int32), ("flags", C.c_uint32),
+                ("reserve", C.c_double)]
 
 
 class SpeciesDesc(C.Structure):
@@ -119,8 +120,8 @@ def lib():
         L.pic_batch_sync.argtypes = [vp]
         L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
         L.pic_batch_destroy.argtypes = [vp]
-        L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(C.c_size_t)]
-        L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, vp, C.c_size_t, vp, C.c_int32,
+        L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, P(C.c_size_t)]
+        L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp, C.c_int32,
                                P(C.c_int32), P(C.c_double)]
         _lib = L
     return _lib
@@ -138,7 +139,7 @@ def _check(rc: int, what: str, handle=None):
 
 
 def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0, tile=0,
-               diag_every=0, flags=0):
+               diag_every=0, flags=0, reserve=0.0):
     """Descriptors from plain values.  species: list of dicts with keys
     charge, mass, density, ppc, drift_u, u_th, cancel_current_of, nu_coll."""
     g = GridDesc()
@@ -153,6 +154,7 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
     g.run = int(run)
     g.diag_every = int(diag_every)
     g.flags = int(flags)
+    g.reserve = float(reserve)
     arr = (SpeciesDesc * len(species))()
     for i, s in enumerate(species):
         arr[i].charge = float(s.get("charge", -1.0))
@@ -168,14 +170,14 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
     return g, arr
 
 
-def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0):
+def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0, reserve=0.0):
     """Descriptors of a synthetic workload object (attributes ndim, n, d, dt,
     seed, species[name, q, m, density, ppc, drift_u, u_th, nu, cancel_current_of])."""
     sp = [dict(charge=s.q, mass=s.m, density=s.density, ppc=s.ppc, drift_u=s.drift_u, u_th=s.u_th,
                cancel_current_of=s.cancel_current_of, nu_coll=s.nu) for s in wl.species]
     if getattr(wl, "lattice", False):
         flags |= PIC_FLAG_LATTICE_LOAD
-    return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags)
+    return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags, reserve)
 
 
 def query(grid: GridDesc, species) -> Sizes:
@@ -378,17 +380,19 @@ class Batch:
         self.close()
 
 
-def tune(grid: GridDesc, species, nsteps: int = 10, stream=None):
-    """pic_tune: (best tile edge, {edge: ms per step}) for this configuration,
-    timed on the current device inside a temporary torch workspace."""
+def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None):
+    """pic_tune: (best tile edge, {edge: ms per step}) for this configuration
+    (copies > 1: a batch of that many copies), timed on the current device
+    inside a temporary torch workspace."""
     import torch
     nbytes = C.c_size_t()
-    _check(lib().pic_tune_query(C.byref(grid), species, len(species), C.byref(nbytes)), "pic_tune_query")
+    _check(lib().pic_tune_query(C.byref(grid), species, len(species), int(copies), C.byref(nbytes)),
+           "pic_tune_query")
     ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device="cuda")
     st = stream if stream is not None else torch.cuda.current_stream()
     best = C.c_int32()
     ms = (C.c_double * 3)()
-    _check(lib().pic_tune(C.byref(grid), species, len(species), C.c_void_p(ws.data_ptr()), int(ws.numel()),
-                          C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
+    _check(lib().pic_tune(C.byref(grid), species, len(species), int(copies), C.c_void_p(ws.data_ptr()),
+                          int(ws.numel()), C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
     del ws
     return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}

@@ -109,16 +109,20 @@ def test_batch_and_tuner_queries_validate_on_the_host():
     assert L.pic_batch_init(0, None, None, 0, 0, 0, C.byref(out)) == -1
     # workspace of the tuner: the largest candidate's four buffers
     g, sp = pic.workload_descs(synth.C1, precision=pic.PIC_PREC_MIXED)
-    assert L.pic_tune_query(C.byref(g), sp, len(sp), C.byref(nbytes)) == 0
+    assert L.pic_tune_query(C.byref(g), sp, len(sp), 1, C.byref(nbytes)) == 0
     biggest = 0
     for t in (8, 16, 32):
         gt, spt = pic.workload_descs(synth.C1, precision=pic.PIC_PREC_MIXED, tile=t)
         s = pic.query(gt, spt)
         biggest = max(biggest, sum(s.particle_bytes[:2]) + s.field_bytes + s.scratch_bytes + s.diag_bytes)
     assert biggest <= nbytes.value < biggest + 8 * 256
+    one = nbytes.value
+    assert L.pic_tune_query(C.byref(g), sp, len(sp), 3, C.byref(nbytes)) == 0       # 3 copies + batch table
+    assert 3 * biggest < nbytes.value < 3 * one + 64 * 1024
+    assert L.pic_tune_query(C.byref(g), sp, len(sp), 0, C.byref(nbytes)) == -1
     g, sp = pic.make_descs(2, (36, 36), (0.2, 0.2), 0.1, [dict(density=1.0, ppc=4)])
-    assert L.pic_tune_query(C.byref(g), sp, 1, C.byref(nbytes)) == -1  # no edge divides 36
+    assert L.pic_tune_query(C.byref(g), sp, 1, 1, C.byref(nbytes)) == -1  # no edge divides 36
     best = C.c_int32()
     ms = (C.c_double * 3)()
     g, sp = pic.workload_descs(synth.C1)
-    assert L.pic_tune(C.byref(g), sp, len(sp), None, 0, None, 4, C.byref(best), ms) == -1
+    assert L.pic_tune(C.byref(g), sp, len(sp), 1, None, 0, None, 4, C.byref(best), ms) == -1

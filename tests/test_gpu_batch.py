@@ -147,12 +147,14 @@ def test_tuner_and_cache(pic, tmp_path):
     from paper_0808_4078_amd import autotune
     wl = synth.beam_plasma((64, 64), ppc=16, name="tune")
     g, sp = pic.workload_descs(wl)
-    best, ms = pic.tune(g, sp, nsteps=4)
-    assert set(ms) == {8, 16, 32} and best in ms
-    assert all(v > 0 for v in ms.values()) and ms[best] == min(ms.values())
+    for copies in (1, 6):
+        best, ms = pic.tune(g, sp, nsteps=4, copies=copies)
+        assert set(ms) == {8, 16, 32} and best in ms
+        assert all(v > 0 for v in ms.values()) and ms[best] == min(ms.values())
     wls = [wl, synth.beam_plasma((64, 64), ppc=12, name="b"), synth.beam_plasma((32, 32), ppc=16, name="c")]
     cache = str(tmp_path / "tiles.json")
     tiles, rep = autotune.choose_tiles(wls, nsteps=3, cache_path=cache)
+    assert all(v["copies"] > 1 for v in rep.values())
     assert len(rep) == 2 and tiles[0] == tiles[1] and tiles[2] in (8, 16, 32)
     assert not any(v["cached"] for v in rep.values())
     tiles2, rep2 = autotune.choose_tiles(wls, nsteps=3, cache_path=cache)
