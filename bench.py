@@ -27,6 +27,57 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s (gather+push+deposit), mixed-FP32 vs FP64, 2D 1024^2 64 ppc"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_0808_4078_amd/csrc/pic_kernels.hip", "paper_0808_4078_amd/csrc/pic_internal.hpp")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_particle_c3_hbm_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the particle kernel's source files: a hardware-counter
+    reading of the kernel is valid only for the source it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per particle-kernel launch from the committed counter
+    summary, or None when the summary is absent or was taken on other
+    kernel sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device-to-device copy of known size, the calibration kernel
+    for the FETCH_SIZE / WRITE_SIZE counters (each dispatch reads and writes
+    nbytes)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "dispatches": reps,
+                      "ms": ms, "GBs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
@@ -195,6 +246,8 @@ def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the 1 GiB copy that calibrates the HBM byte counters, then exit")
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
@@ -211,6 +264,9 @@ def main():
         print(f"bench.py: --gpus {a.gpus} refused: this PIC build runs on a single GPU "
               "(multi-GPU domain decomposition is not built)", file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
     import synth
     from dataclasses import replace
 
@@ -255,7 +311,7 @@ def main():
         "relayouts": mixed["diag"]["rebins"],
         "graph_replay_ms_per_step": mixed["graph_ms"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if not a.quick else None},
     }
     if fp64 is not None:
         f_ms = fp64["profiled_ms"] / a.steps

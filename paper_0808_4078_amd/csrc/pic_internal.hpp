@@ -103,16 +103,25 @@ struct KParams {
     int32_t *rb_cap;     // [nspecies][tiles]
     int32_t *rb_fill;    // [nspecies][tiles]
     int fd_blocks;       // blocks (and partial records) of the field-diagnostic reduction
+    int32_t *order;      // [tiles] particle-kernel work order (XCD class, then decreasing load)
+    uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
+    double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
 };
 
 // An ensemble of runs stepped together: every launch of a step covers all
 // runs.  Runs share precision and dimension; in 2D each run has its own tile
 // edge, and the particle kernel is launched once per edge (group g: edge
-// 8 << g; 3D runs use group 0).
+// 8 << g; 3D runs use group 0).  The work items (run, k) -- the k-th tile of
+// the run's work order, whose tile index is k mod 8 -- are split by XCD
+// class k mod 8 into one list and one queue per class.
+constexpr int kBatchXcds = 8;
 struct BatchGroup {
-    int n_items;          // particle-kernel work items of the runs with this edge
-    const int2 *items;    // [n_items] (run, tile), heaviest tiles first
-    int *queue;           // work counter of the persistent particle kernel
+    int n_items;                   // work items of the runs with this edge
+    const int2 *items;             // [n_items] (run, k), class-major; in a class,
+                                   // runs with the most particles per tile first
+    int cls_start[kBatchXcds];     // first item of each class
+    int cls_len[kBatchXcds];       // items of each class
+    int *queue;                    // [kBatchXcds] work counters of the persistent particle kernel
 };
 constexpr int kBatchGroups = 3;
 struct BatchTable {

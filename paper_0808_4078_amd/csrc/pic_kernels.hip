@@ -108,19 +108,34 @@ template <> struct Arith<double> {
 // The step counter and particle-set parity live in memory that kernels also
 // update; reading them through readfirstlane tells the compiler they are
 // uniform, so everything indexed by them stays in scalar registers.
-__device__ __forceinline__ int64_t uniform_step(const KParams *kp)
+template <typename KP>
+__device__ __forceinline__ int64_t uniform_step(KP kp)
 {
     const int64_t v = kp->state->step;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ int uniform_par(const KParams *kp)
+// A value every lane of the wave holds (read from LDS or from memory at a
+// uniform address) as a scalar.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename P>
+__device__ __forceinline__ P *wave_uniform_ptr(P *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename KP>
+__device__ __forceinline__ int uniform_par(KP kp)
 {
     return __builtin_amdgcn_readfirstlane(kp->state->par);
 }
 
-__device__ __forceinline__ bool diag_step(const KParams *kp, int64_t step)
+template <typename KP>
+__device__ __forceinline__ bool diag_step(KP kp, int64_t step)
 {
     return kp->diag_every > 0 && (step % kp->diag_every) == 0;
 }
@@ -360,11 +375,17 @@ __device__ __forceinline__ void deposit_cell(A *sJx, A *sJy, A *sJz, const int (
 // Crossing particles wait in a per-wave ring of kQueue entries in LDS and are
 // deposited 64 at a time through deposit_window, with every lane busy.
 constexpr int kQueue = 128;
+constexpr int kOrderBuckets = 64;
+constexpr int kAdvanceThreads = 256;     // workgroup size of the end-of-step kernel
+constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with its own L2
 
 constexpr int kBatch = 2;   // particles fetched per lane before processing
 
-template <typename R, typename A, int D, int T>
-__device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, int bid, int nb)
+// KP: pointer to the run's parameters -- the kernel argument, or (batched
+// runs) a constant-address-space pointer, which lets the parameter loads be
+// scalar loads (the parameter blocks are never written by a kernel).
+template <typename R, typename A, int D, int T, typename KP>
+__device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
 {
     constexpr int NF = T + 2;
     constexpr int NJ = T + 3;
@@ -432,12 +453,14 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
     R dtd[3];
     for (int a = 0; a < 3; ++a) dtd[a] = R(kp->g.dt / kp->g.d[a]);
 
+    uint32_t load = 0;                                      // particles of the tile, all species
     for (int s = 0; s < kp->nspecies; ++s) {
-        const SpeciesDev &S = kp->sp[s];
+        const auto &S = kp->sp[s];
         const int32_t bstart = S.start[tile], bcap = S.cap[tile];
         const uint32_t nf = S.cnt_front[src * ntiles + tile];
         const uint32_t nb = S.cnt_back[src * ntiles + tile];
         const uint32_t total = nf + nb;
+        load += total;
         const R qm = R(S.qmdt2);
         R kd[3];                                            // q w d_a/dt
         for (int a = 0; a < 3; ++a) kd[a] = R(S.qw * kp->g.d[a] / kp->g.dt);
@@ -757,6 +780,8 @@ __device__ __forceinline__ void particle_body(const KParams *__restrict__ kp, in
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0)
+        kp->tile_bucket[tile] = (uint8_t)min(kOrderBuckets - 1, (int)((double)load * kp->order_scale + 0.5));
     GLB R *Jt = gbl((R *)kp->Jtile) + (int64_t)tile * 3 * NJ_D;
     for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) Jt[i] = R(sJ[i]);
 }
@@ -1112,6 +1137,37 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
             kp->sp[s].cnt_back[par * ntiles + t] = 0;
         }
     }
+    // Work order of the next step.  Workgroup b of the particle launch runs
+    // on XCD b mod 8 (round-robin dispatch) and takes tile order[b].  Tile t
+    // keeps XCD class c = t mod 8 -- its y and z neighbours, the destinations
+    // of most of its movers, share that XCD's L2 -- and within a class the
+    // tiles go by decreasing load bucket (written by this step's particle
+    // kernel from the tile's counts at the start of the step), so each XCD
+    // starts its heaviest tiles first: order[8 r + c] is the r-th tile of
+    // class c.  Class c holds exactly the positions b < ntiles with b mod 8
+    // == c, so this is a permutation for any tile count.
+    {
+        __shared__ int s_hist[kXcds][kOrderBuckets];
+        const uint8_t *bucket = kp->tile_bucket;
+        for (int i = threadIdx.x; i < kXcds * kOrderBuckets; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&s_hist[t % kXcds][bucket[t]], 1);
+        __syncthreads();
+        if (threadIdx.x < kXcds) {
+            int run = 0;
+            for (int b = kOrderBuckets - 1; b >= 0; --b) {
+                const int c = s_hist[threadIdx.x][b];
+                s_hist[threadIdx.x][b] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+            const int c = t % kXcds;
+            const int r = atomicAdd(&s_hist[c][bucket[t]], 1);
+            kp->order[kXcds * r + c] = t;
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (diag_step(kp, step)) st->ring_head += 1;
@@ -1146,13 +1202,21 @@ __global__ __launch_bounds__(256) void kb_field_diag(const BatchTable *__restric
     field_diag_body<R>(kp, blockIdx.x, nb);
 }
 
+typedef __attribute__((address_space(4))) const KParams KParamsC;
+
+// One workgroup per tile; workgroup b takes tile order[b] (see the work
+// order built at the end of each step).
 template <typename R, typename A, int D, int T>
 __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
 {
-    particle_body<R, A, D, T>(kp, blockIdx.x, gridDim.x);
+    const KParamsC *kc = (const KParamsC *)kp;
+    particle_body<R, A, D, T>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
 }
-// Persistent: each workgroup takes (run, tile) items of its tile group until
-// the group's list is exhausted.  The counter only grows, so every workgroup
+
+// Persistent: workgroup w (on XCD w mod 8) takes the items of its XCD
+// class from that class's queue -- a run's tile then runs on the XCD it has
+// in a run stepped alone -- and, when its class is exhausted, the remaining
+// items of the other classes.  The counters only grow, so every workgroup
 // reaches the exit.
 template <typename R, typename A, int D, int T>
 __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restrict__ bt)
@@ -1160,15 +1224,21 @@ __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restri
     constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
     __shared__ int s_item;
     const BatchGroup &G = bt->grp[g];
-    const int n_items = G.n_items;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(G.queue, 1);
-        __syncthreads();
-        const int i = s_item;
-        __syncthreads();
-        if (i >= n_items) break;
-        const int2 it = G.items[i];
-        particle_body<R, A, D, T>(bt->kp[it.x], it.y, 0);
+    const int c0 = blockIdx.x % kBatchXcds;
+    for (int cc = 0; cc < kBatchXcds; ++cc) {
+        const int c = (c0 + cc) % kBatchXcds;
+        const int len = G.cls_len[c];
+        const int2 *items = G.items + G.cls_start[c];
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(&G.queue[c], 1);
+            __syncthreads();
+            const int i = wave_uniform(s_item);
+            __syncthreads();
+            if (i >= len) break;
+            const int2 it = items[i];
+            const KParamsC *kp = (const KParamsC *)wave_uniform_ptr(bt->kp[wave_uniform(it.x)]);
+            particle_body<R, A, D, T>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
+        }
     }
 }
 
@@ -1252,15 +1322,16 @@ __global__ __launch_bounds__(256) void kb_yee_e(const BatchTable *__restrict__ b
     yee_e_body<R, D>(bt->kp[cb.x], cb.y, 0);
 }
 
-__global__ __launch_bounds__(256) void k_advance(const KParams *__restrict__ kp)
+__global__ __launch_bounds__(kAdvanceThreads) void k_advance(const KParams *__restrict__ kp)
 {
     advance_body(kp, blockIdx.x, gridDim.x);
 }
 // one workgroup per run; the first also rewinds the particle-kernel queues
-__global__ __launch_bounds__(256) void kb_advance(const BatchTable *__restrict__ bt)
+__global__ __launch_bounds__(kAdvanceThreads) void kb_advance(const BatchTable *__restrict__ bt)
 {
     advance_body(bt->kp[blockIdx.x], 0, 1);
-    if (blockIdx.x == 0 && threadIdx.x < kBatchGroups) *bt->grp[threadIdx.x].queue = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kBatchGroups * kBatchXcds)
+        bt->grp[threadIdx.x / kBatchXcds].queue[threadIdx.x % kBatchXcds] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1423,7 +1494,7 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
     L(k_yee_e<R, D>, dim3(cb), dim3(256), dp);
     L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
-    L(k_advance, dim3(1), dim3(256), dp);
+    L(k_advance, dim3(1), dim3(kAdvanceThreads), dp);
     return hipGetLastError();
 }
 
@@ -1492,7 +1563,7 @@ static hipError_t batch_kernels(const BatchTable &ht, const BatchTable *dt, cons
     L(kb_yee_b<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt, 0.5);
     L(kb_yee_e<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt);
     L(kb_yee_b<R, D>, dim3(ht.n_cell_blocks), dim3(256), dt, 0.5);
-    L(kb_advance, dim3(nr), dim3(256), dt);
+    L(kb_advance, dim3(nr), dim3(kAdvanceThreads), dt);
     return hipGetLastError();
 }
 

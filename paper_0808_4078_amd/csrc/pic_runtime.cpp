@@ -33,7 +33,7 @@ struct Layout {
         uint32_t ovf_cap;
     } sp[kMaxSpecies];
     size_t F, J;                                            // field buffer
-    size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4];   // scratch
+    size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4], order, bucket;   // scratch
     Geometry g;
     int nj;
     size_t real;                                            // sizeof(float|double)
@@ -189,6 +189,8 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         L->state = c.take(sizeof(DevState));
         L->kparams = c.take(sizeof(KParams));
         for (int i = 0; i < 4; ++i) L->rb[i] = c.take((size_t)ns * G.ntiles * 4);
+        L->order = c.take((size_t)G.ntiles * 4);
+        L->bucket = c.take((size_t)G.ntiles);
         L->scratch_bytes = c.off;
     }
     L->diag_bytes = align256(sizeof(pic_diag) * kRing);
@@ -398,7 +400,7 @@ int batch_carve(int nruns, int64_t ncb, const int64_t nit[kBatchGroups], BatchLa
     B->kp = c.take((size_t)nruns * sizeof(void *));
     B->cell_blocks = c.take((size_t)B->n_cell_blocks * sizeof(int2));
     for (int g = 0; g < kBatchGroups; ++g) B->items[g] = c.take((size_t)B->n_items[g] * sizeof(int2));
-    B->queues = c.take(kBatchGroups * sizeof(int));
+    B->queues = c.take(kBatchGroups * kBatchXcds * sizeof(int));
     B->bytes = c.off;
     return PIC_OK;
 }
@@ -636,6 +638,13 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     K.rb_fill = (int32_t *)at(buffers->scratch, L.rb[3]);
     r->dp = (KParams *)at(buffers->scratch, L.kparams);
     K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
+    K.order = (int32_t *)at(buffers->scratch, L.order);
+    K.tile_bucket = (uint8_t *)at(buffers->scratch, L.bucket);
+    {
+        int64_t per_tile = 0;
+        for (int s = 0; s < nspecies; ++s) per_tile += L.sp[s].tile_nominal;
+        K.order_scale = 16.0 / (double)std::max<int64_t>(1, per_tile);
+    }
 
 #define INIT_CHK(expr)                                          \
     do {                                                        \
@@ -654,6 +663,10 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     DevState st0;
     memset(&st0, 0, sizeof(st0));
     INIT_CHK(hipMemcpyAsync(K.state, &st0, sizeof(st0), hipMemcpyHostToDevice, r->stream));
+    std::vector<int32_t> iota((size_t)L.g.ntiles);
+    for (int t = 0; t < L.g.ntiles; ++t) iota[t] = t;
+    INIT_CHK(hipMemcpyAsync(K.order, iota.data(), iota.size() * 4, hipMemcpyHostToDevice, r->stream));
+    INIT_CHK(hipMemsetAsync(K.tile_bucket, 0, (size_t)L.g.ntiles, r->stream));
     for (int s = 0; s < nspecies; ++s) {
         std::vector<int32_t> start, cap;
         uniform_bins(L.sp[s], L.g.ntiles, start, cap);
@@ -1021,11 +1034,19 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
     std::vector<int> order(nruns);
     for (int i = 0; i < nruns; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return load[a] > load[c]; });
+    // class-major lists: class c holds the items (run, k) with k mod 8 == c
     std::vector<int2> items[kBatchGroups];
-    for (int i : order) {
-        const pic_run *r = runs[i];
-        for (int t = 0; t < r->L.g.ntiles; ++t) items[tile_group(r)].push_back(make_int2(i, t));
-    }
+    int cls_start[kBatchGroups][kBatchXcds], cls_len[kBatchGroups][kBatchXcds];
+    for (int g = 0; g < kBatchGroups; ++g)
+        for (int c = 0; c < kBatchXcds; ++c) {
+            cls_start[g][c] = (int)items[g].size();
+            for (int i : order) {
+                const pic_run *r = runs[i];
+                if (tile_group(r) != g) continue;
+                for (int k = c; k < r->L.g.ntiles; k += kBatchXcds) items[g].push_back(make_int2(i, k));
+            }
+            cls_len[g][c] = (int)items[g].size() - cls_start[g][c];
+        }
     char *base = (char *)table;
     BatchTable &H = b->ht;
     memset(&H, 0, sizeof(H));
@@ -1039,7 +1060,11 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
     for (int g = 0; g < kBatchGroups; ++g) {
         H.grp[g].n_items = (int)items[g].size();
         H.grp[g].items = (const int2 *)(base + B.items[g]);
-        H.grp[g].queue = (int *)(base + B.queues) + g;
+        for (int c = 0; c < kBatchXcds; ++c) {
+            H.grp[g].cls_start[c] = cls_start[g][c];
+            H.grp[g].cls_len[c] = cls_len[g][c];
+        }
+        H.grp[g].queue = (int *)(base + B.queues) + g * kBatchXcds;
     }
     b->dt = (BatchTable *)(base + B.table);
     // persistent workgroups: as many as fit on the device at once
@@ -1055,7 +1080,7 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
         he = batch_particle_occupancy(b->precision, b->ndim, g, &per_cu);
         b->pblocks[g] = std::max(1, per_cu) * std::max(1, cus);
     }
-    const int zeros[kBatchGroups] = {0, 0, 0};
+    const std::vector<int> zeros((size_t)kBatchGroups * kBatchXcds, 0);
 #define BINIT_CHK(expr)                                  \
     do {                                                 \
         hipError_t e_ = (expr);                          \
@@ -1075,7 +1100,8 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
         if (!items[g].empty())
             BINIT_CHK(hipMemcpyAsync(base + B.items[g], items[g].data(), items[g].size() * sizeof(int2),
                                      hipMemcpyHostToDevice, b->stream));
-    BINIT_CHK(hipMemcpyAsync(base + B.queues, zeros, sizeof(zeros), hipMemcpyHostToDevice, b->stream));
+    BINIT_CHK(hipMemcpyAsync(base + B.queues, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice,
+                             b->stream));
     BINIT_CHK(hipStreamSynchronize(b->stream));
 #undef BINIT_CHK
     for (pic_run *r : b->runs) r->owner = b;
