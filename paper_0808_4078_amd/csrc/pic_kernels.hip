@@ -379,7 +379,7 @@ constexpr int kOrderBuckets = 64;
 constexpr int kAdvanceThreads = 256;     // workgroup size of the end-of-step kernel
 constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with its own L2
 
-constexpr int kBatch = 2;   // particles fetched per lane before processing
+constexpr int kBatch = 2;   // particles each lane keeps in flight ahead of the one it processes
 
 // KP: pointer to the run's parameters -- the kernel argument, or (batched
 // runs) a constant-address-space pointer, which lets the parameter loads be
@@ -492,9 +492,10 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         if (threadIdx.x == 0) s_front = 0;
         __syncthreads();
 
-        // Raw fields of one particle as stored.  Each lane fetches kBatch
-        // particles (k, k+256, ...) before processing them, so a wave keeps
-        // kBatch particles' loads in flight.
+        // Raw fields of one particle as stored.  Each lane holds the next
+        // kBatch particles (k, k+256, ...): before processing the oldest it
+        // issues the loads of the one kBatch steps ahead, so every lane keeps
+        // kBatch particles' loads in flight while it computes.
         struct Raw {
             uint32_t c;
             R p[D];
@@ -524,20 +525,61 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             }
             deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, sQv[wave][2 * D][e]);
         };
-        for (uint32_t base = 0; base < total; base += kBatch * kBlock) {
-            Raw q[kBatch];
+        // A particle that leaves the tile (mover) reserves its slot at the
+        // back of the new tile's bin with a returning atomic; in mixed mode
+        // the slot, and the room left in that bin, are used one iteration
+        // later, so the round trip overlaps the next particle's work.  Store layout of the
+        // pending mover: packed cell (mixed), position per resolved axis
+        // (offset in mixed mode, cell + offset in FP64), momenta, id.
+        bool pm_valid = false;
+        uint32_t pm_slot = 0;
+        int32_t pm_room = 0, pm_top = 0;
+        Raw pm;
+        auto emit_mover = [&]() {
+            if ((int64_t)pm_slot < (int64_t)pm_room) {
+                const uint32_t o = (uint32_t)pm_top - pm_slot;
+                if constexpr (sizeof(R) == 4) st(ocell, o, pm.c);
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const uint32_t kk = base + u * kBlock + threadIdx.x;
-                if (kk < total) fetch(kk, q[u]);
+                for (int a = 0; a < D; ++a) st(opos_a[a], o, pm.p[a]);
+                st(ou0, o, pm.u[0]);
+                st(ou1, o, pm.u[1]);
+                st(ou2, o, pm.u[2]);
+                if (track) st(oid, o, pm.id);
+            } else {
+                // no room left in the new tile's bin: overflow list (set 2),
+                // re-laid out at the end of the step
+                const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
+                state->rebin = 1;
+                if (oi < S.ovf_cap) {
+                    if constexpr (sizeof(R) == 4) gbl(S.cell[2])[oi] = pm.c;
+                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = pm.p[a];
+                    gbl((R *)S.u[2][0])[oi] = pm.u[0];
+                    gbl((R *)S.u[2][1])[oi] = pm.u[1];
+                    gbl((R *)S.u[2][2])[oi] = pm.u[2];
+                    if (track) gbl(S.id[2])[oi] = pm.id;
+                } else {
+                    atomicOr(&state->fatal, 1);
+                }
             }
+        };
+        Raw q[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t kk = u * kBlock + threadIdx.x;
+            if (kk < total) fetch(kk, q[u]);
+        }
 #pragma unroll 1
-            for (int u = 0; u < kBatch; ++u) {
-            const uint32_t k = base + u * kBlock + threadIdx.x;
+        for (uint32_t base = 0; base < total; base += kBlock) {
+            {
+            const uint32_t k = base + threadIdx.x;
             const bool active = k < total;
             const Raw cur = q[0];
 #pragma unroll
             for (int v = 0; v + 1 < kBatch; ++v) q[v] = q[v + 1];
+            {
+                const uint32_t kn = k + kBatch * kBlock;
+                if (kn < total) fetch(kn, q[kBatch - 1]);
+            }
             int ic1[D];
             R off1[D];
             int t1 = -1;
@@ -717,21 +759,35 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                     wr = true;
                 }
             }
-            bool to_ovf = false;
-            if (active && !stay) {
-                const uint32_t b = __hip_atomic_fetch_add(cb_dst + t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t room = (int64_t)tcap[t1] - (int64_t)cf_src[t1] - (int64_t)cb_src[t1];
-                if ((int64_t)b < room) {
-                    opos = (uint32_t)(tstart[t1] + tcap[t1] - 1) - b;
-                    wr = true;
-                } else {
-                    to_ovf = true;
-                }
-            }
             uint32_t cpack = 0;
             if constexpr (sizeof(R) == 4) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) cpack |= (uint32_t)ic1[a] << csh[a];
+            }
+            // a mover of the previous iteration: its slot and its new bin's
+            // room arrived meanwhile
+            if (pm_valid) emit_mover();
+            pm_valid = false;
+            if (active && !stay) {
+                // reserve a slot at the back of the new tile's bin; the
+                // result is used one iteration later
+                pm_valid = true;
+                pm_slot = __hip_atomic_fetch_add(cb_dst + t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pm_room = tcap[t1] - (int32_t)cf_src[t1] - (int32_t)cb_src[t1];
+                pm_top = tstart[t1] + tcap[t1] - 1;
+                pm.c = cpack;
+#pragma unroll
+                for (int a = 0; a < D; ++a) pm.p[a] = sizeof(R) == 4 ? off1[a] : R((double)ic1[a] + off1[a]);
+                pm.u[0] = ux;
+                pm.u[1] = uy;
+                pm.u[2] = uz;
+                pm.id = pid;
+                // FP64: the pending state would cost occupancy (register
+                // file); store at once
+                if constexpr (sizeof(R) == 8) {
+                    emit_mover();
+                    pm_valid = false;
+                }
             }
             if (wr) {
                 if constexpr (sizeof(R) == 4) {
@@ -747,28 +803,9 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 st(ou2, opos, uz);
                 if (track) st(oid, opos, pid);
             }
-            if (to_ovf) {
-                // no room left in the new tile's bin: overflow list (set 2),
-                // re-laid out at the end of the step
-                const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
-                state->rebin = 1;
-                if (oi < S.ovf_cap) {
-                    if constexpr (sizeof(R) == 4) {
-                        gbl(S.cell[2])[oi] = cpack;
-                        for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = off1[a];
-                    } else {
-                        for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = (double)ic1[a] + off1[a];
-                    }
-                    gbl((R *)S.u[2][0])[oi] = ux;
-                    gbl((R *)S.u[2][1])[oi] = uy;
-                    gbl((R *)S.u[2][2])[oi] = uz;
-                    if (track) gbl(S.id[2])[oi] = pid;
-                } else {
-                    atomicOr(&state->fatal, 1);
-                }
-            }
             }
         }
+        if (pm_valid) emit_mover();
         if ((uint32_t)lane < qtail - qhead) drain((qhead + lane) & (kQueue - 1));
         __syncthreads();
         if (threadIdx.x == 0) S.cnt_front[dst * ntiles + tile] = s_front;
@@ -872,20 +909,28 @@ __device__ __forceinline__ void rebin_scan_body(const KParams *__restrict__ kp, 
     const int64_t m = min((int64_t)64, slack / (2 * (int64_t)ntiles));
     const int64_t rest = slack - m * ntiles;
     auto reserve = [&](int64_t c) { return m + (total > 0 ? (rest * c) / total : rest / ntiles); };
-    // pass 2: exclusive scan of count + reserve
+    // capacity: count + reserve, rounded to a multiple of kBinAlign particles
+    // (down, unless that would cut into the count) so that every bin starts
+    // on a cache-line boundary of each particle array
+    auto capacity = [&](int64_t c) {
+        const int64_t v = c + reserve(c);
+        return max((c + kBinAlign - 1) / kBinAlign * kBinAlign, v / kBinAlign * kBinAlign);
+    };
+    // pass 2: exclusive scan of the capacities
     local = 0;
-    for (int t = t0; t < t1; ++t) local += cnt[t] + reserve(cnt[t]);
+    for (int t = t0; t < t1; ++t) local += capacity(cnt[t]);
     __syncthreads();
     spart[threadIdx.x] = local;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t run = 0;
         for (int i = 0; i < 256; ++i) { const int64_t v = spart[i]; spart[i] = run; run += v; }
+        if (run > S.ncap) atomicOr(&st->fatal, 4);     // rounding left no room (tiny reserve)
     }
     __syncthreads();
     int64_t off = spart[threadIdx.x];
     for (int t = t0; t < t1; ++t) {
-        const int64_t c = cnt[t] + reserve(cnt[t]);
+        const int64_t c = capacity(cnt[t]);
         kp->rb_start[(int64_t)s * ntiles + t] = (int32_t)off;
         kp->rb_cap[(int64_t)s * ntiles + t] = (int32_t)c;
         off += c;

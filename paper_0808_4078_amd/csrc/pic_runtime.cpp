@@ -146,6 +146,8 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         P.tile_nominal = (int64_t)S.ppc * tile_cells;
         P.nominal = P.tile_nominal * G.ntiles;
         P.reserve = std::max<int64_t>(64, (int64_t)std::ceil(reserve * (double)P.tile_nominal));
+        // bins of kBinAlign-multiple capacity start on cache-line boundaries
+        P.reserve = (P.tile_nominal + P.reserve + kBinAlign - 1) / kBinAlign * kBinAlign - P.tile_nominal;
         P.ncap = (P.tile_nominal + P.reserve) * G.ntiles;
         if (P.ncap * (g->precision == PIC_PREC_MIXED ? 4 : 8) >= ((int64_t)1 << 32))
             return fail(err, PIC_E_UNSUPPORTED, "species %d: a particle array would exceed 4 GiB", s);
@@ -734,11 +736,17 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
     std::vector<uint32_t> front(nt);
     int64_t o = 0;
     for (int t = 0; t < nt; ++t) {
+        const int64_t c = count[t];
+        const int64_t v = c + m + (n > 0 ? rest * c / n : rest / nt);
+        // rounded to kBinAlign slots, as the device re-layout does
+        const int64_t cp = std::max((c + kBinAlign - 1) / kBinAlign * kBinAlign, v / kBinAlign * kBinAlign);
         start[t] = (int32_t)o;
-        cap[t] = (int32_t)(count[t] + m + (n > 0 ? rest * count[t] / n : rest / nt));
-        front[t] = (uint32_t)count[t];
-        o += cap[t];
+        cap[t] = (int32_t)cp;
+        front[t] = (uint32_t)c;
+        o += cp;
     }
+    if (o > P.ncap) return fail(&r->err, PIC_E_CAPACITY, "species %d: %lld particles do not fit the store", s,
+                                (long long)n);
     // Inside each tile, order by (rank of the particle within its cell, cell):
     // consecutive slots then hold particles of different cells, which keeps
     // the lanes of a wave off each other's LDS current words.
