@@ -106,7 +106,14 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, graph_steps=None):
+def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, profile: bool = True):
+    """Two fresh runs of the same workload.  Timed run: `warmup` untimed
+    steps, then exactly `steps` steps as enqueued by pic_step (one captured
+    graph replay per step), bracketed by device synchronisations and HIP
+    events on the run's stream.  Profiled run (if requested): the same steps
+    launched kernel by kernel with start/stop events on every dispatch,
+    which give the per-kernel-group times and the particle kernel's average
+    duration."""
     import torch
     from paper_0808_4078_amd import pic
 
@@ -119,48 +126,46 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     progress(f"{wl.name} {precision}: initialised {wl.particles} particles in {init_s:.2f} s")
     run.step(warmup)
     run.sync()
-    stream = run.stream
-    # timed region: K steps, each kernel launched with start/stop events that
-    # carry its dispatch's own execution interval
     torch.cuda.synchronize()
-    p0 = torch.cuda.Event(enable_timing=True)
-    p1 = torch.cuda.Event(enable_timing=True)
-    p0.record(stream)
-    groups = run.step_profiled(steps)
-    p1.record(stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(run.stream)
+    run.step(steps)
+    e1.record(run.stream)
     torch.cuda.synchronize()
-    prof_ms = p0.elapsed_time(p1)
-    diag = run.diagnostics()
-    n = int(sum(wl.cells * s.ppc for s in wl.species))
+    run.sync()
+    ms = e0.elapsed_time(e1)
+    diag = run.diagnostics() if diag_every else None
     device_bytes = run.device_bytes
     run.close()
     del run
     torch.cuda.empty_cache()
-    # the same steps replayed as captured graphs, from a fresh start (reported
-    # beside the timed region)
-    gsteps = steps if graph_steps is None else graph_steps
-    graph_ms = float("nan")
-    if gsteps > 0:
+    groups, prof_ms = None, None
+    if profile:
         run = pic.Run(g, sp)
         run.step(warmup)
         run.sync()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(run.stream)
-        run.step(gsteps)
-        e1.record(run.stream)
+        p0 = torch.cuda.Event(enable_timing=True)
+        p1 = torch.cuda.Event(enable_timing=True)
+        p0.record(run.stream)
+        groups = run.step_profiled(steps)
+        p1.record(run.stream)
         torch.cuda.synchronize()
-        run.sync()
-        graph_ms = e0.elapsed_time(e1) * steps / gsteps
+        prof_ms = p0.elapsed_time(p1)
         run.close()
         del run
         torch.cuda.empty_cache()
-    progress(f"{wl.name} {precision}: {steps} steps {prof_ms / steps:.3f} ms/step (timed, per-kernel events), "
-             f"{graph_ms / steps:.3f} ms/step (graph replay, fresh run); particle kernel "
-             f"{groups['particle'] / steps:.3f} ms; re-layouts {diag['rebins']}")
-    return dict(particles=n, init_s=init_s, graph_ms=graph_ms, profiled_ms=prof_ms, groups_ms=groups,
-                diag=diag, device_bytes=device_bytes)
+    n = int(wl.particles)
+    msg = f"{wl.name} {precision}: {steps} steps {ms / steps:.3f} ms/step"
+    if profile:
+        msg += (f" ({prof_ms / steps:.3f} ms/step launched kernel by kernel with events; particle kernel "
+                f"{groups['particle'] / steps:.3f} ms)")
+    if diag:
+        msg += f"; re-layouts {diag['rebins']}"
+    progress(msg)
+    return dict(particles=n, init_s=init_s, ms=ms, profiled_ms=prof_ms, groups_ms=groups, diag=diag,
+                device_bytes=device_bytes)
 
 
 def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
@@ -277,7 +282,7 @@ def main():
     fp64 = None if a.skip_fp64 else run_gpu(replace(wl, name="C2"), "fp64", a.steps, a.warmup, a.tile,
                                             a.diag_every)
     n = mixed["particles"]
-    ms_step = mixed["profiled_ms"] / a.steps
+    ms_step = mixed["ms"] / a.steps
     value = n / (ms_step * 1e-3)
     pk_ms = mixed["groups_ms"]["particle"] / a.steps
     pk_bytes = particle_kernel_bytes(wl, "mixed", a.tile)
@@ -309,12 +314,12 @@ def main():
                             "algorithmic_bytes": pk_bytes},
         "step_breakdown_ms": {k: v / a.steps for k, v in mixed["groups_ms"].items()},
         "relayouts": mixed["diag"]["rebins"],
-        "graph_replay_ms_per_step": mixed["graph_ms"] / a.steps,
+        "kernel_by_kernel_ms_per_step": mixed["profiled_ms"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if not a.quick else None},
     }
     if fp64 is not None:
-        f_ms = fp64["profiled_ms"] / a.steps
+        f_ms = fp64["ms"] / a.steps
         f_pk = fp64["groups_ms"]["particle"] / a.steps
         f_bytes = particle_kernel_bytes(wl, "fp64", a.tile)
         rec["fp64"] = {"workload": "C2 (same workload, FP64 throughout)", "value": n / (f_ms * 1e-3),
@@ -323,14 +328,14 @@ def main():
                        "step_breakdown_ms": {k: v / a.steps for k, v in fp64["groups_ms"].items()}}
         rec["mixed_over_fp64"] = rec["value"] / rec["fp64"]["value"]
     if a.c4 > 0:
-        c4 = run_gpu(synth.C4, "mixed", a.c4, min(a.warmup, 5), 8, a.diag_every, graph_steps=0)
+        c4 = run_gpu(synth.C4, "mixed", a.c4, min(a.warmup, 5), 8, a.diag_every)
         c4_pk = c4["groups_ms"]["particle"] / a.c4
         c4_bytes = particle_kernel_bytes(synth.C4, "mixed", 8)
         rec["c4"] = {"workload": "C4: 3D3V periodic 256x256x512, dx=0.2, dt=0.1, 8 ppc per species, beam "
                                  "gamma=3 u_th=0.1 + collisionless return-current plasma, mixed precision",
                      "particles": c4["particles"], "steps": a.c4,
-                     "value": c4["particles"] / (c4["profiled_ms"] / a.c4 * 1e-3),
-                     "ms_per_step": c4["profiled_ms"] / a.c4, "particle_kernel_ms": c4_pk,
+                     "value": c4["particles"] / (c4["ms"] / a.c4 * 1e-3),
+                     "ms_per_step": c4["ms"] / a.c4, "particle_kernel_ms": c4_pk,
                      "particle_kernel_GBs": c4_bytes / (c4_pk * 1e-3) / 1e9,
                      "step_breakdown_ms": {k: v / a.c4 for k, v in c4["groups_ms"].items()}}
     if a.c5 > 0:

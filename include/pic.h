@@ -223,6 +223,23 @@ int pic_write_fields(pic_run *run, const double *E, const double *B);
 int pic_read_particles(pic_run *run, int species, double *x, double *u, uint32_t *id,
                        int64_t cap, int64_t *count);
 
+/* Synchronising.  Writes the run's complete state -- particle store, fields,
+ * current, scratch (step counter, parity, work order), diagnostic ring --
+ * with its descriptors to the file `path` (overwritten).  The file holds the
+ * raw buffers (sizes as pic_query gives), so it is as large as the device
+ * state.  Errors: INVALID_ARG (null argument, file not writable),
+ * CAPACITY / HIP (as pic_sync). */
+int pic_checkpoint(pic_run *run, const char *path);
+
+/* Synchronising.  Replaces the run's state by the checkpoint in `path`.  The
+ * run must have been initialised with the same grid and species descriptors
+ * (flags that only steer initialisation -- HOST_LOAD, NO_GRAPH, LATTICE_LOAD
+ * -- may differ; pass PIC_FLAG_HOST_LOAD to skip the device loader of a run
+ * that is about to be restored).  Stepping then continues exactly where the
+ * checkpointed run stood.  Errors: INVALID_ARG (unreadable, foreign or
+ * truncated file), STATE (descriptors differ), HIP. */
+int pic_restore(pic_run *run, const char *path);
+
 /* Host only.  Frees the handle's host state (not the caller's buffers). */
 int pic_destroy(pic_run *run);
 

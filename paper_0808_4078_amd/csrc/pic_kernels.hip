@@ -937,15 +937,34 @@ __device__ __forceinline__ void rebin_scan_body(const KParams *__restrict__ kp, 
     }
 }
 
+// One particle's stored fields, for copies that load several particles
+// before storing any (the loads are then in flight together).
 template <typename R>
-__device__ __forceinline__ void copy_particle(const KParams *kp, const SpeciesDev &S, int from, int64_t a,
-                                              int to, int64_t b)
+struct StoredParticle {
+    uint32_t c;
+    R p[3];
+    R u[3];
+    uint32_t id;
+};
+template <typename R>
+__device__ __forceinline__ void load_stored(const SpeciesDev &S, int nd, int set, int64_t a, StoredParticle<R> &v)
 {
-    if constexpr (sizeof(R) == 4) S.cell[to][b] = S.cell[from][a];
-    for (int c = 0; c < kp->g.ndim; ++c) ((R *)S.pos[to][c])[b] = ((const R *)S.pos[from][c])[a];
-    for (int c = 0; c < 3; ++c) ((R *)S.u[to][c])[b] = ((const R *)S.u[from][c])[a];
-    if (S.track_id) S.id[to][b] = S.id[from][a];
+    if constexpr (sizeof(R) == 4) v.c = gbl(S.cell[set])[a];
+    for (int c = 0; c < 3; ++c)
+        if (c < nd) v.p[c] = gbl((const R *)S.pos[set][c])[a];
+    for (int c = 0; c < 3; ++c) v.u[c] = gbl((const R *)S.u[set][c])[a];
+    v.id = S.track_id ? gbl(S.id[set])[a] : 0u;
 }
+template <typename R>
+__device__ __forceinline__ void store_stored(const SpeciesDev &S, int nd, int set, int64_t b, const StoredParticle<R> &v)
+{
+    if constexpr (sizeof(R) == 4) gbl(S.cell[set])[b] = v.c;
+    for (int c = 0; c < 3; ++c)
+        if (c < nd) gbl((R *)S.pos[set][c])[b] = v.p[c];
+    for (int c = 0; c < 3; ++c) gbl((R *)S.u[set][c])[b] = v.u[c];
+    if (S.track_id) gbl(S.id[set])[b] = v.id;
+}
+constexpr int kCopyUnroll = 4;
 
 // copy each tile's valid bin contents dst -> src (blocks stride over (tile, species))
 template <typename R>
@@ -963,9 +982,19 @@ __device__ __forceinline__ void rebin_scatter_body(const KParams *__restrict__ k
         const int64_t vb = min((int64_t)S.cnt_back[dst * ntiles + t], room);
         const int64_t from0 = S.start[t], cap = S.cap[t];
         const int64_t to0 = kp->rb_start[(int64_t)s * ntiles + t];
-        for (int64_t k = threadIdx.x; k < nf + vb; k += blockDim.x) {
-            const int64_t a = k < nf ? from0 + k : from0 + cap - vb + (k - nf);
-            copy_particle<R>(kp, S, dst, a, src, to0 + k);
+        const int nd = kp->g.ndim;
+        for (int64_t k0 = threadIdx.x; k0 < nf + vb; k0 += kCopyUnroll * (int64_t)blockDim.x) {
+            StoredParticle<R> v[kCopyUnroll];
+#pragma unroll
+            for (int u = 0; u < kCopyUnroll; ++u) {
+                const int64_t k = k0 + u * (int64_t)blockDim.x;
+                if (k < nf + vb) load_stored<R>(S, nd, dst, k < nf ? from0 + k : from0 + cap - vb + (k - nf), v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kCopyUnroll; ++u) {
+                const int64_t k = k0 + u * (int64_t)blockDim.x;
+                if (k < nf + vb) store_stored<R>(S, nd, src, to0 + k, v[u]);
+            }
         }
     }
 }
@@ -983,7 +1012,9 @@ __device__ __forceinline__ void rebin_scatter_ovf_body(const KParams *__restrict
         for (int64_t p = i; p < n; p += (int64_t)nb * blockDim.x) {
             const int64_t idx = (int64_t)s * kp->g.ntiles + tile_of<R>(kp, S, 2, p);
             const int32_t slot = atomicAdd(&kp->rb_fill[idx], 1);
-            copy_particle<R>(kp, S, 2, p, src, (int64_t)kp->rb_start[idx] + slot);
+            StoredParticle<R> v;
+            load_stored<R>(S, kp->g.ndim, 2, p, v);
+            store_stored<R>(S, kp->g.ndim, src, (int64_t)kp->rb_start[idx] + slot, v);
         }
     }
 }

@@ -985,6 +985,130 @@ int pic_destroy(pic_run *r)
 }
 
 // ---------------------------------------------------------------------------
+// Checkpoint / restore: a header (magic, version, descriptors, buffer sizes)
+// followed by the raw contents of the four caller buffers, copied through a
+// host staging buffer.
+
+namespace {
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 1;
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t nspecies;
+    pic_grid_desc grid;
+    pic_species_desc species[kMaxSpecies];
+    uint64_t bytes[kMaxSpecies + 3];   // particle buffers, fields, scratch, diag
+};
+constexpr size_t kStage = size_t(64) << 20;
+
+int ckpt_buffers(const pic_run *r, void *ptr[kMaxSpecies + 3], uint64_t bytes[kMaxSpecies + 3])
+{
+    for (int i = 0; i < kMaxSpecies + 3; ++i) {
+        ptr[i] = nullptr;
+        bytes[i] = 0;
+    }
+    for (int s = 0; s < r->ns; ++s) {
+        ptr[s] = r->buf.particles[s];
+        bytes[s] = r->L.particle_bytes[s];
+    }
+    ptr[kMaxSpecies] = r->buf.fields;
+    bytes[kMaxSpecies] = r->L.field_bytes;
+    ptr[kMaxSpecies + 1] = r->buf.scratch;
+    bytes[kMaxSpecies + 1] = r->L.scratch_bytes;
+    ptr[kMaxSpecies + 2] = r->buf.diag;
+    bytes[kMaxSpecies + 2] = r->L.diag_bytes;
+    return PIC_OK;
+}
+}  // namespace
+
+int pic_checkpoint(pic_run *r, const char *path)
+{
+    if (!r || !path) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "null argument");
+    DevState st;
+    int rc = read_state(r, &st);
+    if (rc) return rc;
+    rc = check_fatal(r, st);
+    if (rc) return rc;
+    CkptHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kCkptMagic, sizeof(h.magic));
+    h.version = kCkptVersion;
+    h.nspecies = r->ns;
+    h.grid = r->grid;
+    for (int s = 0; s < r->ns; ++s) h.species[s] = r->species[s];
+    void *ptr[kMaxSpecies + 3];
+    ckpt_buffers(r, ptr, h.bytes);
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(&r->err, PIC_E_INVALID_ARG, "cannot open %s for writing", path);
+    std::vector<char> stage(kStage);
+    bool ok = fwrite(&h, sizeof(h), 1, f) == 1;
+    for (int i = 0; ok && i < kMaxSpecies + 3; ++i)
+        for (uint64_t o = 0; ok && o < h.bytes[i]; o += kStage) {
+            const size_t n = (size_t)std::min<uint64_t>(kStage, h.bytes[i] - o);
+            if (hipMemcpy(stage.data(), (char *)ptr[i] + o, n, hipMemcpyDeviceToHost) != hipSuccess) {
+                fclose(f);
+                return hip_fail(r, hipGetLastError(), "checkpoint copy");
+            }
+            ok = fwrite(stage.data(), 1, n, f) == n;
+        }
+    if (fclose(f) != 0) ok = false;
+    if (!ok) return fail(&r->err, PIC_E_INVALID_ARG, "short write to %s", path);
+    return PIC_OK;
+}
+
+int pic_restore(pic_run *r, const char *path)
+{
+    if (!r || !path) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "null argument");
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(&r->err, PIC_E_INVALID_ARG, "cannot open %s", path);
+    CkptHeader h;
+    if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, kCkptMagic, sizeof(h.magic)) != 0 ||
+        h.version != kCkptVersion) {
+        fclose(f);
+        return fail(&r->err, PIC_E_INVALID_ARG, "%s is not a checkpoint of this library version", path);
+    }
+    // the checkpoint must come from a run with the same descriptors
+    pic_grid_desc g0 = r->grid, g1 = h.grid;
+    bool same = h.nspecies == r->ns;
+    // flags that only steer initialisation or launching may differ
+    const uint32_t init_only = PIC_FLAG_HOST_LOAD | PIC_FLAG_NO_GRAPH | PIC_FLAG_LATTICE_LOAD;
+    g0.flags &= ~init_only;
+    g1.flags &= ~init_only;
+    same = same && memcmp(&g0, &g1, sizeof(g0)) == 0;
+    for (int s = 0; same && s < r->ns; ++s) same = memcmp(&h.species[s], &r->species[s], sizeof(pic_species_desc)) == 0;
+    void *ptr[kMaxSpecies + 3];
+    uint64_t bytes[kMaxSpecies + 3];
+    ckpt_buffers(r, ptr, bytes);
+    for (int i = 0; same && i < kMaxSpecies + 3; ++i) same = bytes[i] == h.bytes[i];
+    if (!same) {
+        fclose(f);
+        return fail(&r->err, PIC_E_STATE, "%s was written by a run with other descriptors", path);
+    }
+    std::vector<char> stage(kStage);
+    bool ok = true;
+    for (int i = 0; ok && i < kMaxSpecies + 3; ++i)
+        for (uint64_t o = 0; ok && o < h.bytes[i]; o += kStage) {
+            const size_t n = (size_t)std::min<uint64_t>(kStage, h.bytes[i] - o);
+            ok = fread(stage.data(), 1, n, f) == n;
+            if (ok && hipMemcpy((char *)ptr[i] + o, stage.data(), n, hipMemcpyHostToDevice) != hipSuccess) {
+                fclose(f);
+                return hip_fail(r, hipGetLastError(), "restore copy");
+            }
+        }
+    fclose(f);
+    if (!ok) return fail(&r->err, PIC_E_INVALID_ARG, "%s is truncated", path);
+    // the parameter block holds this run's device addresses
+    HIPCHK(r, hipMemcpy(r->dp, &r->hp, sizeof(KParams), hipMemcpyHostToDevice));
+    DevState st;
+    int rc = read_state(r, &st);
+    if (rc) return rc;
+    r->steps_enqueued = st.step;
+    return check_fatal(r, st);
+}
+
+// ---------------------------------------------------------------------------
 // Ensembles
 
 int pic_batch_query(int nruns, pic_run *const *runs, size_t *table_bytes)

@@ -78,7 +78,7 @@ EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
            "pic_status_string", "pic_last_error", "pic_batch_query", "pic_batch_init", "pic_batch_step",
            "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_destroy", "pic_tune_query",
-           "pic_tune"]
+           "pic_tune", "pic_checkpoint", "pic_restore"]
 
 
 def lib():
@@ -110,6 +110,8 @@ def lib():
         L.pic_write_fields.argtypes = [vp, vp, vp]
         L.pic_read_particles.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int64, P(C.c_int64)]
         L.pic_destroy.argtypes = [vp]
+        L.pic_checkpoint.argtypes = [vp, C.c_char_p]
+        L.pic_restore.argtypes = [vp, C.c_char_p]
         L.pic_status_string.argtypes = [C.c_int]
         L.pic_status_string.restype = C.c_char_p
         L.pic_last_error.argtypes = [vp, C.c_char_p, C.c_size_t]
@@ -308,6 +310,12 @@ class Run:
                 raise ValueError(f"field array shape {a.shape}, expected {shp}")
         _check(lib().pic_write_fields(self.h, _ptr(Ep) if Ep is not None else None,
                                       _ptr(Bp) if Bp is not None else None), "pic_write_fields", self.h)
+
+    def checkpoint(self, path: str):
+        _check(lib().pic_checkpoint(self.h, os.fsencode(path)), "pic_checkpoint", self.h)
+
+    def restore(self, path: str):
+        _check(lib().pic_restore(self.h, os.fsencode(path)), "pic_restore", self.h)
 
     def read_particles(self, s: int):
         cnt = C.c_int64()

@@ -126,3 +126,10 @@ def test_batch_and_tuner_queries_validate_on_the_host():
     ms = (C.c_double * 3)()
     g, sp = pic.workload_descs(synth.C1)
     assert L.pic_tune(C.byref(g), sp, len(sp), 1, None, 0, None, 4, C.byref(best), ms) == -1
+
+
+def test_checkpoint_entry_points_reject_null_handles(tmp_path):
+    L = pic.lib()
+    p = str(tmp_path / "x.ckpt").encode()
+    assert L.pic_checkpoint(None, p) == -1
+    assert L.pic_restore(None, p) == -1
