@@ -379,6 +379,11 @@ constexpr int kOrderBuckets = 64;
 constexpr int kAdvanceThreads = 256;     // workgroup size of the end-of-step kernel
 constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with its own L2
 
+// Movers staged per wave in mixed mode before they are written, grouped by
+// destination tile (FP64 writes each mover at once: 1 entry).
+template <typename R, int D>
+constexpr int kMoverStage = sizeof(R) == 4 ? (D == 3 ? 32 : 64) : 1;
+
 constexpr int kBatch = 2;   // particles each lane keeps in flight ahead of the one it processes
 
 // KP: pointer to the run's parameters -- the kernel argument, or (batched
@@ -396,6 +401,11 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
     __shared__ A sJ[3 * NJ_D];
     __shared__ int sQc[kBlock / 64][kQueue];             // crossing-particle ring per wave
     __shared__ R sQv[kBlock / 64][2 * D + 1][kQueue];
+    // movers staged per wave (mixed mode): destination tile and stored words
+    constexpr int MS = kMoverStage<R, D>;
+    constexpr int MW = D + 5;                            // cell, offsets, momenta, id
+    __shared__ int sMt[kBlock / 64][MS];
+    __shared__ uint32_t sMw[kBlock / 64][MW][MS];
     __shared__ uint32_t s_front;
     __shared__ double sred[kBlock / 64][kTileDiag];
 
@@ -525,42 +535,90 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             }
             deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, sQv[wave][2 * D][e]);
         };
-        // A particle that leaves the tile (mover) reserves its slot at the
-        // back of the new tile's bin with a returning atomic; in mixed mode
-        // the slot, and the room left in that bin, are used one iteration
-        // later, so the round trip overlaps the next particle's work.  Store layout of the
-        // pending mover: packed cell (mixed), position per resolved axis
-        // (offset in mixed mode, cell + offset in FP64), momenta, id.
-        bool pm_valid = false;
-        uint32_t pm_slot = 0;
-        int32_t pm_room = 0, pm_top = 0;
-        Raw pm;
-        auto emit_mover = [&]() {
-            if ((int64_t)pm_slot < (int64_t)pm_room) {
-                const uint32_t o = (uint32_t)pm_top - pm_slot;
-                if constexpr (sizeof(R) == 4) st(ocell, o, pm.c);
+        // A particle that leaves the tile (mover) is written at the back of
+        // its new tile's bin, in a slot reserved with a global atomic above
+        // that tile's start-of-step count.  In mixed mode the movers of a
+        // wave are first staged in LDS; a flush groups them by destination,
+        // takes one atomic per destination and writes each destination's
+        // movers to consecutive slots, so their stores are contiguous runs
+        // rather than scattered words, and the atomic round trip is paid
+        // once per flush.  FP64 writes each mover at once (the stage would
+        // cost occupancy).
+        auto emit_mover = [&](uint32_t slot, int32_t room, int32_t top, const Raw &m) {
+            if ((int64_t)slot < (int64_t)room) {
+                const uint32_t o = (uint32_t)top - slot;
+                if constexpr (sizeof(R) == 4) st(ocell, o, m.c);
 #pragma unroll
-                for (int a = 0; a < D; ++a) st(opos_a[a], o, pm.p[a]);
-                st(ou0, o, pm.u[0]);
-                st(ou1, o, pm.u[1]);
-                st(ou2, o, pm.u[2]);
-                if (track) st(oid, o, pm.id);
+                for (int a = 0; a < D; ++a) st(opos_a[a], o, m.p[a]);
+                st(ou0, o, m.u[0]);
+                st(ou1, o, m.u[1]);
+                st(ou2, o, m.u[2]);
+                if (track) st(oid, o, m.id);
             } else {
                 // no room left in the new tile's bin: overflow list (set 2),
                 // re-laid out at the end of the step
                 const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
                 state->rebin = 1;
                 if (oi < S.ovf_cap) {
-                    if constexpr (sizeof(R) == 4) gbl(S.cell[2])[oi] = pm.c;
-                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = pm.p[a];
-                    gbl((R *)S.u[2][0])[oi] = pm.u[0];
-                    gbl((R *)S.u[2][1])[oi] = pm.u[1];
-                    gbl((R *)S.u[2][2])[oi] = pm.u[2];
-                    if (track) gbl(S.id[2])[oi] = pm.id;
+                    if constexpr (sizeof(R) == 4) gbl(S.cell[2])[oi] = m.c;
+                    for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = m.p[a];
+                    gbl((R *)S.u[2][0])[oi] = m.u[0];
+                    gbl((R *)S.u[2][1])[oi] = m.u[1];
+                    gbl((R *)S.u[2][2])[oi] = m.u[2];
+                    if (track) gbl(S.id[2])[oi] = m.id;
                 } else {
                     atomicOr(&state->fatal, 1);
                 }
             }
+        };
+        // reserve one slot in tile t and write m there (unstaged path)
+        auto emit_now = [&](int t, const Raw &m) {
+            const uint32_t slot = __hip_atomic_fetch_add(cb_dst + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            emit_mover(slot, tcap[t] - (int32_t)cf_src[t] - (int32_t)cb_src[t], tstart[t] + tcap[t] - 1, m);
+        };
+        uint32_t mv_n = 0;                                   // staged movers of this wave (uniform)
+        auto flush_movers = [&]() {
+            __builtin_amdgcn_wave_barrier();
+            const bool valid = (uint32_t)lane < mv_n;
+            const int td = valid ? sMt[wave][lane] : -1;
+            uint64_t rem = __ballot(valid);
+            int leader = 0;
+            uint32_t rank = 0, lead_cnt = 0;
+            while (rem) {                                    // one pass per distinct destination
+                const int l = __ffsll((unsigned long long)rem) - 1;
+                const int tl = __builtin_amdgcn_readlane(td, l);
+                const bool mine = valid && td == tl;
+                const uint64_t same = __ballot(mine);
+                if (mine) {
+                    leader = l;
+                    rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+                }
+                if (lane == l) lead_cnt = (uint32_t)__popcll(same);
+                rem &= ~same;
+            }
+            uint32_t b0 = 0;
+            int32_t room = 0, top = 0;
+            if (valid && lane == leader) {
+                b0 = __hip_atomic_fetch_add(cb_dst + td, lead_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                room = tcap[td] - (int32_t)cf_src[td] - (int32_t)cb_src[td];
+                top = tstart[td] + tcap[td] - 1;
+            }
+            b0 = (uint32_t)__shfl((int)b0, leader, 64);
+            room = __shfl(room, leader, 64);
+            top = __shfl(top, leader, 64);
+            if (valid) {
+                Raw m;
+                m.c = sMw[wave][0][lane];
+#pragma unroll
+                for (int a = 0; a < D; ++a) m.p[a] = __uint_as_float(sMw[wave][1 + a][lane]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) m.u[c] = __uint_as_float(sMw[wave][1 + D + c][lane]);
+                m.id = sMw[wave][4 + D][lane];
+                emit_mover(b0 + rank, room, top, m);
+            }
+            __builtin_amdgcn_wave_barrier();
+            mv_n = 0;
         };
         Raw q[kBatch];
 #pragma unroll
@@ -764,29 +822,51 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
 #pragma unroll
                 for (int a = 0; a < D; ++a) cpack |= (uint32_t)ic1[a] << csh[a];
             }
-            // a mover of the previous iteration: its slot and its new bin's
-            // room arrived meanwhile
-            if (pm_valid) emit_mover();
-            pm_valid = false;
-            if (active && !stay) {
-                // reserve a slot at the back of the new tile's bin; the
-                // result is used one iteration later
-                pm_valid = true;
-                pm_slot = __hip_atomic_fetch_add(cb_dst + t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                pm_room = tcap[t1] - (int32_t)cf_src[t1] - (int32_t)cb_src[t1];
-                pm_top = tstart[t1] + tcap[t1] - 1;
-                pm.c = cpack;
+            {
+                const bool mover = active && !stay;
+                if constexpr (MS > 1) {
+                    const uint64_t mm = __ballot(mover);
+                    if (mm) {
+                        const uint32_t inc = (uint32_t)__popcll(mm);
+                        if (mv_n + inc > (uint32_t)MS) flush_movers();
+                        if (inc <= (uint32_t)MS) {
+                            if (mover) {
+                                const uint32_t e = mv_n + __builtin_amdgcn_mbcnt_hi(
+                                                              (uint32_t)(mm >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                                sMt[wave][e] = t1;
+                                sMw[wave][0][e] = cpack;
 #pragma unroll
-                for (int a = 0; a < D; ++a) pm.p[a] = sizeof(R) == 4 ? off1[a] : R((double)ic1[a] + off1[a]);
-                pm.u[0] = ux;
-                pm.u[1] = uy;
-                pm.u[2] = uz;
-                pm.id = pid;
-                // FP64: the pending state would cost occupancy (register
-                // file); store at once
-                if constexpr (sizeof(R) == 8) {
-                    emit_mover();
-                    pm_valid = false;
+                                for (int a = 0; a < D; ++a) sMw[wave][1 + a][e] = __float_as_uint((float)off1[a]);
+                                sMw[wave][1 + D][e] = __float_as_uint((float)ux);
+                                sMw[wave][2 + D][e] = __float_as_uint((float)uy);
+                                sMw[wave][3 + D][e] = __float_as_uint((float)uz);
+                                sMw[wave][4 + D][e] = pid;
+                            }
+                            mv_n += inc;
+                        } else if (mover) {
+                            // more movers than the stage holds (3D): unstaged
+                            Raw m;
+                            m.c = cpack;
+#pragma unroll
+                            for (int a = 0; a < D; ++a) m.p[a] = off1[a];
+                            m.u[0] = ux;
+                            m.u[1] = uy;
+                            m.u[2] = uz;
+                            m.id = pid;
+                            emit_now(t1, m);
+                        }
+                    }
+                } else if (mover) {
+                    Raw m;
+                    m.c = cpack;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) m.p[a] = R((double)ic1[a] + off1[a]);
+                    m.u[0] = ux;
+                    m.u[1] = uy;
+                    m.u[2] = uz;
+                    m.id = pid;
+                    emit_now(t1, m);
                 }
             }
             if (wr) {
@@ -805,7 +885,9 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             }
             }
         }
-        if (pm_valid) emit_mover();
+        if constexpr (MS > 1) {
+            if (mv_n) flush_movers();
+        }
         if ((uint32_t)lane < qtail - qhead) drain((qhead + lane) & (kQueue - 1));
         __syncthreads();
         if (threadIdx.x == 0) S.cnt_front[dst * ntiles + tile] = s_front;
