@@ -86,8 +86,9 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     Every particle's state is read once and written once:
       mixed: int32 cell + one FP32 offset per resolved axis + 3 FP32 momenta
              (2D: 24 B, 3D: 28 B);
-      FP64:  one FP64 position per resolved axis + 3 FP64 momenta (2D: 40 B).
-    Collisional particles also read their 4-byte id, which keys their draw.
+      FP64:  one FP64 position per resolved axis + 3 FP64 momenta (2D: 40 B);
+    a collisional particle's state also holds its 4-byte id, which keys its
+    scattering draw and therefore travels with it (read and written).
     Each tile stages E and B on (T+2)^D nodes and writes its partial current on
     (T+3)^D nodes."""
     r = 4 if precision == "mixed" else 8
@@ -96,7 +97,7 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     total = 0.0
     for sc in wl.species:
         n = wl.cells * sc.ppc
-        total += n * 2 * state + (n * 4 if sc.nu > 0 else 0)
+        total += n * 2 * (state + (4 if sc.nu > 0 else 0))
     tiles = wl.cells // tile ** d
     total += tiles * (6 * (tile + 2) ** d * r + 3 * (tile + 3) ** d * r)
     return total
