@@ -47,6 +47,54 @@ def weibel_cold_rate(k: float, species) -> float:
     return math.sqrt(-min(neg))
 
 
+# ---------------------------------------------------------------------------
+# The paper's warm-beam filamentation dispersion with a resistive return
+# current (Eq. 12), in units of w_p and c/w_p (so k_pe = 1 for the ambient
+# plasma):
+#   omega^2 = c_s^2 k^2 - wb2b2 k^2 / (k^2 + kpe2 / (1 + i nu / omega)),
+# with c_s^2 the beam's sound speed squared and wb2b2 = omega_b^2 beta_0^2.
+# Writing 1/(1 + i nu/omega) = omega/(omega + i nu) and multiplying by
+# (omega + i nu)(k^2 + ...) gives the cubic
+#   (omega^2 - c_s^2 k^2) ((k^2 + kpe2) omega + i nu k^2)
+#       + wb2b2 k^2 (omega + i nu) = 0 .
+# With nu = 0 its roots are omega = 0 and omega^2 = c_s^2 k^2 -
+# wb2b2 k^2/(k^2 + kpe2); for a warm beam (c_s^2 > wb2b2/kpe2) none grows.
+# For small nu and k^2 << kpe2 the growing root tends to Eq. (14),
+#   omega = i nu wb2b2 / (kpe2 c_s^2 - wb2b2).
+def warm_beam_roots(k: float, cs2: float, wb2b2: float, nu: float, kpe2: float = 1.0) -> np.ndarray:
+    """The three roots omega (complex, 1/w_p) of the cubic form of Eq. (12)."""
+    k2 = k * k
+    s = cs2 * k2
+    g = wb2b2 * k2
+    a = k2 + kpe2
+    b = 1j * nu * k2
+    return np.roots([a, b, g - s * a, -s * b + 1j * g * nu])
+
+
+def warm_beam_growth(k: float, cs2: float, wb2b2: float, nu: float, kpe2: float = 1.0) -> float:
+    """Largest imaginary part of the roots of Eq. (12) (0 if none grows)."""
+    return max(0.0, float(np.max(warm_beam_roots(k, cs2, wb2b2, nu, kpe2).imag)))
+
+
+def warm_beam_growth_long_wave(cs2: float, wb2b2: float, nu: float, kpe2: float = 1.0) -> float:
+    """Eq. (14): the collision-driven growth rate of a warm beam at long
+    wavelength, nu wb2b2 / (kpe2 c_s^2 - wb2b2) (positive modified sound
+    speed assumed)."""
+    return nu * wb2b2 / (kpe2 * cs2 - wb2b2)
+
+
+def paper_case_parameters(v_b: float = 0.9, n_b: float = 0.1, u_th: float = 0.37):
+    """(c_s^2, wb2b2) of the paper's 2D beam for Eq. (12), with the
+    relativistic transverse inertia gamma_b m: the beam's transverse thermal
+    velocity is u_th/gamma_b, c_s^2 = 3 (u_th/gamma_b)^2 (the text's
+    c_s^2 = 3 v_th^2), omega_b^2 = n_b/(gamma_b n0) and beta_0 = v_b (the
+    text's approximation of v_bz - v_pz)."""
+    gamma_b = 1.0 / math.sqrt(1.0 - v_b * v_b)
+    cs2 = 3.0 * (u_th / gamma_b) ** 2
+    wb2b2 = n_b / gamma_b * v_b * v_b
+    return cs2, wb2b2
+
+
 def beam_plasma_species(n_b=0.1, u_beam=math.sqrt(8.0)):
     """Cold beam and the cold return current that cancels it."""
     v_b = u_beam / math.sqrt(1 + u_beam ** 2)

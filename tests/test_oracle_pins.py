@@ -468,3 +468,34 @@ def test_synthetic_load_properties():
     ids = np.concatenate([p.id for p in parts])
     assert len(np.unique(ids)) == len(ids)
     assert abs(parts[1].u[2].mean() - synth.cold_return_drift()) < 0.01
+
+
+def test_warm_beam_dispersion_limits():
+    """Eq. (12) as a cubic: with nu = 0 it reduces to the closed form
+    omega^2 = c_s^2 k^2 - wb2b2 k^2/(k^2 + 1) (and omega = 0), no root grows
+    for a warm beam; for small nu and small k the growing root tends to
+    Eq. (14); a cold beam (c_s = 0) grows without collisions."""
+    from oracle import theory
+    cs2, wb2b2 = 0.08, 0.035
+    for k in (0.1, 0.5, 1.0, 3.0):
+        r = np.sort_complex(theory.warm_beam_roots(k, cs2, wb2b2, 0.0))
+        w2 = cs2 * k * k - wb2b2 * k * k / (k * k + 1.0)
+        want = np.sort_complex(np.array([-math.sqrt(w2), 0.0, math.sqrt(w2)], dtype=complex))
+        assert np.max(np.abs(r - want)) < 1e-10
+        assert theory.warm_beam_growth(k, cs2, wb2b2, 0.0) < 1e-10
+    # Eq. (14) needs nu << (modified sound speed) k << k_pe: the ratio tends
+    # to 1 as nu and k shrink in that order
+    nu = 1e-4
+    g0 = theory.warm_beam_growth_long_wave(cs2, wb2b2, nu)
+    assert abs(theory.warm_beam_growth(0.01, cs2, wb2b2, nu) / g0 - 1.0) < 3e-3
+    assert abs(theory.warm_beam_growth(0.003, cs2, wb2b2, 1e-5) / (g0 / 10) - 1.0) < 1e-3
+    # cold beam, collisionless: omega^2 = -wb2b2 k^2/(k^2+1)
+    k = 2.0
+    assert abs(theory.warm_beam_growth(k, 0.0, wb2b2, 0.0) - math.sqrt(wb2b2 * k * k / (k * k + 1.0))) < 1e-10
+    # the paper's hot beam (u_th 0.37, v_b 0.9, n_b 0.1): stable without
+    # collisions, growing with nu = 0.15
+    cs2p, wbp = theory.paper_case_parameters()
+    assert cs2p > wbp
+    ks = np.linspace(0.05, 6.0, 120)
+    assert max(theory.warm_beam_growth(kk, cs2p, wbp, 0.0) for kk in ks) < 1e-10
+    assert max(theory.warm_beam_growth(kk, cs2p, wbp, 0.15) for kk in ks) > 0.04
