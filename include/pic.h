@@ -52,6 +52,12 @@ enum {
 
 enum { PIC_PREC_FP64 = 0, PIC_PREC_MIXED = 1 };
 
+/* Scattering models of a collisional species (pic_species_desc.coll_model). */
+enum {
+    PIC_COLL_ISOTROPIC = 0,  /* isotropic scattering at the fixed rate nu_coll (default) */
+    PIC_COLL_COULOMB = 1     /* Coulomb small-angle scattering, rate nu_coll at speed coll_vref */
+};
+
 enum {
     PIC_FLAG_FREEZE_FIELDS = 1u,  /* skip current reduction and field update (test-particle mode) */
     PIC_FLAG_NO_COLLIDE = 2u,     /* ignore every species' collision rate */
@@ -114,8 +120,18 @@ typedef struct {
  *   cancel_current_of   device loader: shift this species' u_z so the total
  *                       current sum q w u_z/gamma of all species is zero
  *                       (the return current neutralising the beam); -1 = no.
- *   nu_coll             scattering rate off the ions in w_p (0 = collisionless):
- *                       probability 1 - exp(-nu dt) per step, isotropic, |u| kept. */
+ *   nu_coll             scattering rate off the ions in w_p (0 = collisionless).
+ *   coll_model          PIC_COLL_ISOTROPIC: with probability 1 - exp(-nu dt) per
+ *                       step the particle takes an isotropic direction, |u| kept
+ *                       (the drag term of Eq. (3) in the fluid limit).
+ *                       PIC_COLL_COULOMB: binary Coulomb collisions with the
+ *                       immobile ions (Takizuka-Abe small-angle form, ion mass
+ *                       infinite): every step the particle turns by theta,
+ *                       tan(theta/2) ~ N(0, nu_m(v) dt / 2), uniform azimuth, |u|
+ *                       kept, with momentum-transfer rate nu_m(v) =
+ *                       nu_coll (coll_vref / v)^3 (v = |u|/gamma).
+ *   coll_vref           reference speed of PIC_COLL_COULOMB in c (> 0 when
+ *                       nu_coll > 0); ignored otherwise. */
 typedef struct {
     double charge, mass, density;
     int32_t ppc;
@@ -123,6 +139,8 @@ typedef struct {
     double u_th;
     int32_t cancel_current_of;
     double nu_coll;
+    int32_t coll_model;
+    double coll_vref;
 } pic_species_desc;
 
 /* Sizes in bytes of the caller-owned device buffers. */

@@ -43,7 +43,7 @@ class _Grid(C.Structure):
 class _Species(C.Structure):
     _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double), ("nu", C.c_double),
                 ("n", C.c_int64), ("x", C.POINTER(C.c_double) * 3), ("u", C.POINTER(C.c_double) * 3),
-                ("id", C.POINTER(C.c_uint32))]
+                ("id", C.POINTER(C.c_uint32)), ("model", C.c_int), ("vref", C.c_double)]
 
 
 class _Diag(C.Structure):
@@ -73,6 +73,9 @@ def lib():
         L.orc_collision_threshold.restype = C.c_uint32
         L.orc_collide.argtypes = [dp, C.c_uint32, C.c_int64, C.c_uint64, C.c_uint32, C.c_uint32]
         L.orc_collide.restype = C.c_int
+        L.orc_coulomb.argtypes = [dp, C.c_uint32, C.c_int64, C.c_uint64, C.c_uint32, C.c_double, C.c_double,
+                                  C.c_double]
+        L.orc_coulomb.restype = C.c_int
         L.orc_yee_b.argtypes = [P(_Grid), C.c_double]
         L.orc_yee_e.argtypes = [P(_Grid)]
         L.orc_field_energy.argtypes = [P(_Grid), dp]
@@ -124,6 +127,14 @@ def collide(u, pid: int, step: int, seed: int, run: int, thr: int):
     return uu, bool(hit)
 
 
+def coulomb(u, pid: int, step: int, seed: int, run: int, nu: float, vref: float, dt: float):
+    """Apply one step of Coulomb small-angle scattering off the ions to one
+    momentum; returns (u_new, turned)."""
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    hit = lib().orc_coulomb(_dp(uu), pid, step, seed, run, nu, vref, dt)
+    return uu, bool(hit)
+
+
 def boris(u, E, B, qmdt2: float) -> np.ndarray:
     uu = np.ascontiguousarray(u, dtype=np.float64).copy()
     e = np.ascontiguousarray(E, dtype=np.float64)
@@ -142,6 +153,8 @@ class SpeciesState:
     x: np.ndarray          # (ndim, N)
     u: np.ndarray          # (3, N)
     id: np.ndarray         # (N,) uint32
+    model: int = 0         # 0: isotropic scattering at rate nu; 1: Coulomb small-angle, nu at speed vref
+    vref: float = 0.0
 
     @property
     def n(self) -> int:
@@ -192,6 +205,8 @@ def _cspecies(sp: list[SpeciesState], ndim: int):
             c.x[a] = _dp(s.x[a]) if a < ndim else C.POINTER(C.c_double)()
             c.u[a] = _dp(s.u[a])
         c.id = s.id.ctypes.data_as(C.POINTER(C.c_uint32))
+        c.model = int(s.model)
+        c.vref = float(s.vref)
     return arr
 
 

@@ -69,6 +69,10 @@ typedef struct {
     double *x[3];         /* positions in c/w_p (x[2] unused in 2D) */
     double *u[3];         /* momenta gamma v / c */
     const uint32_t *id;   /* particle identity, keys the collision draw */
+    int model;            /* 0: isotropic scattering at the fixed rate nu;
+                             1: Coulomb small-angle scattering, momentum-transfer
+                                rate nu at speed vref, scaling as v^-3 */
+    double vref;          /* reference speed of model 1, units of c */
 } orc_species;
 
 typedef struct {
@@ -287,6 +291,48 @@ uint32_t orc_collision_key(uint64_t seed, uint32_t run)
 {
     return (uint32_t)seed ^ ((uint32_t)(seed >> 32) * 0x9E3779B9u) ^ (run * 0x85EBCA6Bu);
 }
+/* Coulomb small-angle scattering off the immobile ions (Takizuka & Abe
+ * 1977, binary collision of an electron with an ion of infinite mass): in a
+ * step every electron turns by theta with tan(theta/2) = delta, delta normal
+ * with variance nu_m(v) dt / 2, where nu_m(v) = nu (vref/v)^3 is the
+ * momentum-transfer rate at speed v = |u|/gamma; the azimuth phi is uniform
+ * and |u| is kept.  The draw is Philox4x32-10 on counter (id, step, 3, run),
+ * key (seed lo, seed hi): delta = sqrt(var) sqrt(-2 ln U0) cos(2 pi U1),
+ * phi = 2 pi U2.  The new momentum follows Takizuka and Abe's rotation of u
+ * about itself (u along z when its transverse part is zero).  Returns 1 if
+ * the particle turned (u != 0).                                           */
+int orc_coulomb(double u[3], uint32_t id, int64_t step, uint64_t seed, uint32_t run, double nu, double vref,
+                double dt)
+{
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (!(u2 > 0.0) || !(nu > 0.0)) return 0;
+    uint32_t ctr[4] = {id, (uint32_t)step, 3u, run};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    const double U = sqrt(u2);
+    const double v = U / sqrt(1.0 + u2);
+    const double var = 0.5 * nu * dt * (vref / v) * (vref / v) * (vref / v);
+    const double delta = sqrt(var) * sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
+    const double d2 = delta * delta;
+    const double ct = (1.0 - d2) / (1.0 + d2), st = 2.0 * delta / (1.0 + d2);
+    const double ph = 2.0 * M_PI * u01(r[2]);
+    const double cp = cos(ph), sp = sin(ph);
+    const double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+    double du[3];
+    if (up > 0.0) {
+        du[0] = (u[0] * u[2] / up) * st * cp - (u[1] * U / up) * st * sp - u[0] * (1.0 - ct);
+        du[1] = (u[1] * u[2] / up) * st * cp + (u[0] * U / up) * st * sp - u[1] * (1.0 - ct);
+        du[2] = -up * st * cp - u[2] * (1.0 - ct);
+    } else {
+        du[0] = U * st * cp;
+        du[1] = U * st * sp;
+        du[2] = -u[2] * (1.0 - ct);
+    }
+    for (int c = 0; c < 3; ++c) u[c] += du[c];
+    return 1;
+}
+
 uint32_t orc_collision_threshold(double nu, double dt)
 {
     double P = 1.0 - exp(-nu * dt);
@@ -461,7 +507,8 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
             orc_species *S = &sp[s];
             const double qmdt2 = S->q * g->dt / (2.0 * S->m);
             const double qw = S->q * S->w;
-            const uint32_t thr = S->nu > 0.0 ? orc_collision_threshold(S->nu, g->dt) : 0u;
+            const uint32_t thr = (S->nu > 0.0 && S->model == 0) ? orc_collision_threshold(S->nu, g->dt) : 0u;
+            const int coulomb = S->nu > 0.0 && S->model == 1;
             int64_t p0 = S->n * ch / ORC_CHUNKS, p1 = S->n * (ch + 1) / ORC_CHUNKS;
             for (int64_t p = p0; p < p1; ++p) {
                 double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, E[3], B[3];
@@ -479,6 +526,7 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
                     for (int c = 0; c < 3; ++c) pp[ch][c] += S->w * 0.5 * (u_old[c] + u[c]);
                 }
                 if (thr && S->id) ncoll[ch] += orc_collide(u, S->id[p], step, seed, run, thr);
+                if (coulomb && S->id) ncoll[ch] += orc_coulomb(u, S->id[p], step, seed, run, S->nu, S->vref, g->dt);
                 for (int a = 0; a < g->ndim; ++a) S->x[a][p] = wrap_pos(x1[a], L[a]);
                 S->u[0][p] = u[0]; S->u[1][p] = u[1]; S->u[2][p] = u[2];
             }

@@ -27,6 +27,7 @@ constexpr int kMomentVals = 6;
 // Philox counter word 2 tags the purpose of a draw.
 constexpr uint32_t kPurposeCollide = 1u;
 constexpr uint32_t kPurposeLoad = 2u;
+constexpr uint32_t kPurposeCoulomb = 3u;
 
 struct DevState {
     int64_t step;        // index n of the step about to run
@@ -55,8 +56,10 @@ struct SpeciesDev {
     int64_t ncap;        // slots per set
     int64_t nominal;     // ppc * cells
     uint32_t ovf_cap;
-    uint32_t coll_thr;   // scatter when the 32-bit draw is below this
+    uint32_t coll_thr;   // scatter when the 32-bit draw is below this (isotropic model)
     int32_t collide;
+    int32_t coll_model;  // PIC_COLL_ISOTROPIC or PIC_COLL_COULOMB
+    double coll_sig2;    // Coulomb model: variance of tan(theta/2) = coll_sig2 / v^3
     int32_t track_id;    // carry ids (collisional species, or all in test mode)
     double q, m, w;
     double qmdt2;        // q dt / (2 m)
@@ -107,6 +110,7 @@ struct KParams {
     int32_t *order;      // [tiles] particle-kernel work order (XCD class, then decreasing load)
     uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
     double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
+    int32_t coulomb;     // 1 if a species scatters with the Coulomb model (selects the particle kernel)
 };
 
 // An ensemble of runs stepped together: every launch of a step covers all
@@ -131,6 +135,7 @@ struct BatchTable {
     int nst_blocks;       // max over runs of ceil(nspecies * tiles / 256)
     int max_species;
     int max_fd_blocks;    // max over runs of KParams::fd_blocks
+    int coulomb;          // 1 if any run has a species on the Coulomb scattering model
     const KParams *const *kp;   // [nruns] device parameter blocks
     const int2 *cell_blocks;    // [n_cell_blocks] (run, block of that run)
     BatchGroup grp[kBatchGroups];
@@ -155,7 +160,7 @@ hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, cons
                              const int pblocks[kBatchGroups], hipStream_t s, hipEvent_t *ev = nullptr);
 // Workgroups of the batch particle kernel of tile group g that fit on one
 // compute unit at once.
-hipError_t batch_particle_occupancy(int precision, int ndim, int g, int *blocks_per_cu);
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool coulomb, int *blocks_per_cu);
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
 hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);
 hipError_t launch_shift_u(const KParams &hp, const KParams *dp, int s, double dux, double duy,

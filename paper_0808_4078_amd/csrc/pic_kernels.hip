@@ -98,11 +98,15 @@ template <> struct Arith<float> {
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ void sc(float a, float *s, float *c) { sincosf(a, s, c); }
+    static __device__ __forceinline__ float ln(float x) { return logf(x); }
+    static __device__ __forceinline__ float cs(float a) { return cosf(a); }
 };
 template <> struct Arith<double> {
     static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ void sc(double a, double *s, double *c) { sincos(a, s, c); }
+    static __device__ __forceinline__ double ln(double x) { return log(x); }
+    static __device__ __forceinline__ double cs(double a) { return cos(a); }
 };
 
 // The step counter and particle-set parity live in memory that kernels also
@@ -389,7 +393,9 @@ constexpr int kBatch = 2;   // particles each lane keeps in flight ahead of the 
 // KP: pointer to the run's parameters -- the kernel argument, or (batched
 // runs) a constant-address-space pointer, which lets the parameter loads be
 // scalar loads (the parameter blocks are never written by a kernel).
-template <typename R, typename A, int D, int T, typename KP>
+// CB: the kernel carries the Coulomb scattering branch (runs with a species on
+// that model); without it the branch and its registers are compiled out.
+template <typename R, typename A, int D, int T, bool CB, typename KP>
 __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
 {
     constexpr int NF = T + 2;
@@ -477,6 +483,8 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         const R qw = R(S.qw);
         const double wgt = S.w;
         const bool collide = S.collide != 0;
+        const bool coulomb = CB && S.coll_model == PIC_COLL_COULOMB;
+        const R csig2 = R(S.coll_sig2);
         const bool track = S.track_id != 0;
         const uint32_t thr = S.coll_thr;
         const GLB uint32_t *__restrict__ icell = gbl(S.cell[src]);
@@ -741,7 +749,41 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 }
 
                 // ---- scattering off the ions (collisional species)
-                if (collide) {
+                if (collide && coulomb) {
+                    // Coulomb small-angle scattering off the ions: turn by theta,
+                    // tan(theta/2) ~ N(0, coll_sig2 / v^3), uniform azimuth,
+                    // Takizuka-Abe rotation of u (|u| kept)
+                    const R u2 = ux * ux + uy * uy + uz * uz;
+                    if (u2 > R(0)) {
+                        const uint4 r = philox10(make_uint4(pid, (uint32_t)step, kPurposeCoulomb, runid), seed0, seed1);
+                        const R v2 = u2 / (R(1) + u2);
+                        const R var = csig2 / (v2 * sqrt(v2));
+                        const R delta = sqrt(R(-2) * var * Arith<R>::ln(R(u01d(r.x)))) *
+                                        Arith<R>::cs(R(6.283185307179586) * R(u01d(r.y)));
+                        const R d2 = delta * delta;
+                        const R inv = R(1) / (R(1) + d2);
+                        const R omc = R(2) * d2 * inv;                  // 1 - cos(theta)
+                        const R st = R(2) * delta * inv;                // sin(theta)
+                        R sp, cp;
+                        Arith<R>::sc(R(6.283185307179586) * R(u01d(r.z)), &sp, &cp);
+                        const R up2 = ux * ux + uy * uy;
+                        if (up2 > R(0)) {
+                            const R iup = Arith<R>::rsq(up2);
+                            const R a = st * cp * iup, b = st * sp * sqrt(u2) * iup;
+                            const R dz = -up2 * iup * st * cp - uz * omc;
+                            const R dx = ux * uz * a - uy * b - ux * omc;
+                            uy += uy * uz * a + ux * b - uy * omc;
+                            ux += dx;
+                            uz += dz;
+                        } else {
+                            const R U = sqrt(u2);
+                            ux += U * st * cp;
+                            uy += U * st * sp;
+                            uz -= uz * omc;
+                        }
+                        if (diag) acc[5] += 1.0;
+                    }
+                } else if (collide) {
                     if (philox2x32_10_w0(pid, (uint32_t)step, ckey) < thr) {
                         const uint4 r = philox10(make_uint4(pid, (uint32_t)step, kPurposeCollide, runid), seed0, seed1);
                         const R um = sqrt(ux * ux + uy * uy + uz * uz);
@@ -1364,11 +1406,11 @@ typedef __attribute__((address_space(4))) const KParams KParamsC;
 
 // One workgroup per tile; workgroup b takes tile order[b] (see the work
 // order built at the end of each step).
-template <typename R, typename A, int D, int T>
+template <typename R, typename A, int D, int T, bool CB>
 __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
 {
     const KParamsC *kc = (const KParamsC *)kp;
-    particle_body<R, A, D, T>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
+    particle_body<R, A, D, T, CB>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
 }
 
 // Persistent: workgroup w (on XCD w mod 8) takes the items of its XCD
@@ -1376,7 +1418,7 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
 // in a run stepped alone -- and, when its class is exhausted, the remaining
 // items of the other classes.  The counters only grow, so every workgroup
 // reaches the exit.
-template <typename R, typename A, int D, int T>
+template <typename R, typename A, int D, int T, bool CB>
 __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restrict__ bt)
 {
     constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
@@ -1395,7 +1437,7 @@ __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restri
             if (i >= len) break;
             const int2 it = items[i];
             const KParamsC *kp = (const KParamsC *)wave_uniform_ptr(bt->kp[wave_uniform(it.x)]);
-            particle_body<R, A, D, T>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
+            particle_body<R, A, D, T, CB>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
         }
     }
 }
@@ -1639,7 +1681,8 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
     Launcher L{st, ev};
     L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
-    L(k_particle<R, A, D, T>, dim3(ntiles), dim3(kBlock), dp);
+    if (hp.coulomb) L(k_particle<R, A, D, T, true>, dim3(ntiles), dim3(kBlock), dp);
+    else L(k_particle<R, A, D, T, false>, dim3(ntiles), dim3(kBlock), dp);
     L(k_rebin_count, dim3(nst), dim3(256), dp);
     L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_scan, dim3(hp.nspecies), dim3(256), dp);
@@ -1689,7 +1732,8 @@ static void batch_particle(Launcher &L, const BatchTable &ht, const BatchTable *
 {
     constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
     const unsigned nb = ht.grp[g].n_items > 0 ? (unsigned)std::max(1, pblocks) : 1u;
-    L(kb_particle<R, A, D, T>, dim3(nb), dim3(kBlock), dt);
+    if (ht.coulomb) L(kb_particle<R, A, D, T, true>, dim3(nb), dim3(kBlock), dt);
+    else L(kb_particle<R, A, D, T, false>, dim3(nb), dim3(kBlock), dt);
 }
 
 template <typename R, int D>
@@ -1738,19 +1782,20 @@ hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, cons
 }
 
 template <typename R, int D, int T>
-static hipError_t occupancy(int *n)
+static hipError_t occupancy(bool cb, int *n)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T>, kBlock, 0);
+    return cb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T, true>, kBlock, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T, false>, kBlock, 0);
 }
 
-hipError_t batch_particle_occupancy(int precision, int ndim, int g, int *n)
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool cb, int *n)
 {
     const bool mx = precision == PIC_PREC_MIXED;
-    if (ndim == 3) return mx ? occupancy<float, 3, 8>(n) : occupancy<double, 3, 8>(n);
+    if (ndim == 3) return mx ? occupancy<float, 3, 8>(cb, n) : occupancy<double, 3, 8>(cb, n);
     switch (g) {
-    case 0: return mx ? occupancy<float, 2, 8>(n) : occupancy<double, 2, 8>(n);
-    case 1: return mx ? occupancy<float, 2, 16>(n) : occupancy<double, 2, 16>(n);
-    case 2: return mx ? occupancy<float, 2, 32>(n) : occupancy<double, 2, 32>(n);
+    case 0: return mx ? occupancy<float, 2, 8>(cb, n) : occupancy<double, 2, 8>(cb, n);
+    case 1: return mx ? occupancy<float, 2, 16>(cb, n) : occupancy<double, 2, 16>(cb, n);
+    case 2: return mx ? occupancy<float, 2, 32>(cb, n) : occupancy<double, 2, 32>(cb, n);
     default: return hipErrorInvalidValue;
     }
 }

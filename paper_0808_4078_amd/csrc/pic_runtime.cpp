@@ -140,6 +140,10 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         if (!(S.density >= 0.0)) return fail(err, PIC_E_INVALID_ARG, "species %d: density must be >= 0", s);
         if (S.nu_coll < 0.0) return fail(err, PIC_E_INVALID_ARG, "species %d: nu_coll < 0", s);
         if (!(S.u_th >= 0.0)) return fail(err, PIC_E_INVALID_ARG, "species %d: u_th < 0", s);
+        if (S.coll_model != PIC_COLL_ISOTROPIC && S.coll_model != PIC_COLL_COULOMB)
+            return fail(err, PIC_E_INVALID_ARG, "species %d: coll_model %d", s, S.coll_model);
+        if (S.coll_model == PIC_COLL_COULOMB && S.nu_coll > 0.0 && !(S.coll_vref > 0.0 && S.coll_vref < 1.0))
+            return fail(err, PIC_E_INVALID_ARG, "species %d: Coulomb scattering needs 0 < coll_vref < 1", s);
         if (S.cancel_current_of >= ns || S.cancel_current_of < -1)
             return fail(err, PIC_E_INVALID_ARG, "species %d: cancel_current_of %d", s, S.cancel_current_of);
         Layout::Sp &P = L->sp[s];
@@ -615,6 +619,11 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
         const double P_coll = 1.0 - std::exp(-S.nu_coll * grid->dt);
         const double thr = std::floor(P_coll * 4294967296.0);
         D.coll_thr = D.collide ? (uint32_t)std::min(4294967295.0, std::max(0.0, thr)) : 0u;
+        D.coll_model = S.coll_model;
+        D.coll_sig2 = S.coll_model == PIC_COLL_COULOMB
+                          ? 0.5 * S.nu_coll * grid->dt * S.coll_vref * S.coll_vref * S.coll_vref
+                          : 0.0;
+        if (D.collide && D.coll_model == PIC_COLL_COULOMB) K.coulomb = 1;
         D.q = S.charge;
         D.m = S.mass;
         D.w = S.density / S.ppc;
@@ -1187,6 +1196,8 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
     H.nst_blocks = std::max(1, nst);
     H.max_species = max_species;
     H.max_fd_blocks = max_fd;
+    H.coulomb = 0;
+    for (int i = 0; i < nruns; ++i) H.coulomb |= runs[i]->hp.coulomb;
     H.kp = (const KParams *const *)(base + B.kp);
     H.cell_blocks = (const int2 *)(base + B.cell_blocks);
     for (int g = 0; g < kBatchGroups; ++g) {
@@ -1209,7 +1220,7 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
             continue;
         }
         int per_cu = 0;
-        he = batch_particle_occupancy(b->precision, b->ndim, g, &per_cu);
+        he = batch_particle_occupancy(b->precision, b->ndim, g, H.coulomb != 0, &per_cu);
         b->pblocks[g] = std::max(1, per_cu) * std::max(1, cus);
     }
     const std::vector<int> zeros((size_t)kBatchGroups * kBatchXcds, 0);

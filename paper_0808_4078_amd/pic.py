@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK = 0
 PIC_PREC_FP64 = 0
 PIC_PREC_MIXED = 1
+PIC_COLL_ISOTROPIC = 0
+PIC_COLL_COULOMB = 1
 PIC_FLAG_FREEZE_FIELDS = 1
 PIC_FLAG_NO_COLLIDE = 2
 PIC_FLAG_LATTICE_LOAD = 4
@@ -40,7 +42,7 @@ class GridDesc(C.Structure):
 class SpeciesDesc(C.Structure):
     _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("density", C.c_double), ("ppc", C.c_int32),
                 ("drift_u", C.c_double * 3), ("u_th", C.c_double), ("cancel_current_of", C.c_int32),
-                ("nu_coll", C.c_double)]
+                ("nu_coll", C.c_double), ("coll_model", C.c_int32), ("coll_vref", C.c_double)]
 
 
 class Sizes(C.Structure):
@@ -169,14 +171,19 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
         arr[i].u_th = float(s.get("u_th", 0.0))
         arr[i].cancel_current_of = int(s.get("cancel_current_of", -1))
         arr[i].nu_coll = float(s.get("nu_coll", 0.0))
+        arr[i].coll_model = int(s.get("coll_model", PIC_COLL_ISOTROPIC))
+        arr[i].coll_vref = float(s.get("coll_vref", 0.0))
     return g, arr
 
 
 def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0, reserve=0.0):
     """Descriptors of a synthetic workload object (attributes ndim, n, d, dt,
-    seed, species[name, q, m, density, ppc, drift_u, u_th, nu, cancel_current_of])."""
+    seed, species[name, q, m, density, ppc, drift_u, u_th, nu, cancel_current_of, and
+    optionally coll_model, coll_vref])."""
     sp = [dict(charge=s.q, mass=s.m, density=s.density, ppc=s.ppc, drift_u=s.drift_u, u_th=s.u_th,
-               cancel_current_of=s.cancel_current_of, nu_coll=s.nu) for s in wl.species]
+               cancel_current_of=s.cancel_current_of, nu_coll=s.nu,
+               coll_model=getattr(s, "coll_model", PIC_COLL_ISOTROPIC), coll_vref=getattr(s, "coll_vref", 0.0))
+          for s in wl.species]
     if getattr(wl, "lattice", False):
         flags |= PIC_FLAG_LATTICE_LOAD
     return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags, reserve)

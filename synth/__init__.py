@@ -36,6 +36,8 @@ class SpeciesCfg:
     m: float = 1.0
     nu: float = 0.0          # scattering rate off the ions, w_p (0 = collisionless)
     cancel_current_of: int = -1   # shift this species' u_z so the net J_z is zero
+    coll_model: int = 0      # 0: isotropic scattering at rate nu; 1: Coulomb small-angle
+    coll_vref: float = 0.0   # Coulomb model: speed (c) at which the momentum-transfer rate is nu
 
     @property
     def weight(self) -> float:
@@ -68,15 +70,18 @@ U_BEAM = math.sqrt(GAMMA_BEAM ** 2 - 1.0)     # 2.8284271...
 
 
 def beam_plasma(n, d=None, dt=0.1, steps=200, ppc=16, u_th_beam=0.1, u_th_plasma=0.01,
-                nu=0.0, n_b=0.1, u_beam=U_BEAM, name="custom", seed=SEED, lattice=False) -> Workload:
-    """Beam (index 0) along +z and return-current plasma (index 1)."""
+                nu=0.0, n_b=0.1, u_beam=U_BEAM, name="custom", seed=SEED, lattice=False,
+                coll_model=0, coll_vref=0.0) -> Workload:
+    """Beam (index 0) along +z and return-current plasma (index 1); the plasma
+    scatters off the ions at rate nu (coll_model 0: isotropic at a fixed
+    rate; 1: Coulomb small-angle, rate nu at speed coll_vref)."""
     n = tuple(int(v) for v in n)
     ndim = len(n)
     if d is None:
         d = (0.2,) * ndim
     beam = SpeciesCfg("beam", n_b, ppc, (0.0, 0.0, u_beam), u_th_beam)
     plasma = SpeciesCfg("plasma", 1.0 - n_b, ppc, (0.0, 0.0, 0.0), u_th_plasma, nu=nu,
-                        cancel_current_of=0)
+                        cancel_current_of=0, coll_model=coll_model, coll_vref=coll_vref)
     return Workload(name, ndim, n, tuple(d), dt, steps, (beam, plasma), seed, lattice)
 
 

@@ -16,7 +16,8 @@ def log(*a):
 
 
 def oracle_species(wl, parts):
-    return [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x.copy(), p.u.copy(), p.id.copy())
+    return [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x.copy(), p.u.copy(), p.id.copy(),
+                                sc.coll_model, sc.coll_vref)
             for sc, p in zip(wl.species, parts)]
 
 

@@ -499,3 +499,46 @@ def test_warm_beam_dispersion_limits():
     ks = np.linspace(0.05, 6.0, 120)
     assert max(theory.warm_beam_growth(kk, cs2p, wbp, 0.0) for kk in ks) < 1e-10
     assert max(theory.warm_beam_growth(kk, cs2p, wbp, 0.15) for kk in ks) > 0.04
+
+
+def test_coulomb_scattering_drag_and_v3_law():
+    """Coulomb small-angle scattering (model 1): tan(theta/2) = delta with
+    delta ~ N(0, s^2), s^2 = nu (vref/v)^3 dt / 2.  For a Gaussian delta,
+    E[cos theta] = 2 E[1/(1+delta^2)] - 1 and E[1/(1+delta^2)] =
+    sqrt(pi/2)/s erfcx(1/(sqrt(2) s)) exactly, so the mean momentum kept along
+    u after one step is fixed at any s; at small s it tends to 1 - nu_m(v) dt.
+    Checked at two speeds (the v^-3 law) and a large s; |u| is kept, and the
+    azimuth is uniform (u along z: mean transverse momentum 0)."""
+    from scipy.special import erfcx
+    from oracle import coulomb
+    nu, vref, dt = 0.05, 0.1, 0.1
+    n = 60000
+    for U, s2_scale in ((0.1, 1.0), (0.2, 1.0), (0.05, 1.0)):
+        g = math.sqrt(1 + U * U)
+        v = U / g
+        s2 = 0.5 * nu * dt * (vref / v) ** 3
+        s = math.sqrt(s2)
+        want = 2.0 * math.sqrt(math.pi / 2) / s * erfcx(1.0 / (math.sqrt(2) * s)) - 1.0
+        u0 = np.array([0.6, 0.0, 0.8]) * U
+        kept = np.empty(n)
+        norm_err = 0.0
+        for i in range(n):
+            u1, hit = coulomb(u0, i, 3, 77, 0, nu, vref, dt)
+            assert hit
+            kept[i] = float(u1 @ u0) / (U * U)
+            norm_err = max(norm_err, abs(np.linalg.norm(u1) - U) / U)
+        sd = kept.std() / math.sqrt(n)
+        assert abs(kept.mean() - want) < 5 * sd + 1e-12, (U, kept.mean(), want, sd)
+        assert norm_err < 1e-14
+        if s2 < 0.01:
+            assert abs((1 - want) / (2 * s2) - 1) < 0.05          # small angles: loss = nu_m(v) dt
+    # u along z (the special branch): uniform azimuth, mean transverse momentum 0
+    ut = np.empty((n, 3))
+    for i in range(n):
+        ut[i], _ = coulomb(np.array([0.0, 0.0, 0.05]), i, 1, 5, 0, nu, vref, dt)
+    assert abs(ut[:, 0].mean()) < 5 * ut[:, 0].std() / math.sqrt(n)
+    assert abs(ut[:, 1].mean()) < 5 * ut[:, 1].std() / math.sqrt(n)
+    assert np.max(np.abs(np.linalg.norm(ut, axis=1) - 0.05)) < 1e-15
+    # no rate, no scattering
+    u1, hit = coulomb(np.array([0.1, 0.2, 0.3]), 1, 1, 1, 0, 0.0, vref, dt)
+    assert not hit and np.array_equal(u1, [0.1, 0.2, 0.3])
