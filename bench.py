@@ -114,6 +114,9 @@ def progress(msg: str):
 # its tile's spare room) rarer.  The ensemble keeps the default.
 RESERVE_2D = 3.0      # C2/C3: 32 GB of particle store
 RESERVE_3D = 2.0      # C4: 112 GB
+# Coulomb-model line: the momentum-transfer rate is nu at this speed (about
+# the return current's drift speed in C3)
+COULOMB_VREF = 0.1
 
 
 def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, profile: bool = True,
@@ -273,6 +276,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="256^2 grid instead of 1024^2 (for profiling)")
     ap.add_argument("--c4", type=int, default=500, metavar="K",
                     help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed; 0 = skip)")
+    ap.add_argument("--coulomb", type=int, default=300, metavar="K",
+                    help="also time K steps of C3 with the plasma on the Coulomb scattering model (0 = skip)")
     ap.add_argument("--c5", type=int, default=300, metavar="K",
                     help="also time K batch steps of the 256-run 2D ensemble (mixed, autotuned tiles; 0 = skip)")
     a = ap.parse_args()
@@ -350,6 +355,20 @@ def main():
                      "ms_per_step": c4["ms"] / a.c4, "particle_kernel_ms": c4_pk,
                      "particle_kernel_GBs": c4_bytes / (c4_pk * 1e-3) / 1e9,
                      "step_breakdown_ms": {k: v / a.c4 for k, v in c4["groups_ms"].items()}}
+    if a.coulomb > 0:
+        sp0, sp1 = wl.species
+        wc = replace(wl, name=f"{wl.name}-coulomb",
+                     species=(sp0, replace(sp1, coll_model=1, coll_vref=COULOMB_VREF)))
+        cm = run_gpu(wc, "mixed", a.coulomb, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D)
+        cm_pk = cm["groups_ms"]["particle"] / a.coulomb
+        rec["coulomb"] = {"workload": f"{wl.name} with the return-current plasma on the Coulomb small-angle "
+                                      f"model (nu=0.05 at v={COULOMB_VREF}c, every plasma particle turned every "
+                                      "step), mixed precision",
+                          "particles": cm["particles"], "steps": a.coulomb,
+                          "value": cm["particles"] / (cm["ms"] / a.coulomb * 1e-3),
+                          "ms_per_step": cm["ms"] / a.coulomb, "particle_kernel_ms": cm_pk,
+                          "particle_kernel_GBs": pk_bytes / (cm_pk * 1e-3) / 1e9,
+                          "step_breakdown_ms": {k: v / a.coulomb for k, v in cm["groups_ms"].items()}}
     if a.c5 > 0:
         rec["c5"] = run_c5(a.c5, min(a.warmup, 5), a.diag_every)
     if not a.skip_cpu:
