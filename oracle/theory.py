@@ -83,6 +83,47 @@ def warm_beam_growth_long_wave(cs2: float, wb2b2: float, nu: float, kpe2: float 
     return nu * wb2b2 / (kpe2 * cs2 - wb2b2)
 
 
+def hybrid_cold_roots(k: float, n_b: float, u_b: float, nu: float, n0: float = 1.0, dx: float = 0.0):
+    """Linear filamentation of a cold beam (density n_b, u_z = u_b) in the
+    reduced model with local quasi-neutrality, a mode k across the beam.
+    Linearising Eqs. (2)-(4), (6) about the uniform state with the neutralising
+    return current beta_p0 = -n_b beta_0/n_p, n_p = n0 - n_b:
+      force on a beam electron   -(beta_0 - beta_p0) grad a  (transverse mass gamma),
+      current of a density bump  (beta_0 - beta_p0) delta n_b  (the plasma gives way),
+      the beam's own z response  chi = n_b/gamma^3 (Eq. 6: delta u_z = delta a),
+      plasma response            n_p delta a omega/(omega + i nu)  (Eq. 3),
+    give omega^2 (k^2 + chi + n_p omega/(omega + i nu)) = -A k^2 with
+    A = (n_b/gamma)(beta_0 - beta_p0)^2: Eq. (12) with c_s = 0, k_pe^2 = n_p,
+    omega_b^2 beta_0^2 = A, plus chi.  As a cubic:
+      (k^2 + chi + n_p) w^3 + i nu (k^2 + chi) w^2 + A k^2 w + i nu A k^2 = 0.
+    With dx > 0 the grid's own factors replace the continuum ones (mode along
+    a grid axis): the 5-point Laplacian's (2/dx)^2 sin^2(k dx/2) for k^2, the
+    staggered difference (2/dx) sin(k dx/2) for one k of the force, and the
+    cloud-in-cell transfer S = (sin(k dx/2)/(k dx/2))^2 once for the gather
+    and once for the deposit."""
+    gamma = math.sqrt(1.0 + u_b * u_b)
+    beta0 = u_b / gamma
+    n_p = n0 - n_b
+    bbar = beta0 + n_b * beta0 / n_p
+    A = n_b / gamma * bbar * bbar
+    chi = n_b / gamma ** 3
+    if dx > 0:
+        h = 0.5 * k * dx
+        kg = 2.0 / dx * math.sin(h)
+        S = (math.sin(h) / h) ** 2
+        K2 = kg * kg
+        Ak2 = A * k * kg * S * S
+        chi = chi * S * S
+    else:
+        K2 = k * k
+        Ak2 = A * k * k
+    return np.roots([K2 + chi + n_p, 1j * nu * (K2 + chi), Ak2, 1j * nu * Ak2])
+
+
+def hybrid_cold_growth(k, n_b, u_b, nu, n0=1.0, dx=0.0) -> float:
+    return max(0.0, float(np.max(hybrid_cold_roots(k, n_b, u_b, nu, n0, dx).imag)))
+
+
 def paper_case_parameters(v_b: float = 0.9, n_b: float = 0.1, u_th: float = 0.37):
     """(c_s^2, wb2b2) of the paper's 2D beam for Eq. (12), with the
     relativistic transverse inertia gamma_b m: the beam's transverse thermal

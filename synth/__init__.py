@@ -226,3 +226,76 @@ def cold_return_drift(n_b: float = 0.1, u_beam: float = U_BEAM) -> float:
     v_b = u_beam / math.sqrt(1.0 + u_beam ** 2)
     v_p = -n_b * v_b / (1.0 - n_b)
     return v_p / math.sqrt(1.0 - v_p ** 2)
+
+
+# ---------------------------------------------------------------------------
+# The reduced quasi-neutral model (kinetic beam, fluid return current): its
+# inputs are the beam alone; the plasma starts at rest relative to a = A_z
+# (its return current is part of the model's initial solve).
+@dataclass(frozen=True)
+class HybridWorkload:
+    name: str
+    n: tuple                 # nodes per axis (nx, ny), powers of two
+    d: tuple                 # node spacing, c/w_p
+    dt: float                # 1/w_p
+    steps: int
+    n_b: float               # mean beam density / n0
+    ppc: int                 # beam macro-particles per cell
+    u_b: float               # beam u_z drift
+    u_th: float              # Gaussian spread of each beam momentum component
+    nu: float                # collision rate of the return-current plasma
+    iters: int = 10          # fixed-point sweeps of the field solve per step
+    seed: int = SEED
+    lattice: bool = False    # regular sub-lattice (ppc must be a square)
+    seed_mode: tuple = ()    # (m, xi): x -> x + xi sin(2 pi m x / L_x)
+
+    @property
+    def cells(self) -> int:
+        return int(self.n[0] * self.n[1])
+
+    @property
+    def particles(self) -> int:
+        return self.cells * self.ppc
+
+    @property
+    def weight(self) -> float:
+        return self.n_b / self.ppc
+
+
+def hybrid_load(wl: HybridWorkload):
+    """Beam particles in cell-major order (x fastest), exactly ppc per cell:
+    positions (2, N), transverse momenta (2, N) with the sample mean removed,
+    and u_z (N,) = u_b + u_th N(0,1)."""
+    rng = np.random.default_rng(wl.seed)
+    nx, ny = wl.n
+    dx, dy = wl.d
+    cells = nx * ny
+    ci = np.repeat(np.arange(cells, dtype=np.int64), wl.ppc)
+    N = ci.size
+    if wl.lattice:
+        side = int(round(math.sqrt(wl.ppc)))
+        if side * side != wl.ppc:
+            raise ValueError("lattice loading needs a square ppc")
+        k = np.tile(np.arange(wl.ppc), cells)
+        off = np.stack([(k % side + 0.5) / side, (k // side + 0.5) / side])
+    else:
+        off = rng.uniform(0.0, 1.0, (2, N))
+    x = np.stack([((ci % nx) + off[0]) * dx, ((ci // nx) + off[1]) * dy])
+    if wl.seed_mode:
+        m, xi = wl.seed_mode
+        L = nx * dx
+        x[0] = np.mod(x[0] + xi * np.sin(2 * math.pi * m * x[0] / L), L)
+        x[0][x[0] >= L] = 0.0
+    u = np.zeros((2, N))
+    uz = np.full(N, float(wl.u_b))
+    if wl.u_th > 0:
+        u = wl.u_th * rng.standard_normal((2, N))
+        u -= u.mean(axis=1, keepdims=True)
+        uz = uz + wl.u_th * rng.standard_normal(N)
+    return x, u, uz
+
+
+# H1: the reduced-model parity case; H2: the benchmark size (the paper's
+# collisional hot beam, Eqs. 1-7, on a 1024^2 grid).
+H1 = HybridWorkload("H1", (64, 64), (0.2, 0.2), 0.1, 100, 0.1, 16, U_BEAM, 0.1, 0.05)
+H2 = HybridWorkload("H2", (1024, 1024), (0.125, 0.125), 0.0625, 200, 0.1, 64, 0.9 / math.sqrt(1 - 0.81), 0.37, 0.15)
