@@ -339,6 +339,120 @@ int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
              int32_t copies, void *workspace, size_t workspace_bytes, void *hip_stream,
              int32_t nsteps, int32_t *best_tile, double ms[3]);
 
+/* ---- The reduced quasi-neutral model ---------------------------------------
+ * The paper's own model of the filamenting beam (the theory part, Eqs. 1-7):
+ * the beam is kinetic in the transverse plane, the return-current plasma is
+ * a cold fluid streaming along z with collisional drag, and the field is the
+ * single potential a = e A_z/(m c^2) of Ampere's law without displacement
+ * current.  In the units above, with local quasi-neutrality
+ * n_p(x) = max(n0 - n_b(x), 0):
+ *   lap a = n_b beta_bz + n_p beta_pz                         (Eq. 2)
+ *   d_t psi = -nu beta_pz, psi = beta_pz - a                 (Eq. 3)
+ *   d(u_perp)/dt = -(beta_z - beta_pz) grad a                 (Eq. 4)
+ *   u_z = p_z + a, p_z the conserved canonical momentum       (Eq. 6)
+ * so that B_perp = -e_z x grad a, E_z = -d_t a, E_perp = -beta_pz grad a
+ * (Eq. 1), and Eq. (7) is conserved when nu = 0.  Numerics: nodes at
+ * (i dx, j dy), periodic; cloud-in-cell deposit and gathers; grad a by
+ * forward differences at ((i+1/2) dx, j dy) and (i dx, (j+1/2) dy); a^n from
+ * Eq. (2) with the beam current linearised about a* = 2 a^(n-1) - a^(n-2)
+ * (d beta_z/d u_z = (1 + u_perp^2)/gamma^3), solved by `iters` fixed-point
+ * sweeps, each an FFT solve of lap - (n0 - <n_b>); leapfrog in time (x, a at
+ * integer steps, u_perp at half steps).  Everything is FP64.
+ *
+ * Buffers (caller-owned device memory, sizes from pic_hyb_query):
+ *  - particles: two copies (the cell sort alternates between them) of the
+ *    SoA arrays x, y, u_x, u_y, p_z (FP64) and id (u32), each array on a
+ *    256-byte boundary;
+ *  - grid: a^(n-1), a^(n-2), psi, two solve iterates, two deposit sets
+ *    (n_b, J at a*, chi, chi a*), one complex FFT plane, twiddle and
+ *    Laplacian tables, counters, the sort's cell offsets, diagnostic
+ *    partials and a ring of 4096 pic_hyb_diag records.
+ * Errors are reported as for pic_run; pic_hyb_last_error describes them. */
+typedef struct pic_hyb_desc {
+    int32_t nx, ny;        /* nodes per axis: powers of two in 8..4096 */
+    double dx, dy;         /* node spacing, c/w_p (> 0) */
+    double dt;             /* time step, 1/w_p (> 0) */
+    double nu;             /* collision rate of the return-current plasma (Eq. 3), w_p (>= 0) */
+    double n0;             /* ion (background) density, n0 units: 1 in the paper's set-up (> 0) */
+    double weight;         /* beam density carried by one macro-particle: n_b / ppc (>= 0) */
+    int64_t nparticles;    /* beam macro-particles, 0..2^31 - 1 */
+    int32_t iters;         /* fixed-point sweeps of the Eq. (2) solve per step, 1..64 */
+    int32_t diag_every;    /* 0: no diagnostics; k: a record every k steps */
+    int32_t sort_every;    /* 0: never; k: re-sort the particles by cell every k steps */
+    uint32_t flags;        /* PIC_FLAG_NO_GRAPH or 0 */
+} pic_hyb_desc;
+
+/* One diagnostic record at time level n (energies per unit length in z, in
+ * n0 m c^2 (c/w_p)^2): the terms of Eq. (7) and the field energies. */
+typedef struct pic_hyb_diag {
+    int64_t step;
+    double time;
+    double beam_energy;    /* dA sum_j w gamma_j^n, gamma^n = (gamma^- + gamma^+)/2 */
+    double beam_a2;        /* dA sum_j w a(x_j)^2 / 2 */
+    double grad_energy;    /* dA sum |grad a|^2 / 2 (staggered differences) */
+    double a2_energy;      /* dA sum n0 a^2 / 2 */
+    double eq7;            /* beam_energy - beam_a2 + grad_energy + a2_energy */
+    double W_Bperp;        /* dA sum |B_perp|^2 = 2 grad_energy */
+    double W_Ez;           /* dA sum ((a^n - a^(n-1))/dt)^2 */
+    double beam_pz;        /* dA sum_j w u_z,j^n */
+    double mean_a;         /* node mean of a^n */
+    double mean_psi;       /* node mean of psi^n */
+} pic_hyb_diag;
+
+typedef struct pic_hyb pic_hyb;
+
+/* Host only.  Validates the descriptor and gives the two buffer sizes.
+ * Errors: INVALID_ARG (a field out of its range), UNSUPPORTED (a size that
+ * is not a power of two in 8..4096). */
+int pic_hyb_query(const pic_hyb_desc *desc, size_t *particle_bytes, size_t *grid_bytes);
+
+/* Initialises a run on the current device and enqueues everything on
+ * `hip_stream`: the host arrays (nparticles each; ids 0..N-1 follow this
+ * order) are copied in, the beam current of the given u_z is deposited,
+ * Eq. (2) is solved for a^0 (psi = 0: the plasma starts with the
+ * neutralising return current beta_pz = a^0), and p_z = u_z - a^0(x) is
+ * stored.  u_x, u_y are taken as u_perp^(-1/2).  Positions must lie in
+ * [0, nx dx) x [0, ny dy).  Synchronising.  Errors: those of pic_hyb_query,
+ * INVALID_ARG (NULL pointer, a position outside the box), BUFFER_TOO_SMALL,
+ * HIP. */
+int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_bytes, void *grid,
+                 size_t grid_bytes, void *hip_stream, const double *x, const double *y, const double *ux,
+                 const double *uy, const double *uz, pic_hyb **out);
+
+/* Enqueues nsteps steps (one captured graph per step unless
+ * PIC_FLAG_NO_GRAPH).  Asynchronous. */
+int pic_hyb_step(pic_hyb *h, int32_t nsteps);
+
+/* The same steps launched kernel by kernel with HIP events on each launch;
+ * group_ms[4] receives the summed milliseconds of: the Eq. (2) solve, the
+ * particle kernel, the grid update (psi, a, diagnostics), the cell sort and
+ * step bookkeeping.  Synchronising. */
+int pic_hyb_step_profiled(pic_hyb *h, int32_t nsteps, double *group_ms);
+
+/* Waits for the stream; reports a device-side failure. */
+int pic_hyb_sync(pic_hyb *h);
+
+/* Synchronising.  Copies a^n of the last step (a^0 before the first) and
+ * psi^(n+1) into host arrays of ny*nx doubles (row-major, x fastest); either
+ * may be NULL. */
+int pic_hyb_read_grid(pic_hyb *h, double *a, double *psi);
+
+/* Synchronising.  Copies the particles (storage order; the cell sort
+ * permutes them): x^(n+1), y^(n+1), u_perp^(n+1/2), p_z and the ids into
+ * host arrays of nparticles entries; any pointer may be NULL. */
+int pic_hyb_read_particles(pic_hyb *h, double *x, double *y, double *ux, double *uy, double *pz, uint32_t *id);
+
+/* Synchronising.  Copies up to `max` of the most recent records, oldest
+ * first; *n receives the count. */
+int pic_hyb_diag_history(pic_hyb *h, pic_hyb_diag *out, int32_t max, int32_t *n);
+
+/* Message of the last failure on h (h == NULL: of the last failed
+ * pic_hyb_query / pic_hyb_init on this thread). */
+int pic_hyb_last_error(pic_hyb *h, char *buf, size_t n);
+
+/* Waits for the stream and frees the host state (not the caller's buffers). */
+int pic_hyb_destroy(pic_hyb *h);
+
 #ifdef __cplusplus
 }
 #endif

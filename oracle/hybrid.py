@@ -88,6 +88,32 @@ class Hybrid:
         self.a_prev = a0.copy()
         self.dep = self._deposit_linearised(self.x, self.u, 2.0 * self.a_cur - self.a_prev)
 
+    @classmethod
+    def from_state(cls, n, d, dt, nu, x, u, P, w, a_cur, a_prev, psi, n0=1.0, iters=10):
+        """A run continued from a given state: positions x^n, u_perp^(n-1/2),
+        canonical momenta P, a^(n-1), a^(n-2), psi^n; the deposit at x^n is
+        made here about a* = 2 a^(n-1) - a^(n-2)."""
+        h = cls.__new__(cls)
+        h.nx, h.ny = int(n[0]), int(n[1])
+        h.dx, h.dy = float(d[0]), float(d[1])
+        h.dt, h.nu, h.n0, h.iters = float(dt), float(nu), float(n0), int(iters)
+        h.w = float(w)
+        h.x = np.array(x, dtype=np.float64)
+        h.u = np.array(u, dtype=np.float64)
+        h.P = np.array(P, dtype=np.float64)
+        h.dA = h.dx * h.dy
+        h.L = np.array([h.nx * h.dx, h.ny * h.dy])
+        h.c0 = h.n0 - h.w * h.x.shape[1] / (h.nx * h.ny)
+        kx, ky = np.arange(h.nx), np.arange(h.ny)
+        h.symbol = (-(4.0 / h.dx ** 2) * np.sin(math.pi * kx / h.nx)[None, :] ** 2
+                    - (4.0 / h.dy ** 2) * np.sin(math.pi * ky / h.ny)[:, None] ** 2 - h.c0)
+        h.step_index = 0
+        h.psi = np.array(psi, dtype=np.float64)
+        h.a_cur = np.array(a_cur, dtype=np.float64)
+        h.a_prev = np.array(a_prev, dtype=np.float64)
+        h.dep = h._deposit_linearised(h.x, h.u, 2.0 * h.a_cur - h.a_prev)
+        return h
+
     # ---- cloud-in-cell weights, gathers and deposit
     def _axis(self, xa, h, n, shift):
         f = xa / h - shift

@@ -16,6 +16,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK = 0
+PIC_E_INVALID_ARG = -1
+PIC_E_UNSUPPORTED = -2
+PIC_E_CFL = -3
+PIC_E_BUFFER_TOO_SMALL = -4
+PIC_E_HIP = -5
+PIC_E_STATE = -6
+PIC_E_CAPACITY = -7
 PIC_PREC_FP64 = 0
 PIC_PREC_MIXED = 1
 PIC_COLL_ISOTROPIC = 0
@@ -80,7 +87,27 @@ EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
            "pic_status_string", "pic_last_error", "pic_batch_query", "pic_batch_init", "pic_batch_step",
            "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_destroy", "pic_tune_query",
-           "pic_tune", "pic_checkpoint", "pic_restore"]
+           "pic_tune", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
+           "pic_hyb_step_profiled", "pic_hyb_sync", "pic_hyb_read_grid", "pic_hyb_read_particles",
+           "pic_hyb_diag_history", "pic_hyb_last_error", "pic_hyb_destroy"]
+
+
+class HybDesc(C.Structure):
+    """pic_hyb_desc: the reduced quasi-neutral model's run description."""
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dt", C.c_double), ("nu", C.c_double), ("n0", C.c_double), ("weight", C.c_double),
+                ("nparticles", C.c_int64), ("iters", C.c_int32), ("diag_every", C.c_int32),
+                ("sort_every", C.c_int32), ("flags", C.c_uint32)]
+
+
+class HybDiag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("time", C.c_double), ("beam_energy", C.c_double), ("beam_a2", C.c_double),
+                ("grad_energy", C.c_double), ("a2_energy", C.c_double), ("eq7", C.c_double),
+                ("W_Bperp", C.c_double), ("W_Ez", C.c_double), ("beam_pz", C.c_double), ("mean_a", C.c_double),
+                ("mean_psi", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def lib():
@@ -127,6 +154,16 @@ def lib():
         L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, P(C.c_size_t)]
         L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp, C.c_int32,
                                P(C.c_int32), P(C.c_double)]
+        L.pic_hyb_query.argtypes = [P(HybDesc), P(C.c_size_t), P(C.c_size_t)]
+        L.pic_hyb_init.argtypes = [P(HybDesc), vp, C.c_size_t, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
+        L.pic_hyb_step.argtypes = [vp, C.c_int32]
+        L.pic_hyb_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
+        L.pic_hyb_sync.argtypes = [vp]
+        L.pic_hyb_read_grid.argtypes = [vp, vp, vp]
+        L.pic_hyb_read_particles.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pic_hyb_diag_history.argtypes = [vp, P(HybDiag), C.c_int32, P(C.c_int32)]
+        L.pic_hyb_last_error.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.pic_hyb_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -411,3 +448,105 @@ def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None
                           int(ws.numel()), C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
     del ws
     return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}
+
+
+# ---------------------------------------------------------------------------
+# The reduced quasi-neutral model (pic_hyb_*)
+def _hyb_check(rc: int, what: str, handle=None):
+    if rc != PIC_OK:
+        buf = C.create_string_buffer(1024)
+        lib().pic_hyb_last_error(handle, buf, 1024)
+        raise PicError(rc, what, buf.value.decode(errors="replace"))
+
+
+def hyb_desc(wl, nparticles: int, diag_every: int = 0, sort_every: int = 0, flags: int = 0, n0: float = 1.0):
+    """pic_hyb_desc of a synth.HybridWorkload with `nparticles` beam particles."""
+    return HybDesc(int(wl.n[0]), int(wl.n[1]), float(wl.d[0]), float(wl.d[1]), float(wl.dt), float(wl.nu),
+                   float(n0), float(wl.weight), int(nparticles), int(wl.iters), int(diag_every), int(sort_every),
+                   int(flags))
+
+
+class HybridRun:
+    """A run of the reduced model on the current CUDA (HIP) device: torch
+    buffers owned by this object, torch's current stream.  x, y, ux, uy, uz
+    are host FP64 arrays of the beam particles (ids follow their order)."""
+
+    GROUPS = ("solve", "particle", "nodes", "sort_advance")
+
+    def __init__(self, desc: HybDesc, x, y, ux, uy, uz, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required for the PIC library")
+        self.desc = desc
+        self.n = int(desc.nparticles)
+        self.shape = (int(desc.ny), int(desc.nx))
+        pb, gb = C.c_size_t(), C.c_size_t()
+        _hyb_check(lib().pic_hyb_query(C.byref(desc), C.byref(pb), C.byref(gb)), "pic_hyb_query")
+        dev = torch.device(device if device is not None else "cuda")
+        self._pbuf = torch.empty(int(pb.value), dtype=torch.uint8, device=dev)
+        self._gbuf = torch.empty(int(gb.value), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, ux, uy, uz)]
+        for a in arrs:
+            if a.shape != (self.n,):
+                raise ValueError(f"particle arrays must have shape ({self.n},)")
+        h = C.c_void_p()
+        _hyb_check(lib().pic_hyb_init(C.byref(desc), C.c_void_p(self._pbuf.data_ptr()), int(pb.value),
+                                      C.c_void_p(self._gbuf.data_ptr()), int(gb.value),
+                                      C.c_void_p(self.stream.cuda_stream), *[_ptr(a) for a in arrs], C.byref(h)),
+                   "pic_hyb_init")
+        self.h = h
+
+    @property
+    def device_bytes(self) -> int:
+        return int(self._pbuf.numel() + self._gbuf.numel())
+
+    def step(self, n: int = 1):
+        _hyb_check(lib().pic_hyb_step(self.h, int(n)), "pic_hyb_step", self.h)
+
+    def step_profiled(self, n: int) -> dict:
+        g = (C.c_double * 4)()
+        _hyb_check(lib().pic_hyb_step_profiled(self.h, int(n), g), "pic_hyb_step_profiled", self.h)
+        return {k: g[i] for i, k in enumerate(self.GROUPS)}
+
+    def sync(self):
+        _hyb_check(lib().pic_hyb_sync(self.h), "pic_hyb_sync", self.h)
+
+    def read_grid(self):
+        a = np.empty(self.shape)
+        psi = np.empty(self.shape)
+        _hyb_check(lib().pic_hyb_read_grid(self.h, _ptr(a), _ptr(psi)), "pic_hyb_read_grid", self.h)
+        return a, psi
+
+    def read_particles(self):
+        """(x (2, N), u_perp (2, N), p_z (N,), id (N,)) in storage order."""
+        n = self.n
+        x, y, ux, uy, pz = (np.empty(n) for _ in range(5))
+        ids = np.empty(n, dtype=np.uint32)
+        _hyb_check(lib().pic_hyb_read_particles(self.h, _ptr(x), _ptr(y), _ptr(ux), _ptr(uy), _ptr(pz),
+                                                _ptr(ids)), "pic_hyb_read_particles", self.h)
+        return np.stack([x, y]), np.stack([ux, uy]), pz, ids
+
+    def history(self, max_records: int = 4096) -> list:
+        out = (HybDiag * max_records)()
+        n = C.c_int32()
+        _hyb_check(lib().pic_hyb_diag_history(self.h, out, int(max_records), C.byref(n)), "pic_hyb_diag_history",
+                   self.h)
+        return [out[i].as_dict() for i in range(n.value)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            _hyb_check(lib().pic_hyb_destroy(self.h), "pic_hyb_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -31,15 +31,18 @@ def test_library_exports_every_declared_entry_point():
 def test_ctypes_structs_match_the_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include "pic.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc), sizeof(pic_species_desc),'
-                    'sizeof(pic_sizes), sizeof(pic_buffers), sizeof(pic_diag), offsetof(pic_grid_desc, flags),'
-                    'offsetof(pic_diag, rebins)); return 0;}\n')
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc),'
+                    'sizeof(pic_species_desc), sizeof(pic_sizes), sizeof(pic_buffers), sizeof(pic_diag),'
+                    'offsetof(pic_grid_desc, flags), offsetof(pic_diag, rebins), sizeof(pic_hyb_desc),'
+                    'offsetof(pic_hyb_desc, flags), sizeof(pic_hyb_diag), offsetof(pic_hyb_diag, mean_psi));'
+                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     import ctypes as C
     want = [C.sizeof(pic.GridDesc), C.sizeof(pic.SpeciesDesc), C.sizeof(pic.Sizes), C.sizeof(pic.Buffers),
-            C.sizeof(pic.Diag), pic.GridDesc.flags.offset, pic.Diag.rebins.offset]
+            C.sizeof(pic.Diag), pic.GridDesc.flags.offset, pic.Diag.rebins.offset, C.sizeof(pic.HybDesc),
+            pic.HybDesc.flags.offset, C.sizeof(pic.HybDiag), pic.HybDiag.mean_psi.offset]
     assert got == want
 
 
@@ -133,3 +136,64 @@ def test_checkpoint_entry_points_reject_null_handles(tmp_path):
     p = str(tmp_path / "x.ckpt").encode()
     assert L.pic_checkpoint(None, p) == -1
     assert L.pic_restore(None, p) == -1
+
+
+def _hyb(**kw):
+    d = dict(nx=64, ny=32, dx=0.2, dy=0.2, dt=0.1, nu=0.05, n0=1.0, weight=0.1 / 16, nparticles=64 * 32 * 16,
+             iters=10, diag_every=1, sort_every=0, flags=0)
+    d.update(kw)
+    return pic.HybDesc(*[d[f] for f, _ in pic.HybDesc._fields_])
+
+
+def test_reduced_model_query_sizes():
+    """pic_hyb_query: two particle sets of 5 FP64 + 1 u32 arrays, and the node
+    planes of the grid buffer."""
+    import ctypes as C
+    pb, gb = C.c_size_t(), C.c_size_t()
+    assert pic.lib().pic_hyb_query(C.byref(_hyb()), C.byref(pb), C.byref(gb)) == pic.PIC_OK
+    N, cells = 64 * 32 * 16, 64 * 32
+    assert pb.value >= 2 * N * (5 * 8 + 4)
+    assert pb.value < 2 * N * (5 * 8 + 4) + 12 * 256
+    assert gb.value >= cells * (13 * 8 + 16)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nx", 48, pic.PIC_E_UNSUPPORTED), ("ny", 4, pic.PIC_E_UNSUPPORTED), ("nx", 8192, pic.PIC_E_UNSUPPORTED),
+    ("dx", 0.0, pic.PIC_E_INVALID_ARG), ("dt", -1.0, pic.PIC_E_INVALID_ARG), ("nu", -0.1, pic.PIC_E_INVALID_ARG),
+    ("n0", 0.0, pic.PIC_E_INVALID_ARG), ("iters", 0, pic.PIC_E_INVALID_ARG), ("iters", 65, pic.PIC_E_INVALID_ARG),
+    ("nparticles", -1, pic.PIC_E_INVALID_ARG), ("sort_every", -2, pic.PIC_E_INVALID_ARG),
+    ("flags", 1, pic.PIC_E_INVALID_ARG), ("weight", 1.0, pic.PIC_E_UNSUPPORTED)])
+def test_reduced_model_query_validation(field, value, code):
+    """Invalid descriptors are refused on the host (weight 1 at 16 per cell:
+    mean beam density above n0, no plasma left for quasi-neutrality)."""
+    import ctypes as C
+    pb, gb = C.c_size_t(), C.c_size_t()
+    assert pic.lib().pic_hyb_query(C.byref(_hyb(**{field: value})), C.byref(pb), C.byref(gb)) == code
+    buf = C.create_string_buffer(256)
+    pic.lib().pic_hyb_last_error(None, buf, 256)
+    assert buf.value
+
+
+def test_reduced_model_init_rejects_bad_arguments_on_the_host():
+    """Null buffers, short buffers and particles outside the box are refused
+    before any device work."""
+    import ctypes as C
+    import numpy as np
+    d = _hyb(nparticles=4)
+    h = C.c_void_p()
+    z = np.zeros(4)
+    p = z.ctypes.data_as(C.c_void_p)
+    L = pic.lib()
+    assert L.pic_hyb_init(C.byref(d), None, 0, None, 0, None, p, p, p, p, p, C.byref(h)) == pic.PIC_E_INVALID_ARG
+    fake = C.c_void_p(1 << 40)
+    assert L.pic_hyb_init(C.byref(d), fake, 16, fake, 16, None, p, p, p, p, p, C.byref(h)) == \
+        pic.PIC_E_BUFFER_TOO_SMALL
+    xs = np.array([0.0, 1.0, 64 * 0.2, 2.0])            # x = L_x is outside [0, L_x)
+    big = 1 << 40
+    assert L.pic_hyb_init(C.byref(d), fake, big, fake, big, None, xs.ctypes.data_as(C.c_void_p), p, p, p, p,
+                          C.byref(h)) == pic.PIC_E_INVALID_ARG
+    assert not h.value
+    for fn in ("pic_hyb_step", "pic_hyb_sync"):
+        args = (None, 1) if fn == "pic_hyb_step" else (None,)
+        assert getattr(L, fn)(*args) == pic.PIC_E_INVALID_ARG
+    assert L.pic_hyb_destroy(None) == pic.PIC_OK
