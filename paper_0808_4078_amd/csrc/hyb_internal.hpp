@@ -11,7 +11,7 @@
 namespace hyb {
 
 constexpr int kThreads = 256;
-constexpr int kPartBlocks = 2048;     // particle kernels: fixed grid, grid-stride loop
+constexpr int kPartBlocks = 2048;     // sort kernels: fixed grid, grid-stride loop
 constexpr int kGridBlocks = 1024;     // node-wise kernels: fixed grid, grid-stride loop
 constexpr int kRing = 4096;           // diagnostic records kept on the device
 constexpr int kPDiag = 3;             // per-block particle sums: w gamma, w a^2/2, w u_z
@@ -19,7 +19,11 @@ constexpr int kGDiag = 5;             // per-block node sums: |grad a|^2, a^2, (
 constexpr int kScanChunk = 2048;      // cells per block of the sort's prefix sum
 constexpr int kMaxNodes = 4096;       // nodes per axis
 constexpr int kFftLds = 4096;         // complex values per FFT workgroup (64 KiB of LDS)
-constexpr int kWaveRounds = 4;        // distinct deposit cells merged per wave before plain atomics
+constexpr int kWaveRounds = 8;        // distinct sort keys merged per wave before plain atomics
+constexpr int kMaxTile = 16;          // tile edge (cells) of the particle kernel
+constexpr int kMargin = 2;            // cells of drift since the last sort that the tile's window absorbs
+constexpr int kWin = kMaxTile + 2 * kMargin + 1;   // nodes per axis of a tile's deposit window
+constexpr int kFw = kMaxTile + 2 * kMargin + 4;    // nodes per axis of a tile's field window (gathers)
 
 struct State {
     int64_t step;        // time level n of the next step
@@ -32,9 +36,10 @@ struct State {
 struct Params {
     int nx, ny, lx, ly;            // nodes per axis and their log2
     int iters, diag_every, sort_every, cols_per_block;
+    int tile, ltile, tiles_x, ntiles;  // particle tiles: edge (cells) and its log2, tiles along x, count
     int64_t np;                    // beam macro-particles
     int64_t cells;                 // nx * ny
-    double dx, dy, dt, nu, n0, w, c0, dA, Lx, Ly;
+    double dx, dy, dt, nu, n0, w, c0, dA, Lx, Ly, inv_dx, inv_dy;
     // particles: two sets (the sort writes the other one)
     double *x[2], *y[2], *ux[2], *uy[2], *pz[2];
     uint32_t *id[2];
@@ -47,10 +52,11 @@ struct Params {
     double2 *W;                    // complex FFT plane [ny][nx]
     double2 *twx, *twy;            // exp(-2 pi i t / n), t < n/2
     double *lapx, *lapy;           // (4/d^2) sin^2(pi k / n)
-    int32_t *cell_count;           // [cells] particles per cell (sort)
+    int32_t *cell_count;           // [cells] particles per sort key (tile-major cell index)
     int32_t *cell_start;           // [cells] exclusive prefix, then the scatter cursor
+    int32_t *tile_start;           // [ntiles + 1] first particle of each tile after the last sort
     int32_t *scan_part;            // [ceil(cells / kScanChunk)] chunk sums
-    double *pdiag;                 // [kPartBlocks][kPDiag]
+    double *pdiag;                 // [ntiles][kPDiag]
     double *gdiag;                 // [kGridBlocks][kGDiag]
     State *state;
     pic_hyb_diag *ring;            // [kRing]

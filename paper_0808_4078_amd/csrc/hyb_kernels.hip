@@ -7,7 +7,7 @@
 // x^n, Eq. (6) for u_z, Eq. (4) for u_perp, move, deposit at x^(n+1) with
 // the current linearised about a* = 2 a^n - a^(n-1)); the node kernel
 // (Eq. (3) for psi, a^n -> a^(n-1) -> a^(n-2), diagnostics, clears); the
-// cell sort (every sort_every steps); the bookkeeping kernel.
+// particle sort (every sort_every steps); the bookkeeping kernel.
 #include <hip/hip_ext.h>
 #include <math.h>
 
@@ -79,7 +79,7 @@ struct Cic {
 // Weights of the point (x, y) on a lattice shifted by (shx, shy) cells.
 __device__ __forceinline__ Cic cic(double x, double y, const Params &P, double shx, double shy)
 {
-    const double fx = x / P.dx - shx, fy = y / P.dy - shy;
+    const double fx = x * P.inv_dx - shx, fy = y * P.inv_dy - shy;
     const double flx = floor(fx), fly = floor(fy);
     Cic c;
     c.ox = fx - flx;
@@ -91,33 +91,50 @@ __device__ __forceinline__ Cic cic(double x, double y, const Params &P, double s
     return c;
 }
 
-__device__ __forceinline__ double bilin(const double *__restrict__ F, const Cic &c, int nx)
+// Node addressing of the gathers: the global grid, or a tile's field window
+// in LDS (kFw nodes per axis from (wx, wy); node (i, j) of the grid at
+// ((j - wy) mod ny) kFw + (i - wx) mod nx, valid for the nodes around a
+// particle that lies inside the window).
+struct GlobalNodes {
+    int nx;
+    __device__ __forceinline__ int operator()(int i, int j) const { return j * nx + i; }
+};
+struct WindowNodes {
+    int wx, wy, mx, my;
+    __device__ __forceinline__ int operator()(int i, int j) const
+    {
+        return ((j - wy) & my) * kFw + ((i - wx) & mx);
+    }
+};
+
+template <typename N>
+__device__ __forceinline__ double bilin(const double *__restrict__ F, const Cic &c, const N &at)
 {
-    return (1 - c.ox) * (1 - c.oy) * F[c.j0 * nx + c.i0] + c.ox * (1 - c.oy) * F[c.j0 * nx + c.i1] +
-           (1 - c.ox) * c.oy * F[c.j1 * nx + c.i0] + c.ox * c.oy * F[c.j1 * nx + c.i1];
+    return (1 - c.ox) * (1 - c.oy) * F[at(c.i0, c.j0)] + c.ox * (1 - c.oy) * F[at(c.i1, c.j0)] +
+           (1 - c.ox) * c.oy * F[at(c.i0, c.j1)] + c.ox * c.oy * F[at(c.i1, c.j1)];
 }
 
 // d a/dx at ((i+1/2) dx, j dy), interpolated; c from the lattice shifted by half a cell in x.
-__device__ __forceinline__ double grad_x(const double *__restrict__ a, const Cic &c, const Params &P)
+template <typename N>
+__device__ __forceinline__ double grad_x(const double *__restrict__ a, const Cic &c, const Params &P, const N &at)
 {
-    const int nx = P.nx;
-    const int i0p = wrapi(c.i0 + 1, nx), i1p = wrapi(c.i1 + 1, nx);
-    const double g00 = (a[c.j0 * nx + i0p] - a[c.j0 * nx + c.i0]) / P.dx;
-    const double g10 = (a[c.j0 * nx + i1p] - a[c.j0 * nx + c.i1]) / P.dx;
-    const double g01 = (a[c.j1 * nx + i0p] - a[c.j1 * nx + c.i0]) / P.dx;
-    const double g11 = (a[c.j1 * nx + i1p] - a[c.j1 * nx + c.i1]) / P.dx;
+    const int i0p = wrapi(c.i0 + 1, P.nx), i1p = wrapi(c.i1 + 1, P.nx);
+    const double g00 = (a[at(i0p, c.j0)] - a[at(c.i0, c.j0)]) * P.inv_dx;
+    const double g10 = (a[at(i1p, c.j0)] - a[at(c.i1, c.j0)]) * P.inv_dx;
+    const double g01 = (a[at(i0p, c.j1)] - a[at(c.i0, c.j1)]) * P.inv_dx;
+    const double g11 = (a[at(i1p, c.j1)] - a[at(c.i1, c.j1)]) * P.inv_dx;
     return (1 - c.ox) * (1 - c.oy) * g00 + c.ox * (1 - c.oy) * g10 + (1 - c.ox) * c.oy * g01 + c.ox * c.oy * g11;
 }
 
 // d a/dy at (i dx, (j+1/2) dy), interpolated; c from the lattice shifted by half a cell in y.
-__device__ __forceinline__ double grad_y(const double *__restrict__ a, const Cic &c, const Params &P)
+template <typename N>
+__device__ __forceinline__ double grad_y(const double *__restrict__ a, const Cic &c, const Params &P, const N &at)
 {
-    const int nx = P.nx;
     const int j0p = wrapi(c.j0 + 1, P.ny), j1p = wrapi(c.j1 + 1, P.ny);
-    const double g00 = (a[j0p * nx + c.i0] - a[c.j0 * nx + c.i0]) / P.dy;
-    const double g10 = (a[j0p * nx + c.i1] - a[c.j0 * nx + c.i1]) / P.dy;
-    const double g01 = (a[j1p * nx + c.i0] - a[c.j1 * nx + c.i0]) / P.dy;
-    const double g11 = (a[j1p * nx + c.i1] - a[c.j1 * nx + c.i1]) / P.dy;
+    const double g00 = (a[at(c.i0, j0p)] - a[at(c.i0, c.j0)]) * P.inv_dy;
+    const double g10 = (a[at(c.i1, j0p)] - a[at(c.i1, c.j0)]) * P.inv_dy;
+    const double g01 = (a[at(c.i0, j1p)] - a[at(c.i0, c.j1)]) * P.inv_dy;
+    const double g11 = (a[at(c.i1, j1p)] - a[at(c.i1, c.j1)]) * P.inv_dy;
     return (1 - c.ox) * (1 - c.oy) * g00 + c.ox * (1 - c.oy) * g10 + (1 - c.ox) * c.oy * g01 + c.ox * c.oy * g11;
 }
 
@@ -134,130 +151,227 @@ __device__ __forceinline__ bool sort_step(const Params &P, int64_t step)
     return P.sort_every > 0 && step % P.sort_every == P.sort_every - 1;
 }
 
-// Deposit of four quantities q[k] with CIC weights wt[n] on the four nodes
-// off[n] of each lane's cell `key`.  Lanes of one cell are summed across
-// the wave first (particles are kept in cell order, so a wave usually spans
-// one or a few cells) and the leader adds the sums; after kWaveRounds cells
-// the remaining lanes add their own terms.
-__device__ void deposit_wave(double *const dst[4], bool valid, int key, const int off[4], const double q[4],
-                             const double wt[4])
+// Sort key of cell (i, j): tile-major, then row and column inside the tile.
+__device__ __forceinline__ int sort_key(int i, int j, const Params &P)
 {
-    const int lane = threadIdx.x & 63;
-    uint64_t pend = __ballot(valid);
-    int rounds = 0;
-    while (pend) {
-        if (rounds == kWaveRounds) {
-            if ((pend >> lane) & 1ull) {
+    const int lt = P.ltile, m = P.tile - 1;
+    const int tile = (j >> lt) * P.tiles_x + (i >> lt);
+    return (tile << (2 * lt)) + ((j & m) << lt) + (i & m);
+}
+
+// Adds the four quantities acc[k][n] of one cell's run of particles (node n
+// of cell (i0, j0)) into the tile's LDS window when the cell lies inside it,
+// else straight into the global deposit.
+__device__ __forceinline__ void flush_run(double (*win)[kWin * kWin], double *const *dst, const double acc[4][4],
+                                          int i0, int j0, int wx0, int wy0, const Params &P)
+{
+    const int di = wrapi(i0 - wx0, P.nx), dj = wrapi(j0 - wy0, P.ny);
+    if (di <= kWin - 2 && dj <= kWin - 2) {
+        const int e = dj * kWin + di;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int n = 0; n < 4; ++n) unsafeAtomicAdd(dst[k] + off[n], q[k] * wt[n]);
-            }
-            break;
+        for (int k = 0; k < 4; ++k) {
+            atomicAdd(&win[k][e], acc[k][0]);
+            atomicAdd(&win[k][e + 1], acc[k][1]);
+            atomicAdd(&win[k][e + kWin], acc[k][2]);
+            atomicAdd(&win[k][e + kWin + 1], acc[k][3]);
         }
-        const int leader = __ffsll((unsigned long long)pend) - 1;
-        const int lk = __shfl(key, leader, 64);
-        const bool mine = ((pend >> lane) & 1ull) && key == lk;
-        const uint64_t grp = __ballot(mine);
+    } else {
+        const int i1 = wrapi(i0 + 1, P.nx), j1 = wrapi(j0 + 1, P.ny);
+        const int off[4] = {j0 * P.nx + i0, j0 * P.nx + i1, j1 * P.nx + i0, j1 * P.nx + i1};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const double s = wave_sum(mine ? q[k] * wt[n] : 0.0);
-                if (lane == leader) unsafeAtomicAdd(dst[k] + off[n], s);
-            }
-        pend &= ~grp;
-        ++rounds;
+            for (int n = 0; n < 4; ++n) unsafeAtomicAdd(dst[k] + off[n], acc[k][n]);
     }
 }
 
-// MODE 0: one step of every particle (push, move, deposit at the new
-// position).  MODE 1 (init): deposit the exact current of the given u_z
-// (held in the p_z array).  MODE 2 (init): p_z = u_z - a^0(x), then the
+// Sums of the 16 deposit terms v over each run of consecutive lanes with
+// equal `key`; the first lane of each run (returned true) ends with the
+// run's totals.  Doubling: after the step with distance d, lane i holds the
+// sum over [i, i + 2d) within its run.
+__device__ __forceinline__ bool segment_sums(double v[16], int key)
+{
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(head);
+    const int sid = __popcll(heads & (~0ull >> (63 - lane)));     // run index of this lane
+#pragma unroll 1
+    for (int d = 1; d < 64; d <<= 1) {
+        const int sd = __shfl_down(sid, d, 64);
+        const bool same = lane + d < 64 && sd == sid;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double o = __shfl_down(v[k], d, 64);
+            if (same) v[k] += o;
+        }
+    }
+    return head;
+}
+
+// Gather at x^n (a, psi at the nodes, grad a at the staggered points),
+// Eq. (6) for u_z, Eq. (4) for u_perp, move.
+template <typename N>
+__device__ __forceinline__ void push_particle(const Params &P, const double *an, const double *ps, const N &at,
+                                              double &x, double &y, double &ux, double &uy, double pz, bool diag,
+                                              double dacc[kPDiag])
+{
+    const Cic c = cic(x, y, P, 0.0, 0.0);
+    const double abar = bilin(an, c, at);
+    const double psib = bilin(ps, c, at);
+    const double Gx = grad_x(an, cic(x, y, P, 0.5, 0.0), P, at);
+    const double Gy = grad_y(an, cic(x, y, P, 0.0, 0.5), P, at);
+    const double uz = pz + abar;                                   // Eq. (6)
+    const double gm = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double f = -(uz * (1.0 / gm) - (psib + abar)) * P.dt;    // Eq. (4)
+    ux += f * Gx;
+    uy += f * Gy;
+    const double gp = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double vs = P.dt / gp;
+    x = wrap_pos(x + ux * vs, P.Lx);
+    y = wrap_pos(y + uy * vs, P.Ly);
+    if (!(x >= 0.0 && x < P.Lx && y >= 0.0 && y < P.Ly)) {
+        atomicOr(&P.state->fatal, 1);
+        x = 0.0;
+        y = 0.0;
+    }
+    if (diag) {
+        dacc[0] += P.w * (0.5 * (gm + gp));
+        dacc[1] += P.w * (0.5 * abar * abar);
+        dacc[2] += P.w * uz;
+    }
+}
+
+// Deposit terms of a particle at (x, y): n_b, the beam current at a* and its
+// linear response (MODE 1: the exact current of u_z = pz; MODE 2 first sets
+// p_z = u_z - a^0(x)).
+template <int MODE, typename N>
+__device__ __forceinline__ void deposit_terms(const Params &P, const double *an, const double *aold, const N &at,
+                                              const Cic &c, double ux, double uy, double &pz, double v[16])
+{
+    double beta, chi = 0.0, as = 0.0;
+    if (MODE == 1) {
+        beta = pz / sqrt(1.0 + ux * ux + uy * uy + pz * pz);
+    } else {
+        if (MODE == 2) pz = pz - bilin(an, c, at);
+        as = 2.0 * bilin(an, c, at) - bilin(aold, c, at);              // a* at the particle
+        const double uzs = pz + as;
+        const double up2 = ux * ux + uy * uy;
+        const double g = sqrt(1.0 + up2 + uzs * uzs);
+        const double rg = 1.0 / g;
+        beta = uzs * rg;
+        chi = (1.0 + up2) * (rg * rg * rg);
+    }
+    const double q[4] = {P.w, P.w * beta, P.w * chi, P.w * chi * as};
+    const double wt[4] = {(1 - c.ox) * (1 - c.oy), c.ox * (1 - c.oy), (1 - c.ox) * c.oy, c.ox * c.oy};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) v[4 * k + n] = q[k] * wt[n];
+}
+
+// One workgroup per particle tile: the particles that the last sort placed
+// in tile b (they have drifted by less than kMargin cells since, in
+// practice).  Thread t takes kRun consecutive particles at a time (a run;
+// the lanes' runs are adjacent, so every load instruction of the wave reads
+// one contiguous span).  a^n, a^(n-1) and psi on the tile's field window
+// (kFw nodes per axis) are staged in LDS for the gathers (a particle outside
+// the window gathers from the grid).  The particles are cell-sorted: a run's
+// deposit terms are summed in registers while its cell stays the same, then
+// summed across consecutive lanes of the same cell, and the first lane of
+// each such group adds them to an LDS window of (tile + 2 margin + 1)^2
+// nodes, which is added to the global deposit at the end (atomics:
+// neighbouring windows overlap).
+// MODE 0: one step (gather at x^n, Eqs. (6) and (4), move, deposit at
+// x^(n+1)).  MODE 1 (init): deposit the exact current of the given u_z (held
+// in the p_z array).  MODE 2 (init): p_z = u_z - a^0(x), then the
 // linearised deposit about a^0.
+constexpr int kRun = 4;
+
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict__ pp)
 {
+    __shared__ double win[4][kWin * kWin];
+    __shared__ double fw[3][kFw * kFw];        // a^n, a^(n-1), psi on the field window
     const Params &P = *pp;
     const int64_t step = P.state->step;
     const int cur = P.state->cur;
     const bool diag = MODE == 0 && P.diag_every > 0 && step % P.diag_every == 0;
-    const int nx = P.nx;
+    const int nx = P.nx, ny = P.ny;
     const double *an = MODE == 0 ? P.it[(P.iters - 1) & 1] : P.a1;   // a^n
     const double *aold = MODE == 0 ? P.a1 : P.a2;                     // a^(n-1)
     double *const *dst = MODE == 0 ? P.dep[1 - (int)(step & 1)] : P.dep[0];
     double *X = P.x[cur], *Y = P.y[cur], *UX = P.ux[cur], *UY = P.uy[cur], *PZ = P.pz[cur];
-    double acc[kPDiag] = {0.0, 0.0, 0.0};
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < P.np; base += (int64_t)gridDim.x * kThreads) {
-        const int64_t idx = base + threadIdx.x;
-        const bool valid = idx < P.np;
-        double q[4] = {0.0, 0.0, 0.0, 0.0}, wt[4] = {0.0, 0.0, 0.0, 0.0};
-        int key = 0, off[4] = {0, 0, 0, 0};
-        if (valid) {
+    const int b = blockIdx.x;
+    const int tx0 = (b % P.tiles_x) << P.ltile, ty0 = (b / P.tiles_x) << P.ltile;
+    const int wx0 = tx0 - kMargin, wy0 = ty0 - kMargin;               // deposit window origin
+    const int fx0 = tx0 - kMargin - 1, fy0 = ty0 - kMargin - 1;       // field window origin
+    for (int e = threadIdx.x; e < 4 * kWin * kWin; e += kThreads) (&win[0][0])[e] = 0.0;
+    if (MODE != 1) {
+        for (int e = threadIdx.x; e < kFw * kFw; e += kThreads) {
+            const int node = wrapi(fy0 + e / kFw, ny) * nx + wrapi(fx0 + e % kFw, nx);
+            fw[0][e] = an[node];
+            fw[1][e] = aold[node];
+            fw[2][e] = MODE == 0 ? P.psi[node] : 0.0;
+        }
+    }
+    __syncthreads();
+    const GlobalNodes gn{nx};
+    const WindowNodes wn{fx0, fy0, nx - 1, ny - 1};
+    const int s0 = P.tile_start[b], s1 = P.tile_start[b + 1];
+    double dacc[kPDiag] = {0.0, 0.0, 0.0};
+    for (int base = s0; base < s1; base += kThreads * kRun) {
+        double v[16];
+        int key = -1, ci0 = 0, cj0 = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = 0.0;
+#pragma unroll 1
+        for (int r = 0; r < kRun; ++r) {
+            const int idx = base + (int)threadIdx.x * kRun + r;
+            if (idx >= s1) break;
             double x = X[idx], y = Y[idx], ux = UX[idx], uy = UY[idx], pz = PZ[idx];
             if (MODE == 0) {
-                // gather at x^n: a, psi (nodes), grad a (staggered)
-                const Cic c = cic(x, y, P, 0.0, 0.0);
-                const double abar = bilin(an, c, nx);
-                const double psib = bilin(P.psi, c, nx);
-                const double Gx = grad_x(an, cic(x, y, P, 0.5, 0.0), P);
-                const double Gy = grad_y(an, cic(x, y, P, 0.0, 0.5), P);
-                const double uz = pz + abar;                                   // Eq. (6)
-                const double gm = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-                const double f = -(uz / gm - (psib + abar)) * P.dt;            // Eq. (4)
-                ux += f * Gx;
-                uy += f * Gy;
-                const double gp = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-                x = wrap_pos(x + P.dt * ux / gp, P.Lx);
-                y = wrap_pos(y + P.dt * uy / gp, P.Ly);
-                if (!(x >= 0.0 && x < P.Lx && y >= 0.0 && y < P.Ly)) {
-                    atomicOr(&P.state->fatal, 1);
-                    x = 0.0;
-                    y = 0.0;
-                }
-                if (diag) {
-                    acc[0] += P.w * (0.5 * (gm + gp));
-                    acc[1] += P.w * (0.5 * abar * abar);
-                    acc[2] += P.w * uz;
-                }
+                const int di = wrapi((int)floor(x * P.inv_dx) - fx0, nx), dj = wrapi((int)floor(y * P.inv_dy) - fy0, ny);
+                if (di >= 1 && di <= kFw - 3 && dj >= 1 && dj <= kFw - 3)
+                    push_particle(P, fw[0], fw[2], wn, x, y, ux, uy, pz, diag, dacc);
+                else
+                    push_particle(P, an, P.psi, gn, x, y, ux, uy, pz, diag, dacc);
                 X[idx] = x;
                 Y[idx] = y;
                 UX[idx] = ux;
                 UY[idx] = uy;
             }
             const Cic c = cic(x, y, P, 0.0, 0.0);
-            double beta, chi = 0.0, as = 0.0;
-            if (MODE == 1) {
-                beta = pz / sqrt(1.0 + ux * ux + uy * uy + pz * pz);
-            } else {
-                if (MODE == 2) {
-                    pz = pz - bilin(an, c, nx);
-                    PZ[idx] = pz;
-                }
-                as = 2.0 * bilin(an, c, nx) - bilin(aold, c, nx);              // a* at the particle
-                const double uzs = pz + as;
-                const double up2 = ux * ux + uy * uy;
-                const double g = sqrt(1.0 + up2 + uzs * uzs);
-                beta = uzs / g;
-                chi = (1.0 + up2) / (g * g * g);
+            double vv[16];
+            if (MODE != 1 && wrapi(c.i0 - fx0, nx) <= kFw - 2 && wrapi(c.j0 - fy0, ny) <= kFw - 2)
+                deposit_terms<MODE>(P, fw[0], fw[1], wn, c, ux, uy, pz, vv);
+            else
+                deposit_terms<MODE>(P, an, aold, gn, c, ux, uy, pz, vv);
+            if (MODE == 2) PZ[idx] = pz;
+            const int k2 = c.j0 * nx + c.i0;
+            if (k2 != key) {
+                if (key >= 0) flush_run(win, dst, (const double(*)[4])v, ci0, cj0, wx0, wy0, P);
+                key = k2;
+                ci0 = c.i0;
+                cj0 = c.j0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) v[k] = 0.0;
             }
-            q[0] = P.w;
-            q[1] = P.w * beta;
-            q[2] = P.w * chi;
-            q[3] = P.w * chi * as;
-            wt[0] = (1 - c.ox) * (1 - c.oy);
-            wt[1] = c.ox * (1 - c.oy);
-            wt[2] = (1 - c.ox) * c.oy;
-            wt[3] = c.ox * c.oy;
-            key = c.j0 * nx + c.i0;
-            off[0] = key;
-            off[1] = c.j0 * nx + c.i1;
-            off[2] = c.j1 * nx + c.i0;
-            off[3] = c.j1 * nx + c.i1;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] += vv[k];
         }
-        deposit_wave(dst, valid, key, off, q, wt);
+        if (segment_sums(v, key) && key >= 0) flush_run(win, dst, (const double(*)[4])v, ci0, cj0, wx0, wy0, P);
     }
-    if (diag) block_sums<kPDiag>(acc, P.pdiag + (size_t)blockIdx.x * kPDiag);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kWin * kWin; e += kThreads) {
+        const int node = wrapi(wy0 + e / kWin, ny) * nx + wrapi(wx0 + e % kWin, nx);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double val = win[k][e];
+            if (val != 0.0) unsafeAtomicAdd(dst[k] + node, val);
+        }
+    }
+    if (diag) block_sums<kPDiag>(dacc, P.pdiag + (size_t)b * kPDiag);
 }
 
 // ---- Eq. (2): lap a - (n_p + X) a = J - Y + n_p psi, n_p = max(n0 - n_b, 0);
@@ -409,27 +523,63 @@ __global__ __launch_bounds__(kThreads) void k_init_nodes(const Params *__restric
     }
 }
 
-// ---- cell sort (counting sort by cell into the other particle set)
-__device__ __forceinline__ int cell_of(double x, double y, const Params &P)
+// ---- counting sort of the particles by sort key (tile-major cell order)
+// into the other particle set.  Runs every sort_every steps (and once at
+// initialisation, `force`).
+__device__ __forceinline__ bool sorting(const Params &P, int force)
 {
-    const int i = wrapi((int)floor(x / P.dx), P.nx);
-    const int j = wrapi((int)floor(y / P.dy), P.ny);
-    return j * P.nx + i;
+    return force || sort_step(P, P.state->step);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sort_count(const Params *__restrict__ pp)
+__device__ __forceinline__ int key_of(double x, double y, const Params &P)
+{
+    return sort_key(wrapi((int)floor(x * P.inv_dx), P.nx), wrapi((int)floor(y * P.inv_dy), P.ny), P);
+}
+
+// Each valid lane adds 1 to ctr[key]; lanes of the wave with equal keys add
+// together through one atomic by their leader (the particles are nearly in
+// key order, so a wave holds few keys).  Returns the counter's value before
+// the lane's own increment (its slot).
+__device__ int wave_key_add(int *ctr, bool valid, int key)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pend = __ballot(valid);
+    int slot = -1, rounds = 0;
+    while (pend) {
+        if (rounds == kWaveRounds) {
+            if ((pend >> lane) & 1ull) slot = atomicAdd(ctr + key, 1);
+            break;
+        }
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const uint64_t grp = __ballot(((pend >> lane) & 1ull) && key == lk);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(ctr + lk, __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if ((grp >> lane) & 1ull) slot = base + __popcll(grp & ((1ull << lane) - 1ull));
+        pend &= ~grp;
+        ++rounds;
+    }
+    return slot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_count(const Params *__restrict__ pp, int force)
 {
     const Params &P = *pp;
-    if (!sort_step(P, P.state->step)) return;
+    if (!sorting(P, force)) return;
     const int cur = P.state->cur;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P.np; i += (int64_t)gridDim.x * kThreads)
-        atomicAdd(&P.cell_count[cell_of(P.x[cur][i], P.y[cur][i], P)], 1);
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < P.np; base += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < P.np;
+        const int key = valid ? key_of(P.x[cur][i], P.y[cur][i], P) : 0;
+        (void)wave_key_add(P.cell_count, valid, key);
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_chunks(const Params *__restrict__ pp)
+__global__ __launch_bounds__(kThreads) void k_scan_chunks(const Params *__restrict__ pp, int force)
 {
     const Params &P = *pp;
-    if (!sort_step(P, P.state->step)) return;
+    if (!sorting(P, force)) return;
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
     int s = 0;
     for (int k = threadIdx.x; k < kScanChunk; k += kThreads)
@@ -439,10 +589,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_chunks(const Params *__restri
     if (threadIdx.x == 0) P.scan_part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_top(const Params *__restrict__ pp, int nchunks)
+__global__ __launch_bounds__(kThreads) void k_scan_top(const Params *__restrict__ pp, int nchunks, int force)
 {
     const Params &P = *pp;
-    if (!sort_step(P, P.state->step)) return;
+    if (!sorting(P, force)) return;
     const int per = (nchunks + kThreads - 1) / kThreads;
     const int b = threadIdx.x * per;
     int s = 0;
@@ -456,14 +606,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(const Params *__restrict_
             P.scan_part[b + k] = run;
             run += v;
         }
+    if (threadIdx.x == 0) P.tile_start[P.ntiles] = (int)P.np;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const Params *__restrict__ pp)
+// Exclusive prefix of the counts: the scatter cursor of each key, and the
+// first particle of each tile.
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const Params *__restrict__ pp, int force)
 {
     const Params &P = *pp;
-    if (!sort_step(P, P.state->step)) return;
+    if (!sorting(P, force)) return;
     constexpr int per = kScanChunk / kThreads;
     const int64_t b = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
+    const int tmask = (1 << (2 * P.ltile)) - 1;
     int v[per];
     int s = 0;
 #pragma unroll
@@ -477,29 +631,46 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const Params *__restric
     for (int k = 0; k < per; ++k)
         if (b + k < P.cells) {
             P.cell_start[b + k] = run;
+            if (((b + k) & tmask) == 0) P.tile_start[(b + k) >> (2 * P.ltile)] = run;
             run += v[k];
         }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sort_scatter(const Params *__restrict__ pp)
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const Params *__restrict__ pp, int force)
 {
     const Params &P = *pp;
-    if (!sort_step(P, P.state->step)) return;
+    if (!sorting(P, force)) return;
     const int s = P.state->cur, d = s ^ 1;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P.np; i += (int64_t)gridDim.x * kThreads) {
-        const double x = P.x[s][i], y = P.y[s][i];
-        const int64_t slot = atomicAdd(&P.cell_start[cell_of(x, y, P)], 1);
-        P.x[d][slot] = x;
-        P.y[d][slot] = y;
-        P.ux[d][slot] = P.ux[s][i];
-        P.uy[d][slot] = P.uy[s][i];
-        P.pz[d][slot] = P.pz[s][i];
-        P.id[d][slot] = P.id[s][i];
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < P.np; base += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < P.np;
+        double x = 0.0, y = 0.0;
+        int key = 0;
+        if (valid) {
+            x = P.x[s][i];
+            y = P.y[s][i];
+            key = key_of(x, y, P);
+        }
+        const int slot = wave_key_add(P.cell_start, valid, key);
+        if (valid) {
+            P.x[d][slot] = x;
+            P.y[d][slot] = y;
+            P.ux[d][slot] = P.ux[s][i];
+            P.uy[d][slot] = P.uy[s][i];
+            P.pz[d][slot] = P.pz[s][i];
+            P.id[d][slot] = P.id[s][i];
+        }
     }
 }
 
-// ---- bookkeeping: the diagnostic record (fixed-order sums), the particle
-// set after a sort, the step counter.
+// The sorted set becomes the current one.
+__global__ void k_sort_finish(const Params *__restrict__ pp, int force)
+{
+    const Params &P = *pp;
+    if (threadIdx.x == 0 && sorting(P, force)) P.state->cur ^= 1;
+}
+
+// ---- bookkeeping: the diagnostic record (fixed-order sums) and the step counter.
 __global__ __launch_bounds__(kThreads) void k_advance(const Params *__restrict__ pp)
 {
     const Params &P = *pp;
@@ -509,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_advance(const Params *__restrict__
     if (diag) {
         __shared__ double part[kThreads][kPDiag + kGDiag];
         double s[kPDiag + kGDiag] = {};
-        for (int b = threadIdx.x; b < kPartBlocks; b += kThreads)
+        for (int b = threadIdx.x; b < P.ntiles; b += kThreads)
             for (int k = 0; k < kPDiag; ++k) s[k] += P.pdiag[(size_t)b * kPDiag + k];
         for (int b = threadIdx.x; b < kGridBlocks; b += kThreads)
             for (int k = 0; k < kGDiag; ++k) s[kPDiag + k] += P.gdiag[(size_t)b * kGDiag + k];
@@ -537,10 +708,7 @@ __global__ __launch_bounds__(kThreads) void k_advance(const Params *__restrict__
             S->ring_count = S->ring_count < kRing ? S->ring_count + 1 : kRing;
         }
     }
-    if (threadIdx.x == 0) {
-        if (sort_step(P, step)) S->cur ^= 1;
-        S->step = step + 1;
-    }
+    if (threadIdx.x == 0) S->step = step + 1;
 }
 
 struct Launcher {
@@ -571,32 +739,39 @@ void solve(Launcher &L, const Params &hp, const Params *dp)
 
 int scan_chunks(const Params &hp) { return (int)((hp.cells + kScanChunk - 1) / kScanChunk); }
 
+void sort(Launcher &L, const Params &hp, const Params *dp, int force)
+{
+    const int nch = scan_chunks(hp);
+    L(3, k_sort_count, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    L(3, k_scan_chunks, dim3(nch), dim3(kThreads), 0, dp, force);
+    L(3, k_scan_top, dim3(1), dim3(kThreads), 0, dp, nch, force);
+    L(3, k_scan_apply, dim3(nch), dim3(kThreads), 0, dp, force);
+    L(3, k_sort_scatter, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    L(3, k_sort_finish, dim3(1), dim3(64), 0, dp, force);
+}
+
 }  // namespace
 
 hipError_t launch_init(const Params &hp, const Params *dp, hipStream_t st)
 {
     Launcher L{st, nullptr, nullptr};
-    L(0, k_particle<1>, dim3(kPartBlocks), dim3(kThreads), 0, dp);
+    sort(L, hp, dp, 1);
+    L(0, k_particle<1>, dim3(hp.ntiles), dim3(kThreads), 0, dp);
     solve(L, hp, dp);
     L(0, k_init_nodes, dim3(kGridBlocks), dim3(kThreads), 0, dp);
-    L(0, k_particle<2>, dim3(kPartBlocks), dim3(kThreads), 0, dp);
+    L(0, k_particle<2>, dim3(hp.ntiles), dim3(kThreads), 0, dp);
     return hipGetLastError();
 }
 
-int step_launches(const Params &hp) { return 3 * hp.iters + 8; }
+int step_launches(const Params &hp) { return 3 * hp.iters + 9; }
 
 hipError_t launch_step(const Params &hp, const Params *dp, hipStream_t st, hipEvent_t *ev, int *groups, int *nlaunch)
 {
     Launcher L{st, ev, groups};
     solve(L, hp, dp);
-    L(1, k_particle<0>, dim3(kPartBlocks), dim3(kThreads), 0, dp);
+    L(1, k_particle<0>, dim3(hp.ntiles), dim3(kThreads), 0, dp);
     L(2, k_nodes, dim3(kGridBlocks), dim3(kThreads), 0, dp);
-    const int nch = scan_chunks(hp);
-    L(3, k_sort_count, dim3(kPartBlocks), dim3(kThreads), 0, dp);
-    L(3, k_scan_chunks, dim3(nch), dim3(kThreads), 0, dp);
-    L(3, k_scan_top, dim3(1), dim3(kThreads), 0, dp, nch);
-    L(3, k_scan_apply, dim3(nch), dim3(kThreads), 0, dp);
-    L(3, k_sort_scatter, dim3(kPartBlocks), dim3(kThreads), 0, dp);
+    sort(L, hp, dp, 0);
     L(3, k_advance, dim3(1), dim3(kThreads), 0, dp);
     if (nlaunch) *nlaunch = L.k;
     return hipGetLastError();

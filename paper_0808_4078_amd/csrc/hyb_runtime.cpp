@@ -65,8 +65,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t part_bytes = 0, grid_bytes = 0;
     size_t px[2], py[2], pux[2], puy[2], ppz[2], pid[2];
-    size_t a1, a2, psi, it[2], dep[2][4], W, twx, twy, lapx, lapy, count, start, scan, pdiag, gdiag, state, params,
-        ring;
+    size_t a1, a2, psi, it[2], dep[2][4], W, twx, twy, lapx, lapy, count, start, tstart, scan, pdiag, gdiag, state,
+        params, ring;
 };
 
 struct Carver {
@@ -129,8 +129,11 @@ int validate(const pic_hyb_desc *d, Layout *L, std::string *err)
     L->lapy = g.take((size_t)d->ny * 8);
     L->count = g.take(C * 4);
     L->start = g.take(C * 4);
+    const int T = std::min(kMaxTile, std::min(d->nx, d->ny));
+    const size_t ntiles = C / ((size_t)T * T);
+    L->tstart = g.take((ntiles + 1) * 4);
     L->scan = g.take(((C + kScanChunk - 1) / kScanChunk) * 4);
-    L->pdiag = g.take((size_t)kPartBlocks * kPDiag * 8);
+    L->pdiag = g.take(ntiles * kPDiag * 8);
     L->gdiag = g.take((size_t)kGridBlocks * kGDiag * 8);
     L->state = g.take(sizeof(State));
     L->params = g.take(sizeof(Params));
@@ -230,6 +233,10 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.diag_every = desc->diag_every;
     P.sort_every = desc->sort_every;
     P.cols_per_block = std::min(desc->nx, kFftLds / desc->ny);
+    P.tile = std::min(kMaxTile, std::min(desc->nx, desc->ny));
+    P.ltile = log2_pow2(P.tile);
+    P.tiles_x = desc->nx / P.tile;
+    P.ntiles = (desc->nx / P.tile) * (desc->ny / P.tile);
     P.np = N;
     P.cells = (int64_t)desc->nx * desc->ny;
     P.dx = desc->dx;
@@ -240,6 +247,8 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.w = desc->weight;
     P.c0 = desc->n0 - desc->weight * (double)N / (double)P.cells;
     P.dA = desc->dx * desc->dy;
+    P.inv_dx = 1.0 / desc->dx;
+    P.inv_dy = 1.0 / desc->dy;
     P.Lx = Lx;
     P.Ly = Ly;
     for (int s = 0; s < 2; ++s) {
@@ -263,6 +272,7 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.lapy = at<double>(grid, L.lapy);
     P.cell_count = at<int32_t>(grid, L.count);
     P.cell_start = at<int32_t>(grid, L.start);
+    P.tile_start = at<int32_t>(grid, L.tstart);
     P.scan_part = at<int32_t>(grid, L.scan);
     P.pdiag = at<double>(grid, L.pdiag);
     P.gdiag = at<double>(grid, L.gdiag);
