@@ -24,6 +24,7 @@ constexpr int kMaxTile = 16;          // tile edge (cells) of the particle kerne
 constexpr int kMargin = 2;            // cells of drift since the last sort that the tile's window absorbs
 constexpr int kWin = kMaxTile + 2 * kMargin + 1;   // nodes per axis of a tile's deposit window
 constexpr int kFw = kMaxTile + 2 * kMargin + 4;    // nodes per axis of a tile's field window (gathers)
+constexpr int kWinC = kMaxTile + 2 * kMargin;      // cells per axis of a tile's sort bins
 
 struct State {
     int64_t step;        // time level n of the next step
@@ -54,7 +55,8 @@ struct Params {
     double *lapx, *lapy;           // (4/d^2) sin^2(pi k / n)
     int32_t *cell_count;           // [cells] particles per sort key (tile-major cell index)
     int32_t *cell_start;           // [cells] exclusive prefix, then the scatter cursor
-    int32_t *tile_start;           // [ntiles + 1] first particle of each tile after the last sort
+    int32_t *tile_start[2];        // [ntiles + 1] per particle set: first particle of each tile after the sort
+    int32_t *bins;                 // [ntiles][kWinC^2] particles per cell of each tile's sort window
     int32_t *scan_part;            // [ceil(cells / kScanChunk)] chunk sums
     double *pdiag;                 // [ntiles][kPDiag]
     double *gdiag;                 // [kGridBlocks][kGDiag]

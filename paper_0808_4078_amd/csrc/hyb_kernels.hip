@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict_
     __syncthreads();
     const GlobalNodes gn{nx};
     const WindowNodes wn{fx0, fy0, nx - 1, ny - 1};
-    const int s0 = P.tile_start[b], s1 = P.tile_start[b + 1];
+    const int s0 = P.tile_start[cur][b], s1 = P.tile_start[cur][b + 1];
     double dacc[kPDiag] = {0.0, 0.0, 0.0};
     for (int base = s0; base < s1; base += kThreads * kRun) {
         double v[16];
@@ -524,8 +524,9 @@ __global__ __launch_bounds__(kThreads) void k_init_nodes(const Params *__restric
 }
 
 // ---- counting sort of the particles by sort key (tile-major cell order)
-// into the other particle set.  Runs every sort_every steps (and once at
-// initialisation, `force`).
+// into the other particle set.  Runs every sort_every steps (tile kernels
+// below) and once at initialisation (`force`: the particles are in input
+// order, so the count and scatter run over the whole array).
 __device__ __forceinline__ bool sorting(const Params &P, int force)
 {
     return force || sort_step(P, P.state->step);
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(const Params *__restrict_
             P.scan_part[b + k] = run;
             run += v;
         }
-    if (threadIdx.x == 0) P.tile_start[P.ntiles] = (int)P.np;
+    if (threadIdx.x == 0) P.tile_start[P.state->cur ^ 1][P.ntiles] = (int)P.np;
 }
 
 // Exclusive prefix of the counts: the scatter cursor of each key, and the
@@ -618,6 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const Params *__restric
     constexpr int per = kScanChunk / kThreads;
     const int64_t b = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
     const int tmask = (1 << (2 * P.ltile)) - 1;
+    const int nxt = P.state->cur ^ 1;
     int v[per];
     int s = 0;
 #pragma unroll
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const Params *__restric
     for (int k = 0; k < per; ++k)
         if (b + k < P.cells) {
             P.cell_start[b + k] = run;
-            if (((b + k) & tmask) == 0) P.tile_start[(b + k) >> (2 * P.ltile)] = run;
+            if (((b + k) & tmask) == 0) P.tile_start[nxt][(b + k) >> (2 * P.ltile)] = run;
             run += v[k];
         }
 }
@@ -653,6 +655,107 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Params *__restr
         }
         const int slot = wave_key_add(P.cell_start, valid, key);
         if (valid) {
+            P.x[d][slot] = x;
+            P.y[d][slot] = y;
+            P.ux[d][slot] = P.ux[s][i];
+            P.uy[d][slot] = P.uy[s][i];
+            P.pz[d][slot] = P.pz[s][i];
+            P.id[d][slot] = P.id[s][i];
+        }
+    }
+}
+
+// The regular sort, one workgroup per tile over the particles of the tile's
+// current range (they lie within its kWinC^2-cell window, apart from rare
+// stragglers).  Count: an LDS histogram of the window's cells, added to the
+// global counts; the histogram is kept per tile for the scatter.
+__device__ __forceinline__ int tile_bin(double x, double y, int wcx, int wcy, const Params &P, int *key)
+{
+    const int i = wrapi((int)floor(x * P.inv_dx), P.nx), j = wrapi((int)floor(y * P.inv_dy), P.ny);
+    *key = sort_key(i, j, P);
+    const int di = wrapi(i - wcx, P.nx), dj = wrapi(j - wcy, P.ny);
+    return di < kWinC && dj < kWinC ? dj * kWinC + di : -1;
+}
+
+// Lanes with equal bins add together (one LDS atomic per bin per wave);
+// returns the bin's count before the lane's own increment.
+__device__ int wave_lds_add(int *cnt, bool valid, int bin)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pend = __ballot(valid);
+    int slot = -1;
+    while (pend) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int lb = __shfl(bin, leader, 64);
+        const uint64_t grp = __ballot(((pend >> lane) & 1ull) && bin == lb);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(cnt + lb, __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if ((grp >> lane) & 1ull) slot = base + __popcll(grp & ((1ull << lane) - 1ull));
+        pend &= ~grp;
+    }
+    return slot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_count_tiles(const Params *__restrict__ pp)
+{
+    __shared__ int hist[kWinC * kWinC];
+    const Params &P = *pp;
+    if (!sort_step(P, P.state->step)) return;
+    const int cur = P.state->cur, b = blockIdx.x;
+    const int wcx = ((b % P.tiles_x) << P.ltile) - kMargin, wcy = ((b / P.tiles_x) << P.ltile) - kMargin;
+    for (int e = threadIdx.x; e < kWinC * kWinC; e += kThreads) hist[e] = 0;
+    __syncthreads();
+    const int s0 = P.tile_start[cur][b], s1 = P.tile_start[cur][b + 1];
+    for (int base = s0; base < s1; base += kThreads) {
+        const int i = base + (int)threadIdx.x;
+        const bool valid = i < s1;
+        int key = 0, bin = -1;
+        if (valid) bin = tile_bin(P.x[cur][i], P.y[cur][i], wcx, wcy, P, &key);
+        if (valid && bin < 0) atomicAdd(P.cell_count + key, 1);
+        (void)wave_lds_add(hist, valid && bin >= 0, bin);
+    }
+    __syncthreads();
+    int *keep = P.bins + (size_t)b * kWinC * kWinC;
+    for (int e = threadIdx.x; e < kWinC * kWinC; e += kThreads) {
+        const int c = hist[e];
+        keep[e] = c;
+        if (c) atomicAdd(P.cell_count + sort_key(wrapi(wcx + e % kWinC, P.nx), wrapi(wcy + e / kWinC, P.ny), P), c);
+    }
+}
+
+// Scatter: each non-empty bin reserves its range of its cell's slots with one
+// atomic; particles take consecutive slots of their bin's range.
+__global__ __launch_bounds__(kThreads) void k_sort_scatter_tiles(const Params *__restrict__ pp)
+{
+    __shared__ int hbase[kWinC * kWinC];
+    __shared__ int hcur[kWinC * kWinC];
+    const Params &P = *pp;
+    if (!sort_step(P, P.state->step)) return;
+    const int s = P.state->cur, d = s ^ 1, b = blockIdx.x;
+    const int wcx = ((b % P.tiles_x) << P.ltile) - kMargin, wcy = ((b / P.tiles_x) << P.ltile) - kMargin;
+    const int *keep = P.bins + (size_t)b * kWinC * kWinC;
+    for (int e = threadIdx.x; e < kWinC * kWinC; e += kThreads) {
+        const int c = keep[e];
+        hbase[e] = c ? atomicAdd(P.cell_start + sort_key(wrapi(wcx + e % kWinC, P.nx), wrapi(wcy + e / kWinC, P.ny), P), c)
+                     : 0;
+        hcur[e] = 0;
+    }
+    __syncthreads();
+    const int s0 = P.tile_start[s][b], s1 = P.tile_start[s][b + 1];
+    for (int base = s0; base < s1; base += kThreads) {
+        const int i = base + (int)threadIdx.x;
+        const bool valid = i < s1;
+        double x = 0.0, y = 0.0;
+        int key = 0, bin = -1;
+        if (valid) {
+            x = P.x[s][i];
+            y = P.y[s][i];
+            bin = tile_bin(x, y, wcx, wcy, P, &key);
+        }
+        const int rank = wave_lds_add(hcur, valid && bin >= 0, bin);
+        if (valid) {
+            const int slot = bin >= 0 ? hbase[bin] + rank : atomicAdd(P.cell_start + key, 1);
             P.x[d][slot] = x;
             P.y[d][slot] = y;
             P.ux[d][slot] = P.ux[s][i];
@@ -742,11 +845,13 @@ int scan_chunks(const Params &hp) { return (int)((hp.cells + kScanChunk - 1) / k
 void sort(Launcher &L, const Params &hp, const Params *dp, int force)
 {
     const int nch = scan_chunks(hp);
-    L(3, k_sort_count, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    if (force) L(3, k_sort_count, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    else L(3, k_sort_count_tiles, dim3(hp.ntiles), dim3(kThreads), 0, dp);
     L(3, k_scan_chunks, dim3(nch), dim3(kThreads), 0, dp, force);
     L(3, k_scan_top, dim3(1), dim3(kThreads), 0, dp, nch, force);
     L(3, k_scan_apply, dim3(nch), dim3(kThreads), 0, dp, force);
-    L(3, k_sort_scatter, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    if (force) L(3, k_sort_scatter, dim3(kPartBlocks), dim3(kThreads), 0, dp, force);
+    else L(3, k_sort_scatter_tiles, dim3(hp.ntiles), dim3(kThreads), 0, dp);
     L(3, k_sort_finish, dim3(1), dim3(64), 0, dp, force);
 }
 

@@ -65,8 +65,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t part_bytes = 0, grid_bytes = 0;
     size_t px[2], py[2], pux[2], puy[2], ppz[2], pid[2];
-    size_t a1, a2, psi, it[2], dep[2][4], W, twx, twy, lapx, lapy, count, start, tstart, scan, pdiag, gdiag, state,
-        params, ring;
+    size_t a1, a2, psi, it[2], dep[2][4], W, twx, twy, lapx, lapy, count, start, tstart[2], bins, scan, pdiag, gdiag,
+        state, params, ring;
 };
 
 struct Carver {
@@ -131,7 +131,9 @@ int validate(const pic_hyb_desc *d, Layout *L, std::string *err)
     L->start = g.take(C * 4);
     const int T = std::min(kMaxTile, std::min(d->nx, d->ny));
     const size_t ntiles = C / ((size_t)T * T);
-    L->tstart = g.take((ntiles + 1) * 4);
+    L->tstart[0] = g.take((ntiles + 1) * 4);
+    L->tstart[1] = g.take((ntiles + 1) * 4);
+    L->bins = g.take(ntiles * kWinC * kWinC * 4);
     L->scan = g.take(((C + kScanChunk - 1) / kScanChunk) * 4);
     L->pdiag = g.take(ntiles * kPDiag * 8);
     L->gdiag = g.take((size_t)kGridBlocks * kGDiag * 8);
@@ -272,7 +274,9 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.lapy = at<double>(grid, L.lapy);
     P.cell_count = at<int32_t>(grid, L.count);
     P.cell_start = at<int32_t>(grid, L.start);
-    P.tile_start = at<int32_t>(grid, L.tstart);
+    P.tile_start[0] = at<int32_t>(grid, L.tstart[0]);
+    P.tile_start[1] = at<int32_t>(grid, L.tstart[1]);
+    P.bins = at<int32_t>(grid, L.bins);
     P.scan_part = at<int32_t>(grid, L.scan);
     P.pdiag = at<double>(grid, L.pdiag);
     P.gdiag = at<double>(grid, L.gdiag);
