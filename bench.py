@@ -236,6 +236,67 @@ def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
             "relayouts_total": rebins, "tune_s": tune_s, "init_s": init_s}
 
 
+HYB_SORT_EVERY = 10      # reduced model: particle sort interval (steps)
+
+
+def hybrid_particle_bytes(wl) -> float:
+    """Algorithmic HBM bytes of one launch of the reduced model's particle
+    kernel: x, y, u_x, u_y, p_z read (5 x 8 B) and x, y, u_x, u_y written
+    (4 x 8 B) per particle; per tile, a^n, a^(n-1) and psi read on its
+    field window and the four deposit planes added on its deposit window
+    (counted once per node: 3 + 4 planes of FP64)."""
+    return wl.particles * 72.0 + wl.cells * 7 * 8.0
+
+
+def run_hybrid(steps: int, warmup: int, diag_every: int, prof_steps: int = 20):
+    """The reduced quasi-neutral model (Eqs. 1-7) at the paper's 2D hot-beam
+    collisional parameters on a 1024^2 grid (H2): graph-replayed steps, then
+    kernel-by-kernel steps with events on every launch for the breakdown and
+    the particle kernel's average duration."""
+    import torch
+    import synth
+    from paper_0808_4078_amd import pic
+
+    wl = synth.H2
+    t0 = time.time()
+    x, u, uz = synth.hybrid_load(wl)
+    n = x.shape[1]
+    run = pic.HybridRun(pic.hyb_desc(wl, n, diag_every=diag_every, sort_every=HYB_SORT_EVERY),
+                        x[0], x[1], u[0], u[1], uz)
+    del x, u, uz
+    run.sync()
+    init_s = time.time() - t0
+    progress(f"H2 reduced model: {n} beam particles, initialised in {init_s:.1f} s")
+    run.step(warmup)
+    run.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(run.stream)
+    run.step(steps)
+    e1.record(run.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    groups = run.step_profiled(prof_steps)
+    hist = run.history(8)
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    pk = groups["particle"] / prof_steps
+    nbytes = hybrid_particle_bytes(wl)
+    progress(f"H2 reduced model: {steps} steps {ms / steps:.3f} ms/step, particle kernel {pk:.3f} ms")
+    return {"workload": "H2: the reduced quasi-neutral model (kinetic beam, fluid return current with drag, "
+                        "A_z from Eq. 2 by 10 FFT sweeps), 1024x1024 nodes, dx=0.125, dt=0.0625, 64 beam "
+                        "particles per cell, v_b=0.9c, u_th=0.37, nu=0.15, FP64",
+            "particles": n, "steps": steps, "value": n * steps / (ms * 1e-3), "unit": "particle-steps/s",
+            "ms_per_step": ms / steps, "sort_every": HYB_SORT_EVERY, "iters": wl.iters,
+            "step_breakdown_ms": {k: v / prof_steps for k, v in groups.items()},
+            "particle_kernel": {"ms": pk, "algorithmic_bytes": nbytes,
+                                "GBs": nbytes / (pk * 1e-3) / 1e9,
+                                "frac_of_hbm_peak": nbytes / (pk * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "eq7_last": hist[-1]["eq7"] if hist else None, "init_s": init_s}
+
+
 def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
     """The FP64 oracle on a bounded sample of the workload: a 256 x 256 box
     with the same per-cell load and physics, timed for whole steps until
@@ -278,6 +339,8 @@ def main():
                     help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed; 0 = skip)")
     ap.add_argument("--coulomb", type=int, default=300, metavar="K",
                     help="also time K steps of C3 with the plasma on the Coulomb scattering model (0 = skip)")
+    ap.add_argument("--hybrid", type=int, default=200, metavar="K",
+                    help="also time K steps of the reduced quasi-neutral model on 1024^2 nodes (FP64; 0 = skip)")
     ap.add_argument("--c5", type=int, default=300, metavar="K",
                     help="also time K batch steps of the 256-run 2D ensemble (mixed, autotuned tiles; 0 = skip)")
     a = ap.parse_args()
@@ -369,6 +432,8 @@ def main():
                           "ms_per_step": cm["ms"] / a.coulomb, "particle_kernel_ms": cm_pk,
                           "particle_kernel_GBs": pk_bytes / (cm_pk * 1e-3) / 1e9,
                           "step_breakdown_ms": {k: v / a.coulomb for k, v in cm["groups_ms"].items()}}
+    if a.hybrid > 0:
+        rec["hybrid"] = run_hybrid(a.hybrid, a.warmup, a.diag_every)
     if a.c5 > 0:
         rec["c5"] = run_c5(a.c5, min(a.warmup, 5), a.diag_every)
     if not a.skip_cpu:

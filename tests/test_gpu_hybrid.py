@@ -160,3 +160,66 @@ def test_hybrid_full_size_step_recomputed(pic):
     eu = float(np.max(np.abs(u2[:, j] - un)))
     log(f"  sampled particles: |dx| {ex:.2e} |du| {eu:.2e}")
     assert ex < 1e-10 and eu < 1e-10
+
+
+def test_hybrid_paper_hot_beam_cases(pic):
+    """The paper's hot-beam cases in its own reduced model (the 2D PIC
+    paragraph's parameters on a 128^2 grid of a 20 x 20 c/w_p box: v_b = 0.9c,
+    n_b = 0.1, u_th = 0.37, 64 particles per cell, dt = 0.0625, T = 20 plasma
+    periods): (c) collisionless stays in the noise band, (d) with nu = 0.15
+    grows, at the rate of the model's warm dispersion relation (Eq. (12) with
+    k_pe^2 = n_p and omega_b^2 beta_0^2 = (n_b/gamma)(v_bz - v_pz)^2),
+    evaluated at the beam's u_z through the fit window (the resistive field
+    slows the beam), within the bounds a fluid closure of a kinetic beam
+    allows."""
+    import math
+    log("case hybrid paper cases (c), (d)")
+    N, L, dt = 128, 20.0, 0.0625
+    steps = int(round(20 * 2 * math.pi / dt))
+    u_b = 0.9 / math.sqrt(1 - 0.81)
+    kx = np.fft.fftfreq(N, d=L / N) * 2 * math.pi
+    K = np.sqrt(kx[None, :] ** 2 + kx[:, None] ** 2)
+    shell = np.rint(K / (2 * math.pi / L)).astype(int)
+    out = {}
+    for name, nu in (("c", 0.0), ("d", 0.15)):
+        wl = synth.HybridWorkload(f"paper-{name}", (N, N), (L / N, L / N), dt, steps, 0.1, 64, u_b, 0.37, nu,
+                                  seed=synth.SEED + 7)
+        x, u, uz = synth.hybrid_load(wl)
+        g = pic.HybridRun(pic.hyb_desc(wl, x.shape[1], diag_every=10, sort_every=10), x[0], x[1], u[0], u[1], uz)
+        ts, m1, uzm = [], [], []
+        for s0 in range(0, steps, 50):
+            a, _ = g.read_grid()
+            gx = (np.roll(a, -1, axis=1) - a) / (L / N)
+            gy = (np.roll(a, -1, axis=0) - a) / (L / N)
+            Pk = np.abs(np.fft.fft2(gx)) ** 2 + np.abs(np.fft.fft2(gy)) ** 2
+            m1.append(float(np.sum(Pk[shell == 1])))
+            ts.append(s0 * dt)
+            g.step(min(50, steps - s0))
+        hist = g.history()
+        g.close()
+        t = np.array([h["time"] for h in hist])
+        W = np.array([h["W_Bperp"] for h in hist])
+        uzb = np.array([h["beam_pz"] for h in hist]) / (wl.n_b * L * L)
+        out[name] = dict(ts=np.array(ts), m1=np.array(m1), t=t, W=W, uz=uzb)
+    c, d = out["c"], out["d"]
+    log(f"  W_Bperp end: (c) {c['W'][-1]:.3e} (d) {d['W'][-1]:.3e}; beam u_z (d) {d['uz'][0]:.3f} -> {d['uz'][-1]:.3f}")
+    assert d["W"][-1] > 30 * c["W"][-1]
+    i25, i100 = int(np.argmin(abs(d["t"] - 25))), int(np.argmin(abs(d["t"] - 100)))
+    assert d["W"][i100] > 20 * d["W"][i25]
+    # (c): the noise level creeps up (finite-particle heating) but does not grow exponentially
+    j25, j100 = int(np.argmin(abs(c["t"] - 25))), int(np.argmin(abs(c["t"] - 100)))
+    assert c["W"].max() < 1e-2 and c["W"][j100] < 8 * c["W"][j25]
+    # mode-1 growth of (d) over t = 25..75 against the warm relation along the slowing beam
+    ts, e = d["ts"], d["m1"]
+    i0, i1 = int(np.argmin(abs(ts - 25))), int(np.argmin(abs(ts - 75)))
+    rate = 0.5 * math.log(e[i1] / e[i0]) / (ts[i1] - ts[i0])
+    k1 = 2 * math.pi / L
+    win = (d["t"] >= 25) & (d["t"] <= 75)
+    want = []
+    for v in d["uz"][win]:
+        gam = math.sqrt(1 + v * v)
+        bbar = v / gam * (1 + 0.1 / 0.9)
+        want.append(theory.warm_beam_growth(k1, 3 * (0.37 / gam) ** 2, 0.1 / gam * bbar ** 2, 0.15, kpe2=0.9))
+    want = float(np.mean(want))
+    log(f"  (d) mode-1 growth {rate:.4f}, warm relation along the beam {want:.4f}")
+    assert 0.6 * want < rate < 1.6 * want
