@@ -64,8 +64,10 @@ enum {
     PIC_FLAG_LATTICE_LOAD = 4u,   /* device loader: regular sub-lattice positions */
     PIC_FLAG_HOST_LOAD = 8u,      /* do not load on the device; caller calls pic_load_particles */
     PIC_FLAG_NO_GRAPH = 16u,      /* launch kernels one by one instead of replaying a graph */
-    PIC_FLAG_TRACK_IDS = 32u      /* carry particle ids for every species (by default only
+    PIC_FLAG_TRACK_IDS = 32u,     /* carry particle ids for every species (by default only
                                      collisional species, whose draws are keyed by id, do) */
+    PIC_FLAG_GAUSS_RESIDUAL = 64u /* at step 0 and on diagnostic steps, deposit the particles'
+                                     charge and record Gauss's-law residuals (single runs only) */
 };
 
 #define PIC_MAX_SPECIES 8
@@ -165,7 +167,13 @@ typedef struct {
  *   p_field_z      dV sum (E x B)_z.
  *   collisions     scattering events during the step.
  *   n_particles[s] particles of species s.
- *   rebins         particle-store re-layouts performed so far. */
+ *   rebins         particle-store re-layouts performed so far.
+ *   gauss_resid    with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
+ *                  |div E - (rho - rho_0)| at the step, rho the CIC charge
+ *                  of the particles on the nodes, rho_0 that of step 0 (the
+ *                  immobile ions carry -rho_0); -1 when not computed.
+ *   rho_dev        with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
+ *                  |rho - rho_0| (the scale of the residual); -1 otherwise. */
 typedef struct {
     int64_t step;
     double time;
@@ -176,6 +184,8 @@ typedef struct {
     int64_t collisions;
     int64_t n_particles[PIC_MAX_SPECIES];
     int64_t rebins;
+    double gauss_resid;
+    double rho_dev;
 } pic_diag;
 
 typedef struct pic_run pic_run;

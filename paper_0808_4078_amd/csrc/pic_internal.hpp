@@ -111,6 +111,9 @@ struct KParams {
     uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
     double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
     int32_t coulomb;     // 1 if a species scatters with the Coulomb model (selects the particle kernel)
+    double *rho_tile;    // [tiles][(T+1)^ndim] per-tile charge partials (Gauss-law check)
+    double *rho0;        // [cells] charge on the nodes at step 0
+    double *gauss_part;  // [ceil(cells / 256)][2] per-block maxima of the residual and of |rho - rho0|
 };
 
 // An ensemble of runs stepped together: every launch of a step covers all
@@ -148,6 +151,10 @@ constexpr int kBatchRebinBlocks = 256;
 constexpr int kNumGroups = 6;
 constexpr int kStepKernels = 13;
 constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
+// With PIC_FLAG_GAUSS_RESIDUAL the step starts with the charge deposit and
+// the residual reduction (counted with the field diagnostics).
+constexpr int kGaussStepKernels = kStepKernels + 2;
+constexpr int kKernelGroupGauss[kGaussStepKernels] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
 // ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
 // Batch step: the particle kernel is one launch per tile group (empty groups

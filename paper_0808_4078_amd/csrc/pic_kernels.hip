@@ -983,6 +983,154 @@ __device__ __forceinline__ int tile_of(const KParams *kp, const SpeciesDev &S, i
     return t;
 }
 
+// ---- Gauss's-law check (PIC_FLAG_GAUSS_RESIDUAL): at step 0 and on
+// diagnostic steps, the CIC charge of the particles at the start of the
+// step, one workgroup per tile into an LDS tile of (T+1)^D nodes (a tile's
+// particles have their cells in the tile), written as the tile's partial;
+// then per node: the partials' sum rho, div E of the fields at the start of
+// the step, and the maxima of |div E - (rho - rho_0)| and |rho - rho_0|.
+template <typename KP>
+__device__ __forceinline__ bool gauss_step(KP kp, int64_t step)
+{
+    return (kp->flags & PIC_FLAG_GAUSS_RESIDUAL) && (step == 0 || diag_step(kp, step));
+}
+
+template <typename R, int D, int T>
+__global__ __launch_bounds__(256) void k_rho(const KParams *__restrict__ kp)
+{
+    constexpr int N1 = T + 1;
+    constexpr int ND = D == 3 ? N1 * N1 * N1 : N1 * N1;
+    __shared__ double srho[ND];
+    const int64_t step = kp->state->step;
+    if (!gauss_step(kp, step)) return;
+    const int tile = blockIdx.x, ntiles = kp->g.ntiles, par = kp->state->par;
+    const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
+    const int t0[3] = {(tile % ntx) * T, ((tile / ntx) % nty) * T, (tile / (ntx * nty)) * T};
+    for (int e = threadIdx.x; e < ND; e += blockDim.x) srho[e] = 0.0;
+    __syncthreads();
+    for (int s = 0; s < kp->nspecies; ++s) {
+        const SpeciesDev &S = kp->sp[s];
+        const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
+        const int64_t b0 = S.start[tile], cap = S.cap[tile];
+        const double qw = S.qw;
+        for (int64_t k = threadIdx.x; k < nf + nb; k += blockDim.x) {
+            const int64_t slot = k < nf ? b0 + k : b0 + cap - nb + (k - nf);
+            int l[3] = {0, 0, 0};
+            double o[3] = {0.0, 0.0, 0.0};
+            bool inside = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int ic;
+                if constexpr (sizeof(R) == 4) {
+                    ic = (int)((S.cell[par][slot] >> kp->g.csh[a]) & kp->g.cmask[a]);
+                    o[a] = (double)((const float *)S.pos[par][a])[slot];
+                } else {
+                    const double X = ((const double *)S.pos[par][a])[slot];
+                    ic = (int)floor(X);
+                    o[a] = X - ic;
+                }
+                l[a] = ic - t0[a];
+                inside = inside && l[a] >= 0 && l[a] < T;
+            }
+            if (!inside) {
+                atomicOr(&kp->state->fatal, 8);
+                continue;
+            }
+#pragma unroll
+            for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx) {
+                        double w = (dx ? o[0] : 1.0 - o[0]) * (dy ? o[1] : 1.0 - o[1]);
+                        if (D == 3) w *= dz ? o[2] : 1.0 - o[2];
+                        atomicAdd(&srho[((l[2] + dz) * N1 + l[1] + dy) * N1 + l[0] + dx], qw * w);
+                    }
+        }
+    }
+    __syncthreads();
+    double *out = kp->rho_tile + (int64_t)tile * ND;
+    for (int e = threadIdx.x; e < ND; e += blockDim.x) out[e] = srho[e];
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_gauss(const KParams *__restrict__ kp)
+{
+    __shared__ double sred[4][2];
+    const int64_t step = kp->state->step;
+    if (!gauss_step(kp, step)) return;
+    const int64_t cells = kp->g.cells;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m[2] = {0.0, 0.0};
+    if (o < cells) {
+        const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
+        const int idx[3] = {(int)(o % n[0]), (int)((o / n[0]) % n[1]), (int)(o / ((int64_t)n[0] * n[1]))};
+        const int T = kp->g.tile[0], N1 = T + 1;
+        const int64_t ND = D == 3 ? (int64_t)N1 * N1 * N1 : (int64_t)N1 * N1;
+        double rho = 0.0;
+        // a node belongs to its own tile (local index i mod T) and, on a tile
+        // edge, to the tile below (local index T)
+        for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz) {
+            int tz = 0, lz = 0;
+            if (D == 3) {
+                tz = idx[2] / T;
+                lz = idx[2] - tz * T;
+                if (cz) {
+                    if (lz) continue;
+                    tz = tz ? tz - 1 : kp->g.nt[2] - 1;
+                    lz = T;
+                }
+            }
+            for (int cy = 0; cy < 2; ++cy) {
+                int ty = idx[1] / T, ly = idx[1] - (idx[1] / T) * T;
+                if (cy) {
+                    if (ly) continue;
+                    ty = ty ? ty - 1 : kp->g.nt[1] - 1;
+                    ly = T;
+                }
+                for (int cx = 0; cx < 2; ++cx) {
+                    int tx = idx[0] / T, lx = idx[0] - (idx[0] / T) * T;
+                    if (cx) {
+                        if (lx) continue;
+                        tx = tx ? tx - 1 : kp->g.nt[0] - 1;
+                        lx = T;
+                    }
+                    const int64_t t = ((int64_t)tz * kp->g.nt[1] + ty) * kp->g.nt[0] + tx;
+                    rho += kp->rho_tile[t * ND + ((int64_t)lz * N1 + ly) * N1 + lx];
+                }
+            }
+        }
+        if (step == 0) kp->rho0[o] = rho;
+        const double dev = rho - kp->rho0[o];
+        // div E on the node: E_a is stored at the lower node of its half-integer point
+        const R *F = (const R *)kp->F;
+        double div = 0.0;
+        for (int a = 0; a < D; ++a) {
+            int im[3] = {idx[0], idx[1], idx[2]};
+            im[a] = idx[a] ? idx[a] - 1 : n[a] - 1;
+            const int64_t om = ((int64_t)im[2] * n[1] + im[1]) * n[0] + im[0];
+            const R *Ea = F + (int64_t)a * cells;
+            div += ((double)Ea[o] - (double)Ea[om]) / kp->g.d[a];
+        }
+        m[0] = fabs(div - dev);
+        m[1] = fabs(dev);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        double x = m[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+        if (lane == 0) sred[wave][i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double x = sred[0][threadIdx.x];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = fmax(x, sred[w][threadIdx.x]);
+        kp->gauss_part[2 * (int64_t)blockIdx.x + threadIdx.x] = x;
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void rebin_count_ovf_body(const KParams *__restrict__ kp, int bid, int nb)
 {
@@ -1321,7 +1469,32 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
                 coll_total += a[5];
             }
         }
+        double gm[2] = {-1.0, -1.0};
+        if (gauss_step(kp, step)) {
+            const int64_t nbk = (kp->g.cells + 255) / 256;
+            gm[0] = gm[1] = 0.0;
+            for (int64_t b = threadIdx.x; b < nbk; b += blockDim.x) {
+                gm[0] = fmax(gm[0], kp->gauss_part[2 * b]);
+                gm[1] = fmax(gm[1], kp->gauss_part[2 * b + 1]);
+            }
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int i = 0; i < 2; ++i) {
+                double x = gm[i];
+                for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+                if (lane == 0) sred[wave][i] = x;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int i = 0; i < 2; ++i) {
+                    double x = sred[0][i];
+                    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = fmax(x, sred[w][i]);
+                    gm[i] = x;
+                }
+            __syncthreads();
+        }
         if (threadIdx.x == 0) {
+            rec.gauss_resid = gm[0];
+            rec.rho_dev = gm[1];
             for (int s = ns; s < kMaxSpecies; ++s) { rec.kinetic[s] = 0.0; rec.n_particles[s] = 0; }
             for (int c = 0; c < 3; ++c) rec.p_particles[c] = pp[c];
             rec.collisions = (int64_t)coll_total;
@@ -1680,6 +1853,10 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     const unsigned cb = (unsigned)((cells + 255) / 256);
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
     Launcher L{st, ev};
+    if (hp.flags & PIC_FLAG_GAUSS_RESIDUAL) {
+        L(k_rho<R, D, T>, dim3(ntiles), dim3(256), dp);
+        L(k_gauss<R, D>, dim3(cb), dim3(256), dp);
+    }
     L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
     if (hp.coulomb) L(k_particle<R, A, D, T, true>, dim3(ntiles), dim3(kBlock), dp);
     else L(k_particle<R, A, D, T, false>, dim3(ntiles), dim3(kBlock), dp);

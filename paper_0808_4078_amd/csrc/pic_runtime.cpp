@@ -34,6 +34,7 @@ struct Layout {
     } sp[kMaxSpecies];
     size_t F, J;                                            // field buffer
     size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4], order, bucket;   // scratch
+    size_t rho_tile, rho0, gauss_part;                      // scratch (Gauss-law check)
     Geometry g;
     int nj;
     size_t real;                                            // sizeof(float|double)
@@ -197,6 +198,11 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         for (int i = 0; i < 4; ++i) L->rb[i] = c.take((size_t)ns * G.ntiles * 4);
         L->order = c.take((size_t)G.ntiles * 4);
         L->bucket = c.take((size_t)G.ntiles);
+        int64_t n1 = 1;
+        for (int a = 0; a < g->ndim; ++a) n1 *= G.tile[0] + 1;
+        L->rho_tile = c.take((size_t)G.ntiles * n1 * 8);
+        L->rho0 = c.take((size_t)G.cells * 8);
+        L->gauss_part = c.take((size_t)((G.cells + 255) / 256) * 2 * 8);
         L->scratch_bytes = c.off;
     }
     L->diag_bytes = align256(sizeof(pic_diag) * kRing);
@@ -291,6 +297,7 @@ int check_fatal(pic_run *r, const DevState &st)
     if (st.fatal & 1) { r->err = "particle overflow list exhausted"; return PIC_E_CAPACITY; }
     if (st.fatal & 4) { r->err = "particle store reserve exhausted"; return PIC_E_CAPACITY; }
     if (st.fatal & 2) { r->err = "particle left the grid (corrupt state)"; return PIC_E_HIP; }
+    if (st.fatal & 8) { r->err = "particle outside its tile's bin (corrupt state)"; return PIC_E_HIP; }
     return PIC_OK;
 }
 
@@ -421,6 +428,8 @@ int batch_layout(int nruns, pic_run *const *runs, BatchLayout *B, std::string *e
         if (!r) return fail(err, PIC_E_INVALID_ARG, "run %d is NULL", i);
         if (r->grid.precision != runs[0]->grid.precision || r->grid.ndim != runs[0]->grid.ndim)
             return fail(err, PIC_E_UNSUPPORTED, "run %d: members must share precision and ndim", i);
+        if (r->grid.flags & PIC_FLAG_GAUSS_RESIDUAL)
+            return fail(err, PIC_E_UNSUPPORTED, "run %d: PIC_FLAG_GAUSS_RESIDUAL is for single runs", i);
         for (int j = 0; j < i; ++j)
             if (runs[j] == r) return fail(err, PIC_E_INVALID_ARG, "run %d listed twice", i);
         ncb += (r->L.g.cells + 255) / 256;
@@ -651,6 +660,9 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
     K.order = (int32_t *)at(buffers->scratch, L.order);
     K.tile_bucket = (uint8_t *)at(buffers->scratch, L.bucket);
+    K.rho_tile = (double *)at(buffers->scratch, L.rho_tile);
+    K.rho0 = (double *)at(buffers->scratch, L.rho0);
+    K.gauss_part = (double *)at(buffers->scratch, L.gauss_part);
     {
         int64_t per_tile = 0;
         for (int s = 0; s < nspecies; ++s) per_tile += L.sp[s].tile_nominal;
@@ -832,7 +844,9 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
     if (!r || !group_ms) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
     if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
     if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; step the batch");
-    return profiled_steps(&r->err, r->stream, nsteps, kStepKernels, kKernelGroup, group_ms, [&](hipEvent_t *ev) {
+    const bool gauss = (r->hp.flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
+    return profiled_steps(&r->err, r->stream, nsteps, gauss ? kGaussStepKernels : kStepKernels,
+                          gauss ? kKernelGroupGauss : kKernelGroup, group_ms, [&](hipEvent_t *ev) {
         hipError_t e = launch_step(r->hp, r->dp, r->stream, ev);
         if (e == hipSuccess) r->steps_enqueued += 1;
         return e;

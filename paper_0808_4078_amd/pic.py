@@ -33,6 +33,7 @@ PIC_FLAG_LATTICE_LOAD = 4
 PIC_FLAG_HOST_LOAD = 8
 PIC_FLAG_NO_GRAPH = 16
 PIC_FLAG_TRACK_IDS = 32
+PIC_FLAG_GAUSS_RESIDUAL = 64
 MAX_SPECIES = 8
 
 STATUS = {0: "PIC_OK", -1: "PIC_E_INVALID_ARG", -2: "PIC_E_UNSUPPORTED", -3: "PIC_E_CFL",
@@ -66,13 +67,15 @@ class Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("time", C.c_double), ("W", C.c_double * 6),
                 ("kinetic", C.c_double * MAX_SPECIES), ("p_particles", C.c_double * 3),
                 ("p_field_z", C.c_double), ("collisions", C.c_int64),
-                ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64)]
+                ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64), ("gauss_resid", C.c_double),
+                ("rho_dev", C.c_double)]
 
     def as_dict(self, ns: int) -> dict:
         return dict(step=int(self.step), time=float(self.time), W=np.array(self.W[:]),
                     kinetic=np.array(self.kinetic[:ns]), p_particles=np.array(self.p_particles[:]),
                     p_field_z=float(self.p_field_z), collisions=int(self.collisions),
-                    n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins))
+                    n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins),
+                    gauss_resid=float(self.gauss_resid), rho_dev=float(self.rho_dev))
 
 
 class PicError(RuntimeError):
