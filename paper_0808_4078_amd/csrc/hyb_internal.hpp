@@ -19,6 +19,7 @@ constexpr int kGDiag = 5;             // per-block node sums: |grad a|^2, a^2, (
 constexpr int kScanChunk = 2048;      // cells per block of the sort's prefix sum
 constexpr int kMaxNodes = 4096;       // nodes per axis
 constexpr int kFftLds = 4096;         // complex values per FFT workgroup (64 KiB of LDS)
+constexpr int kColThreads = 1024;     // threads of a column-transform workgroup (few workgroups: latency hiding)
 constexpr int kWaveRounds = 8;        // distinct sort keys merged per wave before plain atomics
 constexpr int kMaxTile = 16;          // tile edge (cells) of the particle kernel
 constexpr int kMargin = 2;            // cells of drift since the last sort that the tile's window absorbs
@@ -48,7 +49,8 @@ struct Params {
     double *a1;                    // a^(n-1): the last solved potential
     double *a2;                    // a^(n-2)
     double *psi;                   // plasma canonical momentum beta_pz - a
-    double *it[2];                 // solve iterates (it[(iters-1) & 1] holds a^n after the solve)
+    double *it[2];                 // solve result (it[(iters-1) & 1] holds a^n after the solve)
+    double *rhsR, *rhsC;           // per step: J - Y + n_p psi, and n_p + X - c0 (the sweeps' coefficients)
     double *dep[2][4];             // deposit sets: n_b, J at a*, chi, chi a*
     double2 *W;                    // complex FFT plane [ny][nx]
     double2 *twx, *twy;            // exp(-2 pi i t / n), t < n/2

@@ -2,8 +2,9 @@
 // paper, Eqs. 1-7), FP64, for gfx950.
 //
 // A step (time level n): the Eq. (2) solve for a^n from the deposit made at
-// x^n (iters x [row FFT, column FFT + inverse symbol + inverse column FFT,
-// inverse row FFT]); the particle kernel (gather a^n, grad a^n and psi^n at
+// x^n (a row transform, then per sweep: column transform + inverse symbol +
+// inverse column transform, and the inverse row transform fused with the
+// next sweep's row transform); the particle kernel (gather a^n, grad a^n and psi^n at
 // x^n, Eq. (6) for u_z, Eq. (4) for u_perp, move, deposit at x^(n+1) with
 // the current linearised about a* = 2 a^n - a^(n-1)); the node kernel
 // (Eq. (3) for psi, a^n -> a^(n-1) -> a^(n-2), diagnostics, clears); the
@@ -210,17 +211,44 @@ __device__ __forceinline__ bool segment_sums(double v[16], int key)
 }
 
 // Gather at x^n (a, psi at the nodes, grad a at the staggered points),
-// Eq. (6) for u_z, Eq. (4) for u_perp, move.
+// Eq. (6) for u_z, Eq. (4) for u_perp, move.  The three stencils share
+// nodes: bilinear a on the cell's 4 nodes, d a/dx on 3 columns x the cell's
+// 2 rows, d a/dy on the cell's 2 columns x 3 rows -- 8 distinct nodes, each
+// loaded once (the staggered lattices' first column / row is the cell's or
+// the one before it).
 template <typename N>
 __device__ __forceinline__ void push_particle(const Params &P, const double *an, const double *ps, const N &at,
                                               double &x, double &y, double &ux, double &uy, double pz, bool diag,
                                               double dacc[kPDiag])
 {
     const Cic c = cic(x, y, P, 0.0, 0.0);
-    const double abar = bilin(an, c, at);
+    const Cic cx = cic(x, y, P, 0.5, 0.0);
+    const Cic cy = cic(x, y, P, 0.0, 0.5);
+    const int nx = P.nx, ny = P.ny;
+    const double a00 = an[at(c.i0, c.j0)], a10 = an[at(c.i1, c.j0)];
+    const double a01 = an[at(c.i0, c.j1)], a11 = an[at(c.i1, c.j1)];
+    // x: the staggered lattice starts at the cell's column (hx) or the one before
+    const bool hx = cx.i0 == c.i0;
+    const int xe = hx ? wrapi(c.i0 + 2, nx) : cx.i0;
+    const double e0 = an[at(xe, c.j0)], e1 = an[at(xe, c.j1)];
+    const double gA0 = hx ? (a10 - a00) * P.inv_dx : (a00 - e0) * P.inv_dx;
+    const double gB0 = hx ? (e0 - a10) * P.inv_dx : (a10 - a00) * P.inv_dx;
+    const double gA1 = hx ? (a11 - a01) * P.inv_dx : (a01 - e1) * P.inv_dx;
+    const double gB1 = hx ? (e1 - a11) * P.inv_dx : (a11 - a01) * P.inv_dx;
+    const bool hy = cy.j0 == c.j0;
+    const int ye = hy ? wrapi(c.j0 + 2, ny) : cy.j0;
+    const double f0 = an[at(c.i0, ye)], f1 = an[at(c.i1, ye)];
+    const double hA0 = hy ? (a01 - a00) * P.inv_dy : (a00 - f0) * P.inv_dy;
+    const double hB0 = hy ? (f0 - a01) * P.inv_dy : (a01 - a00) * P.inv_dy;
+    const double hA1 = hy ? (a11 - a10) * P.inv_dy : (a10 - f1) * P.inv_dy;
+    const double hB1 = hy ? (f1 - a11) * P.inv_dy : (a11 - a10) * P.inv_dy;
+    const double abar = (1 - c.ox) * (1 - c.oy) * a00 + c.ox * (1 - c.oy) * a10 + (1 - c.ox) * c.oy * a01 +
+                        c.ox * c.oy * a11;
     const double psib = bilin(ps, c, at);
-    const double Gx = grad_x(an, cic(x, y, P, 0.5, 0.0), P, at);
-    const double Gy = grad_y(an, cic(x, y, P, 0.0, 0.5), P, at);
+    const double Gx = (1 - cx.ox) * (1 - cx.oy) * gA0 + cx.ox * (1 - cx.oy) * gB0 + (1 - cx.ox) * cx.oy * gA1 +
+                      cx.ox * cx.oy * gB1;
+    const double Gy = (1 - cy.ox) * (1 - cy.oy) * hA0 + cy.ox * (1 - cy.oy) * hA1 + (1 - cy.ox) * cy.oy * hB0 +
+                      cy.ox * cy.oy * hB1;
     const double uz = pz + abar;                                   // Eq. (6)
     const double gm = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
     const double f = -(uz * (1.0 / gm) - (psib + abar)) * P.dt;    // Eq. (4)
@@ -242,19 +270,37 @@ __device__ __forceinline__ void push_particle(const Params &P, const double *an,
     }
 }
 
+// a* = 2 a^n - a^(n-1) at a particle: from the staged a* plane (LDS window),
+// or from the grid node by node (the same arithmetic).
+struct StarWindow {
+    const double *astar;
+    WindowNodes at;
+    __device__ __forceinline__ double operator()(const Cic &c) const { return bilin(astar, c, at); }
+};
+struct StarGrid {
+    const double *an, *aold;
+    GlobalNodes at;
+    __device__ __forceinline__ double node(int i, int j) const { return 2.0 * an[at(i, j)] - aold[at(i, j)]; }
+    __device__ __forceinline__ double operator()(const Cic &c) const
+    {
+        return (1 - c.ox) * (1 - c.oy) * node(c.i0, c.j0) + c.ox * (1 - c.oy) * node(c.i1, c.j0) +
+               (1 - c.ox) * c.oy * node(c.i0, c.j1) + c.ox * c.oy * node(c.i1, c.j1);
+    }
+};
+
 // Deposit terms of a particle at (x, y): n_b, the beam current at a* and its
 // linear response (MODE 1: the exact current of u_z = pz; MODE 2 first sets
-// p_z = u_z - a^0(x)).
-template <int MODE, typename N>
-__device__ __forceinline__ void deposit_terms(const Params &P, const double *an, const double *aold, const N &at,
-                                              const Cic &c, double ux, double uy, double &pz, double v[16])
+// p_z = u_z - a^0(x), where a* = a^0).
+template <int MODE, typename S>
+__device__ __forceinline__ void deposit_terms(const Params &P, const S &star, const Cic &c, double ux, double uy,
+                                              double &pz, double v[16])
 {
     double beta, chi = 0.0, as = 0.0;
     if (MODE == 1) {
         beta = pz / sqrt(1.0 + ux * ux + uy * uy + pz * pz);
     } else {
-        if (MODE == 2) pz = pz - bilin(an, c, at);
-        as = 2.0 * bilin(an, c, at) - bilin(aold, c, at);              // a* at the particle
+        as = star(c);                                                  // a* at the particle
+        if (MODE == 2) pz = pz - as;
         const double uzs = pz + as;
         const double up2 = ux * ux + uy * uy;
         const double g = sqrt(1.0 + up2 + uzs * uzs);
@@ -292,7 +338,7 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict__ pp)
 {
     __shared__ double win[4][kWin * kWin];
-    __shared__ double fw[3][kFw * kFw];        // a^n, a^(n-1), psi on the field window
+    __shared__ double fw[3][kFw * kFw];        // a^n, a* = 2 a^n - a^(n-1), psi on the field window
     const Params &P = *pp;
     const int64_t step = P.state->step;
     const int cur = P.state->cur;
@@ -311,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict_
         for (int e = threadIdx.x; e < kFw * kFw; e += kThreads) {
             const int node = wrapi(fy0 + e / kFw, ny) * nx + wrapi(fx0 + e % kFw, nx);
             fw[0][e] = an[node];
-            fw[1][e] = aold[node];
+            fw[1][e] = 2.0 * an[node] - aold[node];
             fw[2][e] = MODE == 0 ? P.psi[node] : 0.0;
         }
     }
@@ -344,9 +390,9 @@ __global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict_
             const Cic c = cic(x, y, P, 0.0, 0.0);
             double vv[16];
             if (MODE != 1 && wrapi(c.i0 - fx0, nx) <= kFw - 2 && wrapi(c.j0 - fy0, ny) <= kFw - 2)
-                deposit_terms<MODE>(P, fw[0], fw[1], wn, c, ux, uy, pz, vv);
+                deposit_terms<MODE>(P, StarWindow{fw[1], wn}, c, ux, uy, pz, vv);
             else
-                deposit_terms<MODE>(P, an, aold, gn, c, ux, uy, pz, vv);
+                deposit_terms<MODE>(P, StarGrid{an, aold, gn}, c, ux, uy, pz, vv);
             if (MODE == 2) PZ[idx] = pz;
             const int k2 = c.j0 * nx + c.i0;
             if (k2 != key) {
@@ -405,23 +451,54 @@ __device__ void fft_lds(double2 *z, int logn, int batch, const double2 *__restri
     }
 }
 
-// Row transform of the sweep's right-hand side (one workgroup per row).
-__global__ __launch_bounds__(kThreads) void k_rows_fwd(const Params *__restrict__ pp, int iter)
+// First sweep's row transform (one workgroup per row): the step's
+// coefficients R = J - Y + n_p psi and C = n_p + X - c0 are stored for the
+// later sweeps, and the right-hand side R + C a^(0), a^(0) = 2 a^(n-1) -
+// a^(n-2), is transformed along x.
+__global__ __launch_bounds__(kThreads) void k_rows_first(const Params *__restrict__ pp)
 {
     extern __shared__ double2 z[];
     const Params &P = *pp;
     const int j = blockIdx.x, nx = P.nx;
     const int p = (int)(P.state->step & 1);
     const double *nb = P.dep[p][0], *J = P.dep[p][1], *Xc = P.dep[p][2], *Yc = P.dep[p][3];
-    const double *prev = P.it[(iter + 1) & 1];
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         const int64_t o = (int64_t)j * nx + i;
-        const double ap = iter == 0 ? 2.0 * P.a1[o] - P.a2[o] : prev[o];
+        const double ap = 2.0 * P.a1[o] - P.a2[o];
         const double n_p = fmax(P.n0 - nb[o], 0.0);
         const double c = n_p + Xc[o];
         const double R = J[o] - Yc[o] + n_p * P.psi[o];
-        z[brev(i, P.lx)] = make_double2(R + (c - P.c0) * ap, 0.0);
+        const double C = c - P.c0;
+        P.rhsR[o] = R;
+        P.rhsC[o] = C;
+        z[brev(i, P.lx)] = make_double2(R + C * ap, 0.0);
     }
+    __syncthreads();
+    fft_lds(z, P.lx, 1, P.twx, false);
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) P.W[(int64_t)j * nx + i] = z[i];
+}
+
+// Between sweeps (one workgroup per row): the inverse row transform gives
+// the sweep's result a, from which the next right-hand side R + C a is
+// transformed along x, without a round trip of a through memory.
+__global__ __launch_bounds__(kThreads) void k_rows_mid(const Params *__restrict__ pp)
+{
+    extern __shared__ double2 z[];
+    const Params &P = *pp;
+    const int j = blockIdx.x, nx = P.nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) z[brev(i, P.lx)] = P.W[(int64_t)j * nx + i];
+    __syncthreads();
+    fft_lds(z, P.lx, 1, P.twx, true);
+    const double s = 1.0 / (double)P.cells;
+    double v[kFftLds / kThreads];
+    int m = 0;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x, ++m) {
+        const int64_t o = (int64_t)j * nx + i;
+        v[m] = P.rhsR[o] + P.rhsC[o] * (z[i].x * s);
+    }
+    __syncthreads();
+    m = 0;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x, ++m) z[brev(i, P.lx)] = make_double2(v[m], 0.0);
     __syncthreads();
     fft_lds(z, P.lx, 1, P.twx, false);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) P.W[(int64_t)j * nx + i] = z[i];
@@ -429,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_fwd(const Params *__restrict_
 
 // Column transform, division by the symbol -(4/dx^2) sin^2 - (4/dy^2) sin^2 - c0,
 // inverse column transform (cols_per_block columns per workgroup).
-__global__ __launch_bounds__(kThreads) void k_cols(const Params *__restrict__ pp)
+__global__ __launch_bounds__(kColThreads) void k_cols(const Params *__restrict__ pp)
 {
     extern __shared__ double2 z[];
     const Params &P = *pp;
@@ -462,8 +539,8 @@ __global__ __launch_bounds__(kThreads) void k_cols(const Params *__restrict__ pp
     }
 }
 
-// Inverse row transform; the real part / (nx ny) is the sweep's result.
-__global__ __launch_bounds__(kThreads) void k_rows_inv(const Params *__restrict__ pp, int iter)
+// Last sweep's inverse row transform; the real part / (nx ny) is a^n.
+__global__ __launch_bounds__(kThreads) void k_rows_inv(const Params *__restrict__ pp)
 {
     extern __shared__ double2 z[];
     const Params &P = *pp;
@@ -472,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_inv(const Params *__restrict_
     __syncthreads();
     fft_lds(z, P.lx, 1, P.twx, true);
     const double s = 1.0 / (double)P.cells;
-    double *out = P.it[iter & 1];
+    double *out = P.it[(P.iters - 1) & 1];
     for (int i = threadIdx.x; i < nx; i += blockDim.x) out[(int64_t)j * nx + i] = z[i].x * s;
 }
 
@@ -833,11 +910,12 @@ void solve(Launcher &L, const Params &hp, const Params *dp)
 {
     const size_t row_lds = sizeof(double2) * (size_t)hp.nx;
     const size_t col_lds = sizeof(double2) * (size_t)hp.cols_per_block * hp.ny;
+    L(0, k_rows_first, dim3(hp.ny), dim3(kThreads), row_lds, dp);
     for (int it = 0; it < hp.iters; ++it) {
-        L(0, k_rows_fwd, dim3(hp.ny), dim3(kThreads), row_lds, dp, it);
-        L(0, k_cols, dim3(hp.nx / hp.cols_per_block), dim3(kThreads), col_lds, dp);
-        L(0, k_rows_inv, dim3(hp.ny), dim3(kThreads), row_lds, dp, it);
+        L(0, k_cols, dim3(hp.nx / hp.cols_per_block), dim3(kColThreads), col_lds, dp);
+        if (it + 1 < hp.iters) L(0, k_rows_mid, dim3(hp.ny), dim3(kThreads), row_lds, dp);
     }
+    L(0, k_rows_inv, dim3(hp.ny), dim3(kThreads), row_lds, dp);
 }
 
 int scan_chunks(const Params &hp) { return (int)((hp.cells + kScanChunk - 1) / kScanChunk); }
@@ -868,7 +946,7 @@ hipError_t launch_init(const Params &hp, const Params *dp, hipStream_t st)
     return hipGetLastError();
 }
 
-int step_launches(const Params &hp) { return 3 * hp.iters + 9; }
+int step_launches(const Params &hp) { return 2 * hp.iters + 1 + 9; }
 
 hipError_t launch_step(const Params &hp, const Params *dp, hipStream_t st, hipEvent_t *ev, int *groups, int *nlaunch)
 {

@@ -65,7 +65,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t part_bytes = 0, grid_bytes = 0;
     size_t px[2], py[2], pux[2], puy[2], ppz[2], pid[2];
-    size_t a1, a2, psi, it[2], dep[2][4], W, twx, twy, lapx, lapy, count, start, tstart[2], bins, scan, pdiag, gdiag,
+    size_t a1, a2, psi, it[2], rhsR, rhsC, dep[2][4], W, twx, twy, lapx, lapy, count, start, tstart[2], bins, scan, pdiag, gdiag,
         state, params, ring;
 };
 
@@ -120,6 +120,8 @@ int validate(const pic_hyb_desc *d, Layout *L, std::string *err)
     L->psi = g.take(C * 8);
     L->it[0] = g.take(C * 8);
     L->it[1] = g.take(C * 8);
+    L->rhsR = g.take(C * 8);
+    L->rhsC = g.take(C * 8);
     for (int s = 0; s < 2; ++s)
         for (int k = 0; k < 4; ++k) L->dep[s][k] = g.take(C * 8);
     L->W = g.take(C * 16);
@@ -265,6 +267,8 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.a2 = at<double>(grid, L.a2);
     P.psi = at<double>(grid, L.psi);
     for (int s = 0; s < 2; ++s) P.it[s] = at<double>(grid, L.it[s]);
+    P.rhsR = at<double>(grid, L.rhsR);
+    P.rhsC = at<double>(grid, L.rhsC);
     for (int s = 0; s < 2; ++s)
         for (int k = 0; k < 4; ++k) P.dep[s][k] = at<double>(grid, L.dep[s][k]);
     P.W = at<double2>(grid, L.W);
