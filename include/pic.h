@@ -163,8 +163,10 @@ typedef struct {
  *   W[6]           sum over cells of F_i^2 dV for Ex,Ey,Ez,Bx,By,Bz at time step
  *                  (the paper's per-component field energy, no factor 1/2).
  *   kinetic[s]     dV sum w (gamma - 1), gamma time-centred at the step.
+ *   p_species[s]   dV sum w u of species s, time-centred.
  *   p_particles[3] dV sum w u, time-centred, all species.
- *   p_field_z      dV sum (E x B)_z.
+ *   p_field[3]     dV sum E x B, each product at its E component's point (B
+ *                  averaged over the two points around it).
  *   collisions     scattering events during the step.
  *   n_particles[s] particles of species s.
  *   rebins         particle-store re-layouts performed so far.
@@ -179,8 +181,9 @@ typedef struct {
     double time;
     double W[6];
     double kinetic[PIC_MAX_SPECIES];
+    double p_species[PIC_MAX_SPECIES][3];
     double p_particles[3];
-    double p_field_z;
+    double p_field[3];
     int64_t collisions;
     int64_t n_particles[PIC_MAX_SPECIES];
     int64_t rebins;

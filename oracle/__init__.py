@@ -48,7 +48,7 @@ class _Species(C.Structure):
 
 class _Diag(C.Structure):
     _fields_ = [("W", C.c_double * 6), ("kinetic", C.c_double * 8), ("p_particles", C.c_double * 3),
-                ("p_field_z", C.c_double), ("collisions", C.c_int64)]
+                ("p_species", (C.c_double * 3) * 8), ("p_field", C.c_double * 3), ("collisions", C.c_int64)]
 
 
 _lib = None
@@ -79,8 +79,7 @@ def lib():
         L.orc_yee_b.argtypes = [P(_Grid), C.c_double]
         L.orc_yee_e.argtypes = [P(_Grid)]
         L.orc_field_energy.argtypes = [P(_Grid), dp]
-        L.orc_field_momentum_z.argtypes = [P(_Grid)]
-        L.orc_field_momentum_z.restype = C.c_double
+        L.orc_field_momentum.argtypes = [P(_Grid), P(C.c_double)]
         L.orc_rho.argtypes = [P(_Grid), P(_Species), C.c_int, dp]
         L.orc_divergence.argtypes = [P(_Grid), dp * 3, dp]
         L.orc_step.argtypes = [P(_Grid), P(_Species), C.c_int, C.c_int64, C.c_uint64, C.c_uint32, P(_Diag)]
@@ -251,7 +250,9 @@ class OracleRun:
             if diag:
                 out.append(dict(step=self.step_index, W=np.array(d.W[:]),
                                 kinetic=np.array(d.kinetic[:len(self.species)]),
-                                p_particles=np.array(d.p_particles[:]), p_field_z=d.p_field_z,
+                                p_particles=np.array(d.p_particles[:]),
+                                p_species=np.array([d.p_species[s][:] for s in range(len(self.species))]),
+                                p_field=np.array(d.p_field[:]),
                                 collisions=int(d.collisions)))
             self.step_index += 1
         return out
@@ -261,8 +262,10 @@ class OracleRun:
         lib().orc_field_energy(C.byref(self._g), _dp(W))
         return W
 
-    def field_momentum_z(self) -> float:
-        return float(lib().orc_field_momentum_z(C.byref(self._g)))
+    def field_momentum(self) -> np.ndarray:
+        p = np.zeros(3)
+        lib().orc_field_momentum(C.byref(self._g), _dp(p))
+        return p
 
     def rho(self) -> np.ndarray:
         r = np.zeros(self.f.E.shape[1:])

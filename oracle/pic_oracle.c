@@ -79,7 +79,8 @@ typedef struct {
     double W[6];          /* sum F_i^2 dV at time n, Ex Ey Ez Bx By Bz */
     double kinetic[8];    /* dV sum w (gamma^n - 1) per species */
     double p_particles[3];/* dV sum w u^n over all species */
-    double p_field_z;     /* dV sum (E x B)_z */
+    double p_species[8][3];/* dV sum w u^n per species */
+    double p_field[3];    /* dV sum E x B (each product at the E component's point) */
     int64_t collisions;   /* number of scattering events in the step */
 } orc_diag;
 
@@ -417,16 +418,24 @@ void orc_field_energy(const orc_grid *g, double W[6])
 /* z component of the field momentum, dV sum (E_x B_y - E_y B_x); B_x, B_y
  * are averaged over their two z neighbours onto the E_x, E_y points (in
  * 2D the pairs are co-located and the average is the identity).         */
-double orc_field_momentum_z(const orc_grid *g)
+/* Field momentum sum E x B dV.  Each product E_a B_b is taken at E_a's
+ * point; B_b is averaged over the two points around it along the axis in
+ * which the staggers differ (Yee: E_x (i+1/2,j,k), B_y (i+1/2,j,k+1/2),
+ * B_z (i+1/2,j+1/2,k) and cyclically).                                    */
+void orc_field_momentum(const orc_grid *g, double p[3])
 {
-    double s = 0.0;
+    double s[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {
-                size_t o = at(g, i, j, k), m = at(g, i, j, k - 1);
-                s += g->E[0][o] * 0.5 * (g->B[1][o] + g->B[1][m]) - g->E[1][o] * 0.5 * (g->B[0][o] + g->B[0][m]);
+                size_t o = at(g, i, j, k);
+                size_t mi = at(g, i - 1, j, k), mj = at(g, i, j - 1, k), mk = at(g, i, j, k - 1);
+                const double *E[3] = {g->E[0], g->E[1], g->E[2]}, *B[3] = {g->B[0], g->B[1], g->B[2]};
+                s[0] += E[1][o] * 0.5 * (B[2][o] + B[2][mi]) - E[2][o] * 0.5 * (B[1][o] + B[1][mi]);
+                s[1] += E[2][o] * 0.5 * (B[0][o] + B[0][mj]) - E[0][o] * 0.5 * (B[2][o] + B[2][mj]);
+                s[2] += E[0][o] * 0.5 * (B[1][o] + B[1][mk]) - E[1][o] * 0.5 * (B[0][o] + B[0][mk]);
             }
-    return s * cell_volume(g);
+    for (int c = 0; c < 3; ++c) p[c] = s[c] * cell_volume(g);
 }
 
 /* charge density on integer nodes, rho = sum q w S(x) (CIC) */
@@ -489,13 +498,13 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
     if (diag) {
         memset(diag, 0, sizeof(*diag));
         orc_field_energy(g, diag->W);
-        diag->p_field_z = orc_field_momentum_z(g);
+        orc_field_momentum(g, diag->p_field);
     }
     /* per-chunk current partials, summed in chunk order: the result does
      * not depend on the number of threads                                 */
     double *part = (double *)calloc((size_t)ORC_CHUNKS * 3 * nc, sizeof(double));
     if (!part) return -1;
-    double ke[ORC_CHUNKS][8], pp[ORC_CHUNKS][3];
+    double ke[ORC_CHUNKS][8], pp[ORC_CHUNKS][8][3];
     int64_t ncoll[ORC_CHUNKS];
     memset(ke, 0, sizeof(ke)); memset(pp, 0, sizeof(pp)); memset(ncoll, 0, sizeof(ncoll));
 
@@ -523,7 +532,7 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
                 orc_deposit(g, Jp, qw, x0, x1, u[2] / gam);
                 if (diag) {
                     ke[ch][s] += S->w * (0.5 * (g_old + gam) - 1.0);
-                    for (int c = 0; c < 3; ++c) pp[ch][c] += S->w * 0.5 * (u_old[c] + u[c]);
+                    for (int c = 0; c < 3; ++c) pp[ch][s < 8 ? s : 7][c] += S->w * 0.5 * (u_old[c] + u[c]);
                 }
                 if (thr && S->id) ncoll[ch] += orc_collide(u, S->id[p], step, seed, run, thr);
                 if (coulomb && S->id) ncoll[ch] += orc_coulomb(u, S->id[p], step, seed, run, S->nu, S->vref, g->dt);
@@ -544,7 +553,11 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
     if (diag) {
         for (int ch = 0; ch < ORC_CHUNKS; ++ch) {
             for (int s = 0; s < ns && s < 8; ++s) diag->kinetic[s] += ke[ch][s] * dv;
-            for (int c = 0; c < 3; ++c) diag->p_particles[c] += pp[ch][c] * dv;
+            for (int s = 0; s < ns && s < 8; ++s)
+                for (int c = 0; c < 3; ++c) {
+                    diag->p_species[s][c] += pp[ch][s][c] * dv;
+                    diag->p_particles[c] += pp[ch][s][c] * dv;
+                }
             diag->collisions += ncoll[ch];
         }
     } else {

@@ -18,7 +18,7 @@ constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
 constexpr int kRing = 4096;          // diagnostic records kept on the device
 constexpr int kTileDiag = 6;         // per tile and species: KE, px, py, pz, count, collisions
-constexpr int kFieldDiag = 8;        // per block: W[6], p_field_z, unused
+constexpr int kFieldDiag = 10;       // per block: W[6], p_field[3], unused
 constexpr int kFieldDiagBlocks = 512;
 constexpr int kBinAlign = 64;        // particle-store bins start at multiples of this many slots
 constexpr int kMomentBlocks = 1024;  // loader reductions

@@ -178,13 +178,14 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*sred)[N])
 template <typename R>
 __device__ __forceinline__ void field_diag_body(const KParams *__restrict__ kp, int bid, int nb)
 {
-    __shared__ double sred[4][7];
+    __shared__ double sred[4][9];
     const int64_t step = uniform_step(kp);
     if (!diag_step(kp, step)) return;
     const R *F = (const R *)kp->F;
     const int64_t cells = kp->g.cells;
-    const int64_t nxy = (int64_t)kp->g.n[0] * kp->g.n[1];
-    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int nx = kp->g.n[0], ny = kp->g.n[1];
+    const int64_t nxy = (int64_t)nx * ny;
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t o = (int64_t)bid * 256 + threadIdx.x; o < cells; o += (int64_t)nb * 256) {
         double v[6];
 #pragma unroll
@@ -192,15 +193,25 @@ __device__ __forceinline__ void field_diag_body(const KParams *__restrict__ kp, 
             v[c] = (double)F[c * cells + o];
             a[c] += v[c] * v[c];
         }
-        int64_t om = o - nxy;
-        if (om < 0) om += cells;                      // k-1 (in 2D: the same cell)
-        const double by = 0.5 * (v[4] + (double)F[4 * cells + om]);
-        const double bx = 0.5 * (v[3] + (double)F[3 * cells + om]);
-        a[6] += v[0] * by - v[1] * bx;
+        // E x B with each product at its E component's point: B averaged over
+        // the two points around it along the axis where the staggers differ
+        const int i = (int)(o % nx), j = (int)((o / nx) % ny);
+        const int64_t mi = i ? o - 1 : o + nx - 1;                 // i-1
+        const int64_t mj = j ? o - nx : o + nxy - nx;              // j-1
+        const int64_t mk = o >= nxy ? o - nxy : o + cells - nxy;   // k-1 (2D: the same cell)
+        const double bz_i = 0.5 * (v[5] + (double)F[5 * cells + mi]);
+        const double by_i = 0.5 * (v[4] + (double)F[4 * cells + mi]);
+        const double bx_j = 0.5 * (v[3] + (double)F[3 * cells + mj]);
+        const double bz_j = 0.5 * (v[5] + (double)F[5 * cells + mj]);
+        const double by_k = 0.5 * (v[4] + (double)F[4 * cells + mk]);
+        const double bx_k = 0.5 * (v[3] + (double)F[3 * cells + mk]);
+        a[6] += v[1] * bz_i - v[2] * by_i;
+        a[7] += v[2] * bx_j - v[0] * bz_j;
+        a[8] += v[0] * by_k - v[1] * bx_k;
     }
-    block_sum<7>(a, sred);
+    block_sum<9>(a, sred);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 7; ++c) kp->field_diag[bid * kFieldDiag + c] = a[c];
+        for (int c = 0; c < 9; ++c) kp->field_diag[bid * kFieldDiag + c] = a[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,7 +1448,7 @@ __device__ __forceinline__ void yee_e_body(const KParams *__restrict__ kp, int b
 // counters, step and parity update.  One workgroup.
 __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int bid, int nb)
 {
-    __shared__ double sred[4][8];
+    __shared__ double sred[4][10];
     DevState *st = kp->state;
     const int64_t step = st->step;
     const int par = st->par;
@@ -1446,14 +1457,14 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
     const int ns = kp->nspecies;
     if (diag_step(kp, step)) {
         const double dv = kp->g.d[0] * kp->g.d[1] * (kp->g.ndim == 3 ? kp->g.d[2] : 1.0);
-        double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int b = threadIdx.x; b < kp->fd_blocks; b += blockDim.x)
-            for (int c = 0; c < 7; ++c) f[c] += kp->field_diag[b * kFieldDiag + c];
-        block_sum<8>(f, sred);
+            for (int c = 0; c < 9; ++c) f[c] += kp->field_diag[b * kFieldDiag + c];
+        block_sum<10>(f, sred);
         pic_diag rec;
         if (threadIdx.x == 0) {
             for (int c = 0; c < 6; ++c) rec.W[c] = f[c] * dv;
-            rec.p_field_z = f[6] * dv;
+            for (int c = 0; c < 3; ++c) rec.p_field[c] = f[6 + c] * dv;
         }
         double coll_total = 0.0;
         double pp[3] = {0, 0, 0};
@@ -1461,10 +1472,13 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
             double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
                 for (int v = 0; v < kTileDiag; ++v) a[v] += kp->tile_diag[((int64_t)t * ns + s) * kTileDiag + v];
-            block_sum<8>(a, sred);
+            block_sum<8>(a, (double(*)[8])sred);
             if (threadIdx.x == 0) {
                 rec.kinetic[s] = a[0] * dv;
-                for (int c = 0; c < 3; ++c) pp[c] += a[1 + c] * dv;
+                for (int c = 0; c < 3; ++c) {
+                    rec.p_species[s][c] = a[1 + c] * dv;
+                    pp[c] += a[1 + c] * dv;
+                }
                 rec.n_particles[s] = (int64_t)a[4];
                 coll_total += a[5];
             }
@@ -1495,7 +1509,11 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
         if (threadIdx.x == 0) {
             rec.gauss_resid = gm[0];
             rec.rho_dev = gm[1];
-            for (int s = ns; s < kMaxSpecies; ++s) { rec.kinetic[s] = 0.0; rec.n_particles[s] = 0; }
+            for (int s = ns; s < kMaxSpecies; ++s) {
+                rec.kinetic[s] = 0.0;
+                rec.n_particles[s] = 0;
+                for (int c = 0; c < 3; ++c) rec.p_species[s][c] = 0.0;
+            }
             for (int c = 0; c < 3; ++c) rec.p_particles[c] = pp[c];
             rec.collisions = (int64_t)coll_total;
             rec.step = step;

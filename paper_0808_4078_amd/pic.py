@@ -65,15 +65,16 @@ class Buffers(C.Structure):
 
 class Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("time", C.c_double), ("W", C.c_double * 6),
-                ("kinetic", C.c_double * MAX_SPECIES), ("p_particles", C.c_double * 3),
-                ("p_field_z", C.c_double), ("collisions", C.c_int64),
+                ("kinetic", C.c_double * MAX_SPECIES), ("p_species", (C.c_double * 3) * MAX_SPECIES),
+                ("p_particles", C.c_double * 3), ("p_field", C.c_double * 3), ("collisions", C.c_int64),
                 ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64), ("gauss_resid", C.c_double),
                 ("rho_dev", C.c_double)]
 
     def as_dict(self, ns: int) -> dict:
         return dict(step=int(self.step), time=float(self.time), W=np.array(self.W[:]),
                     kinetic=np.array(self.kinetic[:ns]), p_particles=np.array(self.p_particles[:]),
-                    p_field_z=float(self.p_field_z), collisions=int(self.collisions),
+                    p_species=np.array([self.p_species[s][:] for s in range(ns)]),
+                    p_field=np.array(self.p_field[:]), collisions=int(self.collisions),
                     n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins),
                     gauss_resid=float(self.gauss_resid), rho_dev=float(self.rho_dev))
 

@@ -542,3 +542,30 @@ def test_coulomb_scattering_drag_and_v3_law():
     # no rate, no scattering
     u1, hit = coulomb(np.array([0.1, 0.2, 0.3]), 1, 1, 1, 0, 0.0, vref, dt)
     assert not hit and np.array_equal(u1, [0.1, 0.2, 0.3])
+
+
+def test_field_momentum_of_a_travelling_wave(orc):
+    """E_y = B_z = A cos(k x - w t) (a plane wave along x) on the Yee grid:
+    E x B has only an x component, and with B_z averaged over the two points
+    around E_y's, sum E_y <B_z> dV = A^2 cos(k dx/2) sum cos^2(k x_i) dV
+    = A^2 cos(k dx/2) N dV / 2 exactly; the same wave along y gives p_y."""
+    n, d = 32, 0.2
+    wl = synth.beam_plasma((n, n), steps=1)
+    run = orc.OracleRun(2, (n, n), (d, d), 0.1, [], 1)
+    k = 2 * math.pi * 3 / (n * d)
+    A = 0.7
+    xi = np.arange(n) * d
+    xh = (np.arange(n) + 0.5) * d
+    run.f.E[...] = 0.0
+    run.f.B[...] = 0.0
+    run.f.E[1, 0] = A * np.cos(k * xi)[None, :]          # E_y at (i, j+1/2): x = i dx
+    run.f.B[2, 0] = A * np.cos(k * xh)[None, :]          # B_z at (i+1/2, j+1/2)
+    p = run.field_momentum()
+    want = A * A * math.cos(k * d / 2) * n * n * d * d / 2
+    assert abs(p[0] / want - 1) < 1e-12 and abs(p[1]) < 1e-12 * want and abs(p[2]) < 1e-12 * want
+    run.f.E[...] = 0.0
+    run.f.B[...] = 0.0
+    run.f.E[2, 0] = A * np.cos(k * xi)[:, None]          # E_z at (i, j): y = j dy
+    run.f.B[0, 0] = A * np.cos(k * xh)[:, None]          # B_x at (i, j+1/2)
+    p = run.field_momentum()
+    assert abs(p[1] / want - 1) < 1e-12 and abs(p[0]) < 1e-12 * want and abs(p[2]) < 1e-12 * want
