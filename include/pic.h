@@ -324,6 +324,11 @@ int pic_batch_step_profiled(pic_batch *batch, int32_t nsteps, double *group_ms);
 /* Waits for the stream; returns the first member's failure, if any. */
 int pic_batch_sync(pic_batch *batch);
 
+/* Synchronising.  The most recent diagnostic record of member `run` (its
+ * index in the runs given to pic_batch_init), as pic_diagnostics.  Errors:
+ * INVALID_ARG (run out of range), STATE (no record yet). */
+int pic_batch_diagnostics(pic_batch *batch, int run, pic_diag *out);
+
 /* Host only.  For tile edges 8, 16, 32 (index 0..2): the particle kernel's
  * workgroups and work items (0 where no member uses the edge). */
 int pic_batch_info(pic_batch *batch, int32_t persistent_blocks[3], int32_t items[3]);

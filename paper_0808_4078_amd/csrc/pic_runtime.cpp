@@ -1310,6 +1310,16 @@ int pic_batch_sync(pic_batch *b)
     return PIC_OK;
 }
 
+int pic_batch_diagnostics(pic_batch *b, int run, pic_diag *out)
+{
+    if (!b || !out) return fail(b ? &b->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
+    if (run < 0 || run >= (int)b->runs.size())
+        return fail(&b->err, PIC_E_INVALID_ARG, "run %d out of 0..%d", run, (int)b->runs.size() - 1);
+    const int rc = pic_diagnostics(b->runs[(size_t)run], out);
+    if (rc != PIC_OK) b->err = b->runs[(size_t)run]->err;
+    return rc;
+}
+
 int pic_batch_info(pic_batch *b, int32_t *persistent_blocks, int32_t *items)
 {
     if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");

@@ -90,7 +90,8 @@ _lib = None
 EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_profiled", "pic_sync", "pic_diagnostics",
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
            "pic_status_string", "pic_last_error", "pic_batch_query", "pic_batch_init", "pic_batch_step",
-           "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_destroy", "pic_tune_query",
+           "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_diagnostics",
+           "pic_batch_destroy", "pic_tune_query",
            "pic_tune", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
            "pic_hyb_step_profiled", "pic_hyb_sync", "pic_hyb_read_grid", "pic_hyb_read_particles",
            "pic_hyb_diag_history", "pic_hyb_last_error", "pic_hyb_destroy"]
@@ -154,6 +155,7 @@ def lib():
         L.pic_batch_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.pic_batch_sync.argtypes = [vp]
         L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.pic_batch_diagnostics.argtypes = [vp, C.c_int, P(Diag)]
         L.pic_batch_destroy.argtypes = [vp]
         L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, P(C.c_size_t)]
         L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp, C.c_int32,
@@ -417,6 +419,12 @@ class Batch:
         it = (C.c_int32 * 3)()
         _check(lib().pic_batch_info(self.h, pb, it), "pic_batch_info")
         return {"persistent_blocks": list(pb), "items": list(it)}
+
+    def diagnostics(self, run: int) -> dict:
+        """The latest record of member `run` (index in the list given)."""
+        d = Diag()
+        _check(lib().pic_batch_diagnostics(self.h, int(run), C.byref(d)), "pic_batch_diagnostics")
+        return d.as_dict(self.runs[run].ns)
 
     def close(self):
         if getattr(self, "h", None):

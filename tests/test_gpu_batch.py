@@ -74,6 +74,14 @@ def test_batch_members_match_runs_stepped_alone(pic, prec, bar):
             r.sync()
         errs = [_compare(pic, m, r, bar) for m, r in zip(members, alone)]
         log(f"  max member field error {max(errs):.3e}")
+    # pic_batch_diagnostics: member i's latest record, as the run's own
+    for i, (m, r) in enumerate(zip(members, alone)):
+        db, dr = batch.diagnostics(i), r.diagnostics()
+        assert db["step"] == dr["step"] and db["n_particles"].tolist() == dr["n_particles"].tolist()
+        assert np.max(np.abs(db["W"] - dr["W"])) <= 1e3 * bar * max(1e-12, np.max(np.abs(dr["W"])))
+    with pytest.raises(pic.PicError) as e:
+        batch.diagnostics(len(members))
+    assert e.value.code == pic.PIC_E_INVALID_ARG
     batch.close()
     for r in alone + members:
         r.close()
