@@ -223,3 +223,48 @@ def test_hybrid_paper_hot_beam_cases(pic):
     want = float(np.mean(want))
     log(f"  (d) mode-1 growth {rate:.4f}, warm relation along the beam {want:.4f}")
     assert 0.6 * want < rate < 1.6 * want
+
+
+@pytest.mark.parametrize("case", ["empty", "ragged", "one_tile_fast"])
+def test_hybrid_edge_cases(pic, case):
+    """No particles (the potential stays 0); 1000 particles at random
+    positions (no whole wave, runs or tiles of them); an 8 x 8 grid (one
+    tile whose LDS windows alias the periodic grid) with a transverse spread
+    of u_th = 2, so particles cross the box several times and leave their
+    tile's window between sorts.  FP64 against the oracle after 50 steps."""
+    log(f"case hybrid edge {case}")
+    rng = np.random.default_rng(21)
+    if case == "empty":
+        wl = replace(synth.H1, n=(32, 32), steps=50)
+        x, u, uz = np.zeros((2, 0)), np.zeros((2, 0)), np.zeros(0)
+    elif case == "ragged":
+        wl = replace(synth.H1, n=(32, 32), steps=50)
+        N = 1000
+        L = np.array(wl.n) * np.array(wl.d)
+        x = rng.uniform(0, 1, (2, N)) * L[:, None]
+        u = 0.2 * rng.standard_normal((2, N))
+        uz = 2.0 + 0.2 * rng.standard_normal(N)
+    else:
+        wl = replace(synth.H1, n=(8, 8), steps=50, ppc=16, u_th=2.0)
+        x, u, uz = synth.hybrid_load(wl)
+    N = x.shape[1]
+    w = wl.n_b * wl.n[0] * wl.n[1] / max(N, 1) if N else wl.weight
+    orc = Hybrid(wl.n, wl.d, wl.dt, wl.nu, x, u, uz, w, iters=wl.iters)
+    d = pic.hyb_desc(wl, N, diag_every=10, sort_every=7)
+    d.weight = w
+    g = pic.HybridRun(d, x[0], x[1], u[0], u[1], uz)
+    orc.step(wl.steps)
+    g.step(wl.steps)
+    a, psi = g.read_grid()
+    if case == "empty":
+        assert np.max(np.abs(a)) == 0.0 and np.max(np.abs(psi)) == 0.0
+        assert np.max(np.abs(orc.a_cur)) == 0.0
+    else:
+        assert rel_err(a, orc.a_cur) < 1e-9 and rel_err(psi, orc.psi) < 1e-9
+        xg, ug, pzg, ids = g.read_particles()
+        o = np.argsort(ids)
+        L = (np.array(wl.n) * np.array(wl.d))[:, None]
+        assert np.max(np.abs(periodic_diff(xg[:, o], orc.x, L))) < 1e-9
+        assert np.max(np.abs(ug[:, o] - orc.u)) < 1e-9
+        assert np.max(np.abs(pzg[o] - orc.P)) < 1e-9
+    g.close()
