@@ -63,10 +63,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -79,8 +79,8 @@ __device__ __forceinline__ uint32_t philox2x32_10_w0(uint32_t c0, uint32_t c1, u
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi = __umulhi(0xD256D193u, c0);
-        const uint32_t lo = 0xD256D193u * c0;
+        const uint64_t p = (uint64_t)0xD256D193u * c0;
+        const uint32_t hi = (uint32_t)(p >> 32), lo = (uint32_t)p;
         c0 = hi ^ k ^ c1;
         c1 = lo;
         k += 0x9E3779B9u;
@@ -387,9 +387,79 @@ __device__ __forceinline__ void deposit_cell(A *sJx, A *sJy, A *sJz, const int (
     }
 }
 
-// Crossing particles wait in a per-wave ring of kQueue entries in LDS and are
-// deposited 64 at a time through deposit_window, with every lane busy.
-constexpr int kQueue = 128;
+// A 3D move that crosses exactly one cell face, along axis w (per lane): on
+// the two other axes u < v the form factors live on the cell's two nodes (as
+// in deposit_cell); along w they span three nodes starting at nb, the cell's
+// lower node for an upward crossing and the node below it for a downward one.
+// Of the window's 54 entries only 20 can be nonzero: J_w on 2 edges x 2 x 2
+// nodes, J_u and J_v on 1 edge x 2 x 3 nodes.  sJ holds the three components
+// NJ^3 apart.
+template <typename R, typename A, int NJ>
+__device__ __forceinline__ void deposit_face(A *sJ, const int (&lc)[3], const R (&x0)[3], const R (&x1)[3],
+                                             const R (&kd)[3])
+{
+    constexpr int ST[3] = {1, NJ, NJ * NJ};
+    constexpr int NJ_D = NJ * NJ * NJ;
+    auto off = [](R x) { return x < R(0) || x >= R(1); };
+    const int w = off(x1[0]) ? 0 : off(x1[1]) ? 1 : 2;
+    const int u = w == 0 ? 1 : 0, v = w == 2 ? 1 : 2;
+    auto pick = [](const R (&a)[3], int i) { return i == 0 ? a[0] : i == 1 ? a[1] : a[2]; };
+    const R xu0 = pick(x0, u), xv0 = pick(x0, v), xw0 = pick(x0, w);
+    const R du = pick(x1, u) - xu0, dv = pick(x1, v) - xv0, xw1 = pick(x1, w);
+    const int su = u == 0 ? ST[0] : ST[1], sv = v == 1 ? ST[1] : ST[2];
+    const int sw = w == 0 ? ST[0] : w == 1 ? ST[1] : ST[2];
+    // two-node factors on u and v: S0, DS = (-d, d), h = S0 + DS/2, q = S0/2 + DS/3
+    const R s0u[2] = {R(1) - xu0, xu0}, s0v[2] = {R(1) - xv0, xv0};
+    const R dsu[2] = {-du, du}, dsv[2] = {-dv, dv};
+    const R hv[2] = {R(1) - (xv0 + R(0.5) * dv), xv0 + R(0.5) * dv};
+    const R qv[2] = {R(0.5) * s0v[0] - R(1.0 / 3.0) * dv, R(0.5) * s0v[1] + R(1.0 / 3.0) * dv};
+    // three-node factors on w
+    const bool up = xw1 >= R(1);
+    R S0w[3], DSw[3];
+    if (up) {
+        S0w[0] = R(1) - xw0; S0w[1] = xw0; S0w[2] = R(0);
+        DSw[0] = -S0w[0]; DSw[1] = (R(2) - xw1) - xw0; DSw[2] = xw1 - R(1);
+    } else {
+        S0w[0] = R(0); S0w[1] = R(1) - xw0; S0w[2] = xw0;
+        DSw[0] = -xw1; DSw[1] = (R(1) + xw1) - S0w[1]; DSw[2] = -xw0;
+    }
+    R hw[3], qw[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        hw[m] = S0w[m] + R(0.5) * DSw[m];
+        qw[m] = R(0.5) * S0w[m] + R(1.0 / 3.0) * DSw[m];
+    }
+    const R kw = w == 0 ? kd[0] : w == 1 ? kd[1] : kd[2];
+    const R ju = (u == 0 ? kd[0] : kd[1]) * du, jv = (v == 1 ? kd[1] : kd[2]) * dv;
+    const int o = lc[0] + lc[1] * ST[1] + lc[2] * ST[2] - (up ? 0 : sw);
+    A *Ju = sJ + u * NJ_D, *Jv = sJ + v * NJ_D, *Jw = sJ + w * NJ_D;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const R p = s0u[i] * hv[j] + dsu[i] * qv[j];
+            const R j0 = -kw * (DSw[0] * p);
+            const R j1 = j0 - kw * (DSw[1] * p);
+            const int a = o + i * su + j * sv;
+            atomicAdd(&Jw[a], A(j0));
+            atomicAdd(&Jw[a + sw], A(j1));
+        }
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            atomicAdd(&Ju[o + j * sv + m * sw], A(ju * (s0v[j] * hw[m] + dsv[j] * qw[m])));
+            atomicAdd(&Jv[o + j * su + m * sw], A(jv * (s0u[j] * hw[m] + dsu[j] * qw[m])));
+        }
+}
+
+// Crossing particles wait in per-wave LDS stacks and are deposited 64 at a
+// time, with every lane busy: in 3D, single-face crossers (stack A, from the
+// bottom) through deposit_face and the others (stack B, from the top) through
+// deposit_window; in 2D all of them through deposit_window (stack B).  Each
+// stack is drained when it holds 64 entries, so before an append each holds at
+// most 63 and after it both together at most 190.
+template <int D> constexpr int kQueue = D == 3 ? 192 : 128;
 constexpr int kOrderBuckets = 64;
 constexpr int kAdvanceThreads = 256;     // workgroup size of the end-of-step kernel
 constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with its own L2
@@ -397,7 +467,7 @@ constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with i
 // Movers staged per wave in mixed mode before they are written, grouped by
 // destination tile (FP64 writes each mover at once: 1 entry).
 template <typename R, int D>
-constexpr int kMoverStage = sizeof(R) == 4 ? (D == 3 ? 32 : 64) : 1;
+constexpr int kMoverStage = sizeof(R) == 4 ? (D == 3 ? 24 : 64) : 1;
 
 constexpr int kBatch = 2;   // particles each lane keeps in flight ahead of the one it processes
 
@@ -416,8 +486,10 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
     constexpr int SJ_Y = NJ, SJ_Z = NJ * NJ;        // LDS strides of the current tile
     __shared__ R sF[6 * NF_D];
     __shared__ A sJ[3 * NJ_D];
-    __shared__ int sQc[kBlock / 64][kQueue];             // crossing-particle ring per wave
-    __shared__ R sQv[kBlock / 64][2 * D + 1][kQueue];
+    constexpr int QC = kQueue<D>;
+    constexpr int QV = D == 3 ? 2 * D : 2 * D + 1;       // x0, x1 (and q w v_z in 2D)
+    __shared__ int sQc[kBlock / 64][QC];                 // crossing-particle stacks per wave
+    __shared__ R sQv[kBlock / 64][QV][QC];
     // movers staged per wave (mixed mode): destination tile and stored words
     constexpr int MS = kMoverStage<R, D>;
     constexpr int MW = D + 5;                            // cell, offsets, momenta, id
@@ -542,8 +614,8 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             r.id = track ? ld(iid, slot) : 0u;
         };
         double acc[kTileDiag] = {0, 0, 0, 0, 0, 0};
-        uint32_t qhead = 0, qtail = 0;                       // wave-uniform ring indices
-        auto drain = [&](uint32_t e) {
+        uint32_t nqa = 0, nqb = 0;                           // wave-uniform stack heights
+        auto drain = [&](uint32_t e, bool face) {
             const int pk = sQc[wave][e];
             const int qlc[3] = {pk & 0xff, (pk >> 8) & 0xff, (pk >> 16) & 0xff};
             R qx0[3] = {R(0), R(0), R(0)}, qx1[3] = {R(0), R(0), R(0)};
@@ -552,7 +624,14 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 qx0[a] = sQv[wave][a][e];
                 qx1[a] = sQv[wave][D + a][e];
             }
-            deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, sQv[wave][2 * D][e]);
+            if constexpr (D == 3) {
+                if (face)
+                    deposit_face<R, A, NJ>(sJ, qlc, qx0, qx1, kd);
+                else
+                    deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, R(0));
+            } else {
+                deposit_window<R, A, D, NJ>(sJx, sJy, sJz, qlc, qx0, qx1, kd, sQv[wave][2 * D][e]);
+            }
         };
         // A particle that leaves the tile (mover) is written at the back of
         // its new tile's bin, in a slot reserved with a global atomic above
@@ -664,6 +743,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             uint32_t pid = 0;
             for (int a = 0; a < D; ++a) { ic1[a] = 0; off1[a] = R(0); }
             bool cross = false;                               // leaves its cell this step
+            int ncross = 0;                                   // faces crossed
             int q_lc = 0;
             R q_x0[D], q_x1[D], q_kz = R(0);
             if (active) {
@@ -731,8 +811,9 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 for (int a = 0; a < D; ++a) {
                     x1[a] = off[a] + v[a] * dtd[a];
                     kk[a] = (int)floor(x1[a]);
-                    cross = cross || kk[a] != 0;
+                    ncross += kk[a] != 0 ? 1 : 0;
                 }
+                cross = ncross != 0;
 
                 // ---- Esirkepov deposit: particles that stay in their cell now,
                 // the others through the per-wave queue below
@@ -828,27 +909,35 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 if (bad) atomicOr(&state->fatal, 2);
             }
 
-            // ---- crossing particles: append to the wave's ring, drain when a
-            // full wave of entries is waiting
+            // ---- crossing particles: push onto the wave's stacks, drain a
+            // stack when it holds a full wave of entries
             {
-                const uint64_t cm = __ballot(cross);
-                if (cm) {
+                const bool fa = D == 3 && cross && ncross == 1;
+                const bool fb = cross && !fa;
+                const uint64_t am = __ballot(fa), bm = __ballot(fb);
+                if (am | bm) {
                     if (cross) {
-                        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-                        const uint32_t e = (qtail + r) & (kQueue - 1);
+                        const uint64_t m = fa ? am : bm;
+                        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        const uint32_t e = fa ? nqa + r : (uint32_t)QC - 1u - (nqb + r);
                         sQc[wave][e] = q_lc;
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
                             sQv[wave][a][e] = q_x0[a];
                             sQv[wave][D + a][e] = q_x1[a];
                         }
-                        sQv[wave][2 * D][e] = q_kz;
+                        if constexpr (D == 2) sQv[wave][2 * D][e] = q_kz;
                     }
-                    qtail += (uint32_t)__popcll(cm);
-                    if (qtail - qhead >= 64) {
-                        drain((qhead + lane) & (kQueue - 1));
-                        qhead += 64;
+                    nqa += (uint32_t)__popcll(am);
+                    nqb += (uint32_t)__popcll(bm);
+                    if (nqa >= 64) {
+                        nqa -= 64;
+                        drain(nqa + lane, true);
+                    }
+                    if (nqb >= 64) {
+                        nqb -= 64;
+                        drain((uint32_t)QC - 1u - (nqb + lane), false);
                     }
                 }
             }
@@ -941,7 +1030,8 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         if constexpr (MS > 1) {
             if (mv_n) flush_movers();
         }
-        if ((uint32_t)lane < qtail - qhead) drain((qhead + lane) & (kQueue - 1));
+        if ((uint32_t)lane < nqa) drain(lane, true);
+        if ((uint32_t)lane < nqb) drain((uint32_t)QC - 1u - lane, false);
         __syncthreads();
         if (threadIdx.x == 0) S.cnt_front[dst * ntiles + tile] = s_front;
         if (diag) {
