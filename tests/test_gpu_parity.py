@@ -296,3 +296,48 @@ def test_3d_device_loader_and_continuity(pic):
     o = oracle.OracleRun(3, wl.n, wl.d, wl.dt, [], 1)
     res = rho(after) - rho(before) + wl.dt * o.divergence(J)
     assert np.max(np.abs(res)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_3d_face_crossings_current(pic, prec):
+    """J^{1/2} node by node for crafted 3D moves from zero fields: every face
+    crossed in both directions on each axis (single-face path), pairs and
+    triples of faces (general window) and stayers, in cells on both sides of
+    the 8^3 tile boundaries and inside the tiles."""
+    log(f"case 3d face crossings {prec}")
+    wl = synth.beam_plasma((16, 16, 16), ppc=2, u_th_beam=0.0, u_th_plasma=0.0, steps=1)
+    rng = np.random.default_rng(7)
+    cells = [0, 3, 7, 8, 15]
+    xs, us = [], []
+    for cx in cells:
+        for cy in cells:
+            for cz in cells:
+                for kind in range(8):
+                    # kind bit a: cross along axis a; the sign comes from the draw
+                    off = rng.uniform(0.2, 0.8, 3)
+                    u = rng.normal(0.0, 0.05, 3)
+                    for a in range(3):
+                        if kind >> a & 1:
+                            up = rng.random() < 0.5
+                            off[a] = rng.uniform(0.75, 0.95) if up else rng.uniform(0.05, 0.25)
+                            u[a] = (1.0 if up else -1.0) * rng.uniform(1.5, 3.0)
+                    xs.append((np.array([cx, cy, cz]) + off) * np.array(wl.d))
+                    us.append(u)
+    x = np.ascontiguousarray(np.array(xs).T)
+    u = np.ascontiguousarray(np.array(us).T)
+    parts = [synth.Particles(x, u, np.arange(x.shape[1], dtype=np.uint32)),
+             synth.Particles(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0, dtype=np.uint32))]
+    orc = oracle_run(wl, parts)
+    orc.step(1)
+    g = gpu_run(wl, parts, PRECS[prec])
+    g.step(1)
+    _, _, J = g.read_fields()
+    jmax = np.abs(orc.f.J).max()
+    assert jmax > 0 and J.shape == orc.f.J.shape
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.max(np.abs(J - orc.f.J)) < tol * jmax
+    xg, ug, ids = by_id(*g.read_particles(0))
+    L = np.array([n * 0.2 for n in wl.n])[:, None]
+    assert np.array_equal(ids, np.arange(x.shape[1]))
+    assert np.max(np.abs(periodic_diff(xg, orc.species[0].x, L))) < (1e-12 if prec == "fp64" else 1e-5)
+    g.close()
