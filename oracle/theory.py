@@ -144,6 +144,37 @@ def beam_plasma_species(n_b=0.1, u_beam=math.sqrt(8.0)):
     return [(n_b, u_beam), (1 - n_b, u_p)]
 
 
+# ---------------------------------------------------------------------------
+# Cold-fluid longitudinal (two-stream) dispersion of drifting cold electron
+# species with immobile ions, k along the drifts: each species responds to
+# E_z with the longitudinal mass gamma^3 m, so
+#   1 = sum_s alpha_s / (gamma_s^3 (omega - k v_s)^2) .
+# Clearing the denominators gives a polynomial of degree 2 x (number of
+# species) in omega; the growth rate is the largest imaginary part of its
+# roots.
+def two_stream_cold_roots(k: float, species) -> np.ndarray:
+    """species: iterable of (alpha, u_z).  All roots omega (1/w_p) at k."""
+    terms = []
+    for alpha, u in species:
+        g = math.sqrt(1.0 + u * u)
+        terms.append((alpha / g ** 3, k * u / g))
+    full = np.poly1d([1.0])
+    for _, kv in terms:
+        full = full * np.poly1d([1.0, -kv]) ** 2
+    rhs = np.poly1d([0.0])
+    for i, (a, _) in enumerate(terms):
+        others = np.poly1d([1.0])
+        for j, (_, kv) in enumerate(terms):
+            if j != i:
+                others = others * np.poly1d([1.0, -kv]) ** 2
+        rhs = rhs + a * others
+    return np.roots((full - rhs).coeffs)
+
+
+def two_stream_cold_rate(k: float, species) -> float:
+    return max(0.0, float(np.max(two_stream_cold_roots(k, species).imag)))
+
+
 def two_stream_cold_rate_weak(n_b, n_p, gamma_b):
     """Maximum growth rate of the weak cold beam-plasma two-stream
     instability (beam much thinner than the plasma), in w_pe of the plasma:
