@@ -395,13 +395,24 @@ def test_canonical_z_momentum_eq6(orc):
 
 def test_energy_drift_c1_like(orc):
     """Total energy dV[sum w (gamma - 1) + 1/2 sum (E^2 + B^2)] drifts by
-    less than 1e-3 of itself over 200 steps of the 2D beam-plasma case."""
+    less than 1e-3 of itself over 200 steps of the 2D beam-plasma case, and
+    by less when dx and dt are halved."""
     wl, run = _small_noisy(orc, n=(32, 32), ppc=8)
     recs = run.step(200, diag=True)
     tot = np.array([r["kinetic"].sum() + 0.5 * r["W"].sum() for r in recs])
     assert np.max(np.abs(tot - tot[0])) / tot[0] < 1e-3
     # the fields grew from zero (the system is Weibel unstable)
     assert recs[-1]["W"][3] + recs[-1]["W"][4] > 0
+    # convergence: with dx and dt halved (same box and time, same particles
+    # per cell) the drift shrinks about twofold.  Halving dt alone leaves it
+    # unchanged, and halving dx at a fixed particle count per area raises
+    # it: the drift is grid heating of the cold plasma, not time-step error.
+    d0 = np.max(np.abs(tot - tot[0])) / tot[0]
+    wl2 = synth.beam_plasma((64, 64), d=(0.1, 0.1), dt=0.05, ppc=8, u_th_beam=0.1, steps=400)
+    run2 = orc.OracleRun(2, wl2.n, wl2.d, wl2.dt, _species(wl2, synth.load(wl2), orc), wl2.seed)
+    tot2 = np.array([r["kinetic"].sum() + 0.5 * r["W"].sum() for r in run2.step(400, diag=True)])
+    d1 = np.max(np.abs(tot2 - tot2[0])) / tot2[0]
+    assert d1 < 0.6 * d0, (d0, d1)
 
 
 # --------------------------------------------------------------------------- collisions
