@@ -1413,15 +1413,34 @@ __device__ __forceinline__ void rebin_finalize_body(const KParams *__restrict__ 
 // Grid current: fixed-order FP64 sum of the tile partials covering each node.
 // Along an axis, node i = a0*T + r is held by tile a0 (local r+1), by tile
 // a0-1 when r <= 1 (local r+T+1) and by tile a0+1 when r = T-1 (local 0).
+// In 3D consecutive threads take the nodes of one tile in its own x-y-z
+// order, so that a wave reads 8 rows of one tile partial (nearly contiguous)
+// instead of 64 nodes of a grid row spread over 64/T partials; the summation
+// order per node is the same either way.
 template <typename R, int D>
 __device__ __forceinline__ void reduce_j_body(const KParams *__restrict__ kp, int bid, int nb)
 {
     const int64_t cells = kp->g.cells;
-    const int64_t o = (int64_t)bid * blockDim.x + threadIdx.x;
-    if (o >= cells) return;
+    const int64_t q = (int64_t)bid * blockDim.x + threadIdx.x;
+    if (q >= cells) return;
     const int nx = kp->g.n[0], ny = kp->g.n[1];
-    const int idx[3] = {(int)(o % nx), (int)((o / nx) % ny), (int)(o / ((int64_t)nx * ny))};
     const int T = kp->g.tile[0];
+    int idx[3];
+    int64_t o = q;
+    if constexpr (D == 3) {
+        const int ts = kp->g.tshift[0];
+        const int64_t t = q >> (3 * ts);
+        const int r = (int)(q & (((int64_t)1 << (3 * ts)) - 1));
+        const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
+        idx[0] = (int)(t % ntx) * T + (r & (T - 1));
+        idx[1] = (int)((t / ntx) % nty) * T + ((r >> ts) & (T - 1));
+        idx[2] = (int)(t / ((int64_t)ntx * nty)) * T + (r >> (2 * ts));
+        o = ((int64_t)idx[2] * ny + idx[1]) * nx + idx[0];
+    } else {
+        idx[0] = (int)(q % nx);
+        idx[1] = (int)((q / nx) % ny);
+        idx[2] = 0;
+    }
     const int NJ = kp->nj;
     const int64_t NJ_D = D == 3 ? (int64_t)NJ * NJ * NJ : (int64_t)NJ * NJ;
     int tb[3], r[3];
