@@ -461,7 +461,7 @@ __device__ __forceinline__ void deposit_face(A *sJ, const int (&lc)[3], const R 
 // most 63 and after it both together at most 190.
 template <int D> constexpr int kQueue = D == 3 ? 192 : 128;
 constexpr int kOrderBuckets = 64;
-constexpr int kAdvanceThreads = 256;     // workgroup size of the end-of-step kernel
+constexpr int kAdvanceThreads = 1024;    // workgroup size of the end-of-step kernel (one workgroup per run)
 constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with its own L2
 
 // Movers staged per wave in mixed mode before they are written, grouped by
@@ -1557,7 +1557,7 @@ __device__ __forceinline__ void yee_e_body(const KParams *__restrict__ kp, int b
 // counters, step and parity update.  One workgroup.
 __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int bid, int nb)
 {
-    __shared__ double sred[4][10];
+    __shared__ double sred[kAdvanceThreads / 64][10];
     DevState *st = kp->state;
     const int64_t step = st->step;
     const int par = st->par;
