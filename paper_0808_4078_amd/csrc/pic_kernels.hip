@@ -1272,14 +1272,17 @@ __device__ __forceinline__ void rebin_scan_body(const KParams *__restrict__ kp, 
     }
     __syncthreads();
     // reserve of tile t: m + floor(rest * count_t / total), which sums to at
-    // most the free slots; busy tiles get proportionally more room
+    // most the free slots.  Half of the free slots are spread evenly (a tile
+    // emptied by filamentation still takes the stream of movers from a dense
+    // neighbour: in 3D about 6% of a tile's beam crosses into the next tile
+    // along the drift every step) and half in proportion to the counts
     const int64_t total = s_total;
     const int64_t slack = S.ncap - total;
     if (slack < 0) {
         if (threadIdx.x == 0) atomicOr(&st->fatal, 4);
         return;
     }
-    const int64_t m = min((int64_t)64, slack / (2 * (int64_t)ntiles));
+    const int64_t m = slack / (2 * (int64_t)ntiles);
     const int64_t rest = slack - m * ntiles;
     auto reserve = [&](int64_t c) { return m + (total > 0 ? (rest * c) / total : rest / ntiles); };
     // capacity: count + reserve, rounded to a multiple of kBinAlign particles
