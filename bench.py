@@ -10,8 +10,8 @@ Esirkepov deposit, scattering, tile binning, FP64 current reduction, Yee
 update, diagnostics every 10 steps.  Inputs are generated on the device
 before the timed region.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs
-on one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the library
+runs one GPU per run and has no domain decomposition across GPUs.
 """
 from __future__ import annotations
 
@@ -345,8 +345,8 @@ def main():
                     help="also time K batch steps of the 256-run 2D ensemble (mixed, autotuned tiles; 0 = skip)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} refused: this PIC build runs on a single GPU "
-              "(multi-GPU domain decomposition is not built)", file=sys.stderr)
+        print(f"bench.py: --gpus {a.gpus} refused: the PIC library runs on a single GPU "
+              "(domain decomposition across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if a.copy_probe:
         copy_probe()
