@@ -187,27 +187,49 @@ __device__ __forceinline__ void flush_run(double (*win)[kWin * kWin], double *co
 }
 
 // Sums of the 16 deposit terms v over each run of consecutive lanes with
-// equal `key`; the first lane of each run (returned true) ends with the
-// run's totals.  Doubling: after the step with distance d, lane i holds the
-// sum over [i, i + 2d) within its run.
+// equal `key`; the last lane of each run (returned true) ends with the run's
+// totals.  Segmented inclusive scan toward higher lanes with DPP lane moves
+// (no LDS traffic): shifts by 1, 2, 4, 8 within each row of 16 lanes, then
+// lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and
+// 3.  At each step a lane adds the moved value only if its source lane is in
+// the same run (same run index), so lane i ends with the sum over its run's
+// lanes up to i.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_int(int v, int old)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(double v[16], int sid)
+{
+    const bool same = dpp_int<CTRL, ROWS>(sid, -1) == sid;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const long long b = __double_as_longlong(v[k]);
+        const int lo = dpp_int<CTRL, ROWS>((int)(b & 0xffffffffll), 0);
+        const int hi = dpp_int<CTRL, ROWS>((int)(b >> 32), 0);
+        const double o = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        if (same) v[k] += o;
+        __builtin_amdgcn_sched_barrier(0);     // keep the moves of one value at a time live
+    }
+}
+
 __device__ __forceinline__ bool segment_sums(double v[16], int key)
 {
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
     const int lane = threadIdx.x & 63;
     const int prev = __shfl_up(key, 1, 64);
     const bool head = lane == 0 || prev != key;
     const uint64_t heads = __ballot(head);
     const int sid = __popcll(heads & (~0ull >> (63 - lane)));     // run index of this lane
-#pragma unroll 1
-    for (int d = 1; d < 64; d <<= 1) {
-        const int sd = __shfl_down(sid, d, 64);
-        const bool same = lane + d < 64 && sd == sid;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const double o = __shfl_down(v[k], d, 64);
-            if (same) v[k] += o;
-        }
-    }
-    return head;
+    scan_step<kRowShr + 1, 0xf>(v, sid);
+    scan_step<kRowShr + 2, 0xf>(v, sid);
+    scan_step<kRowShr + 4, 0xf>(v, sid);
+    scan_step<kRowShr + 8, 0xf>(v, sid);
+    scan_step<kRowBcast15, 0xa>(v, sid);
+    scan_step<kRowBcast31, 0xc>(v, sid);
+    return lane == 63 || ((heads >> (lane + 1)) & 1ull);
 }
 
 // Gather at x^n (a, psi at the nodes, grad a at the staggered points),
@@ -324,7 +346,7 @@ __device__ __forceinline__ void deposit_terms(const Params &P, const S &star, co
 // (kFw nodes per axis) are staged in LDS for the gathers (a particle outside
 // the window gathers from the grid).  The particles are cell-sorted: a run's
 // deposit terms are summed in registers while its cell stays the same, then
-// summed across consecutive lanes of the same cell, and the first lane of
+// summed across consecutive lanes of the same cell, and the last lane of
 // each such group adds them to an LDS window of (tile + 2 margin + 1)^2
 // nodes, which is added to the global deposit at the end (atomics:
 // neighbouring windows overlap).
@@ -334,8 +356,10 @@ __device__ __forceinline__ void deposit_terms(const Params &P, const S &star, co
 // linearised deposit about a^0.
 constexpr int kRun = 4;
 
+// (Three waves per SIMD: the register budget that keeps the DPP scan's moves
+// from pushing the step kernel to two.)
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_particle(const Params *__restrict__ pp)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_particle(const Params *__restrict__ pp)
 {
     __shared__ double win[4][kWin * kWin];
     __shared__ double fw[3][kFw * kFw];        // a^n, a* = 2 a^n - a^(n-1), psi on the field window
