@@ -450,24 +450,66 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // In-place radix-2 decimation-in-time transforms of `batch` sequences of
 // length 2^logn stored back to back in LDS, input in bit-reversed order,
 // output in natural order; tw[t] = exp(-2 pi i t / 2^logn).
+__device__ __forceinline__ double2 cmul(double2 w, double2 v)
+{
+    return make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+}
+
+__device__ __forceinline__ double2 twiddle(const double2 *__restrict__ tw, int t, bool inverse)
+{
+    double2 w = tw[t];
+    if (inverse) w.y = -w.y;
+    return w;
+}
+
+// Stages are taken two at a time: the four values that two consecutive
+// radix-2 stages combine (i, i+h, i+2h, i+3h) are loaded once, both stages'
+// butterflies are done in registers with the same arithmetic as one stage
+// at a time, and they are stored once -- half the LDS round trips and
+// barriers.  An odd stage count ends with one single stage.
 __device__ void fft_lds(double2 *z, int logn, int batch, const double2 *__restrict__ tw, bool inverse)
 {
     const int n = 1 << logn;
-    const int hn = n >> 1;
-    const int total = batch * hn;
-    for (int s = 1; s <= logn; ++s) {
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int h = 1 << (s - 1);
+        const int qn = n >> 2;
+        const int total = batch * qn;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const int b = e >> (logn - 2);
+            const int k = e & (qn - 1);
+            const int pos = k & (h - 1);
+            const int i = ((k >> (s - 1)) << (s + 1)) + pos;
+            double2 *zb = z + b * n;
+            const double2 w1 = twiddle(tw, pos << (logn - s), inverse);
+            const double2 w2 = twiddle(tw, pos << (logn - s - 1), inverse);
+            const double2 w3 = twiddle(tw, (pos + h) << (logn - s - 1), inverse);
+            const double2 a0 = zb[i], a1 = zb[i + h], a2 = zb[i + 2 * h], a3 = zb[i + 3 * h];
+            // stage s: (i, i+h) and (i+2h, i+3h)
+            const double2 t1 = cmul(w1, a1), t3 = cmul(w1, a3);
+            const double2 b0 = make_double2(a0.x + t1.x, a0.y + t1.y), b1 = make_double2(a0.x - t1.x, a0.y - t1.y);
+            const double2 b2 = make_double2(a2.x + t3.x, a2.y + t3.y), b3 = make_double2(a2.x - t3.x, a2.y - t3.y);
+            // stage s+1: (i, i+2h) and (i+h, i+3h)
+            const double2 u2 = cmul(w2, b2), u3 = cmul(w3, b3);
+            zb[i] = make_double2(b0.x + u2.x, b0.y + u2.y);
+            zb[i + 2 * h] = make_double2(b0.x - u2.x, b0.y - u2.y);
+            zb[i + h] = make_double2(b1.x + u3.x, b1.y + u3.y);
+            zb[i + 3 * h] = make_double2(b1.x - u3.x, b1.y - u3.y);
+        }
+        __syncthreads();
+    }
+    if (s == logn) {
         const int half = 1 << (s - 1);
-        const int tsh = logn - s;
+        const int hn = n >> 1;
+        const int total = batch * hn;
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
             const int b = e >> (logn - 1);
             const int k = e & (hn - 1);
             const int pos = k & (half - 1);
             const int i1 = ((k >> (s - 1)) << s) + pos;
-            double2 w = tw[pos << tsh];
-            if (inverse) w.y = -w.y;
             double2 *zb = z + b * n;
-            const double2 u = zb[i1], v0 = zb[i1 + half];
-            const double2 v = make_double2(w.x * v0.x - w.y * v0.y, w.x * v0.y + w.y * v0.x);
+            const double2 w = twiddle(tw, pos << (logn - s), inverse);
+            const double2 u = zb[i1], v = cmul(w, zb[i1 + half]);
             zb[i1] = make_double2(u.x + v.x, u.y + v.y);
             zb[i1 + half] = make_double2(u.x - v.x, u.y - v.y);
         }
