@@ -167,3 +167,34 @@ def test_tuner_and_cache(pic, tmp_path):
     assert not any(v["cached"] for v in rep.values())
     tiles2, rep2 = autotune.choose_tiles(wls, nsteps=3, cache_path=cache)
     assert tiles2 == tiles and all(v["cached"] for v in rep2.values())
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_batch_3d_members_match_runs_stepped_alone(pic, prec, bar):
+    """3D3V members of uneven size (8^3 tiles) in one batch, against the same
+    runs stepped alone."""
+    log(f"case batch 3d vs alone {prec}")
+    p = pic.PIC_PREC_FP64 if prec == "fp64" else pic.PIC_PREC_MIXED
+    shapes = [((16, 16, 16), 4, 0.1), ((16, 16, 32), 2, 0.3), ((32, 16, 16), 4, 0.2)]
+
+    def runs():
+        out = []
+        for i, (n, ppc, uth) in enumerate(shapes):
+            wl = synth.beam_plasma(n, ppc=ppc, u_th_beam=uth, name=f"m3d{i}", seed=synth.SEED + 200 + i)
+            g, sp = pic.workload_descs(wl, precision=p, tile=8, diag_every=5)
+            out.append(pic.Run(g, sp))
+        return out
+    alone, members = runs(), runs()
+    batch = pic.Batch(members)
+    for _ in range(2):
+        batch.step(15)
+        for r in alone:
+            r.step(15)
+        batch.sync()
+        for r in alone:
+            r.sync()
+        errs = [_compare(pic, m, r, bar) for m, r in zip(members, alone)]
+        log(f"  max member field error {max(errs):.3e}")
+    batch.close()
+    for r in alone + members:
+        r.close()
