@@ -198,3 +198,41 @@ def test_batch_3d_members_match_runs_stepped_alone(pic, prec, bar):
     batch.close()
     for r in alone + members:
         r.close()
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_batch_with_coulomb_members(pic, prec, bar):
+    """A batch whose members mix the two scattering models (Coulomb
+    small-angle and isotropic at a fixed rate) runs the kernel that carries
+    the Coulomb branch; each member matches its twin stepped alone."""
+    log(f"case batch coulomb {prec}")
+    p = pic.PIC_PREC_FP64 if prec == "fp64" else pic.PIC_PREC_MIXED
+    cfg = [((32, 32), 16, pic.PIC_COLL_COULOMB), ((64, 32), 12, 0), ((48, 48), 8, pic.PIC_COLL_COULOMB)]
+
+    def runs():
+        out = []
+        for i, (n, ppc, model) in enumerate(cfg):
+            wl = synth.beam_plasma(n, ppc=ppc, u_th_beam=0.2, nu=0.05, coll_model=model, coll_vref=0.1,
+                                   name=f"mc{i}", seed=synth.SEED + 300 + i)
+            g, sp = pic.workload_descs(wl, precision=p, tile=16, diag_every=5)
+            out.append(pic.Run(g, sp))
+        return out
+    alone, members = runs(), runs()
+    batch = pic.Batch(members)
+    for _ in range(2):
+        batch.step(15)
+        for r in alone:
+            r.step(15)
+        batch.sync()
+        for r in alone:
+            r.sync()
+        errs = [_compare(pic, m, r, bar) for m, r in zip(members, alone)]
+        log(f"  max member field error {max(errs):.3e}")
+    # the Coulomb members turn every plasma particle every step
+    for m, (n, ppc, model) in zip(members, cfg):
+        h = m.history()[-1]
+        if model == pic.PIC_COLL_COULOMB:
+            assert h["collisions"] == n[0] * n[1] * ppc
+    batch.close()
+    for r in alone + members:
+        r.close()
