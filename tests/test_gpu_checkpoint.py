@@ -57,3 +57,37 @@ def test_restore_continues_the_run(pic, prec, tmp_path):
     assert e.value.code == -6
     for r in (a, b, c):
         r.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_restore_continues_a_3d_run(pic, prec, tmp_path):
+    """The same for a 3D3V run (8^3 tiles), with the history continued."""
+    log(f"case checkpoint 3d {prec}")
+    p = pic.PIC_PREC_FP64 if prec == "fp64" else pic.PIC_PREC_MIXED
+    wl = synth.beam_plasma((16, 16, 32), ppc=4, u_th_beam=0.2, name="ckpt3d")
+    # ids stored for every species (collisionless ones keep none by default)
+    g, sp = pic.workload_descs(wl, precision=p, diag_every=5, flags=pic.PIC_FLAG_TRACK_IDS)
+    a = pic.Run(g, sp)
+    a.step(10)
+    path = str(tmp_path / "run3d.ckpt")
+    a.checkpoint(path)
+    a.step(10)
+    Ea, Ba, _ = a.read_fields()
+    g2, sp2 = pic.workload_descs(wl, precision=p, diag_every=5,
+                                 flags=pic.PIC_FLAG_HOST_LOAD | pic.PIC_FLAG_TRACK_IDS)
+    b = pic.Run(g2, sp2)
+    b.restore(path)
+    b.step(10)
+    Eb, Bb, _ = b.read_fields()
+    err = rel_err(stack(Eb, Bb), stack(Ea, Ba))
+    log(f"  restored vs original field error {err:.3e}")
+    assert err < 1e-12
+    assert [r["step"] for r in b.history()] == [r["step"] for r in a.history()]
+    for s in range(2):
+        xa, ua, ia = a.read_particles(s)
+        xb, ub, ib = b.read_particles(s)
+        oa, ob = np.argsort(ia), np.argsort(ib)
+        assert np.array_equal(ia[oa], ib[ob])
+        assert np.max(np.abs(xa[:, oa] - xb[:, ob])) < 1e-12
+    for r in (a, b):
+        r.close()
