@@ -141,3 +141,30 @@ def test_full_size_mixed_both_species(pic):
     deposit of every particle that reaches them."""
     log("case full size C3 mixed, ids tracked (sampled)")
     _sampled_step(pic, "mixed", 30, 2e-5, 2e-5, flags=pic.PIC_FLAG_TRACK_IDS, j_nodes=8)
+
+
+def test_full_size_c4_gauss_and_counts(pic):
+    """C4 at its full size in the configuration bench.py times (256 x 256 x
+    512 cells, 8 particles per cell per species, 536 870 912 particles, 8^3
+    tiles, 200% store reserve): reading the particles back is out of reach,
+    so the check is on properties that hold at any size -- Gauss's law kept
+    to the FP32 level of the mixed deposit at every record, and every
+    particle present."""
+    log("case full size C4 mixed (Gauss residual, counts)")
+    import bench
+    wl = synth.C4
+    g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=8, diag_every=10,
+                               flags=pic.PIC_FLAG_GAUSS_RESIDUAL, reserve=bench.RESERVE_3D)
+    r = pic.Run(g, sp)
+    r.step(31)
+    r.sync()
+    h = r.history()
+    r.close()
+    n_expect = [wl.cells * sc.ppc for sc in wl.species]
+    dev = max(x["rho_dev"] for x in h)
+    worst = max(x["gauss_resid"] for x in h)
+    log(f"  records {len(h)}, max |rho - rho_0| {dev:.3e}, worst residual {worst:.3e}")
+    assert [x["step"] for x in h] == [0, 10, 20, 30]
+    assert dev > 1e-3 and worst < 1e-4 * dev
+    for x in h:
+        assert list(x["n_particles"][:2]) == n_expect
