@@ -241,13 +241,14 @@ def test_cold_beam_weibel_rate_gpu(pic, prec):
 
 
 # --------------------------------------------------------------------------- 3D
-@pytest.mark.parametrize("prec,bar", [("fp64", 1e-5), ("mixed", 1e-3)])
-def test_3d_fields_and_particles(pic, prec, bar):
-    """3D3V (beam along z, collisionless, 8^3 tiles) on a 16x16x32 box:
-    fields within the bar every 10 steps over 60 steps and particles by id
-    at the end."""
-    log(f"case 3d {prec}")
-    wl = synth.beam_plasma((16, 16, 32), ppc=4, u_th_beam=0.1, u_th_plasma=0.02, steps=60)
+@pytest.mark.parametrize("prec,bar,n", [("fp64", 1e-5, (16, 16, 32)), ("mixed", 1e-3, (16, 16, 32)),
+                                         ("fp64", 1e-5, (32, 32, 64))])
+def test_3d_fields_and_particles(pic, prec, bar, n):
+    """3D3V (beam along z, collisionless, 8^3 tiles) on a 16x16x32 box and
+    (FP64) on the reduced 32x32x64 grid: fields within the bar every 10 steps
+    over 60 steps and particles by id at the end."""
+    log(f"case 3d {prec} {n}")
+    wl = synth.beam_plasma(n, ppc=4, u_th_beam=0.1, u_th_plasma=0.02, steps=60)
     parts = synth.load(wl)
     orc = oracle_run(wl, parts)
     g = gpu_run(wl, parts, PRECS[prec], diag_every=10)
