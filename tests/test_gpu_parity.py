@@ -399,3 +399,36 @@ def test_two_stream_growth_3d_gpu(pic, prec, bar):
     E, _, _ = g.read_fields()
     assert rel_err(np.asarray(E[2]), E_o[2]) < bar
     g.close()
+
+
+_C3S_CACHE = {}
+
+
+@pytest.mark.parametrize("prec,w_bar,k_bar", [("fp64", 1e-10, 1e-12), ("mixed", 1e-4, 1e-6)])
+def test_c3_physics_energy_records(pic, prec, w_bar, k_bar):
+    """The C3 workload's physics (beam u_th 0.3 with its return current
+    scattering at nu = 0.05, 64 particles per cell per species) on a 128^2
+    box the oracle can step, 300 steps: every diagnostic record's six field
+    energies W_i and two kinetic energies against the FP64 oracle's -- the
+    error of the mixed-precision path on this workload, stated per record."""
+    log(f"case c3 physics energy records {prec}")
+    wl = synth.beam_plasma((128, 128), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=300,
+                           name="c3-128")
+    parts = synth.load(wl)
+    if "recs" not in _C3S_CACHE:
+        orc = oracle_run(wl, parts)
+        _C3S_CACHE["recs"] = orc.step(wl.steps, diag=True)[::10]
+    ro = _C3S_CACHE["recs"]
+    g = gpu_run(wl, parts, PRECS[prec], diag_every=10)
+    g.step(wl.steps)
+    hg = g.history()
+    g.close()
+    assert [h["step"] for h in hg] == [r["step"] for r in ro]
+    Wg = np.array([h["W"] for h in hg])
+    Wo = np.array([r["W"] for r in ro])
+    kg = np.array([h["kinetic"][:2] for h in hg])
+    ko = np.array([r["kinetic"][:2] for r in ro])
+    w_err = float(np.max(np.abs(Wg - Wo)[1:] / np.abs(Wo)[1:]))
+    k_err = float(np.max(np.abs(kg - ko) / ko))
+    log(f"  worst per-record W_i error {w_err:.2e}, kinetic {k_err:.2e}")
+    assert w_err < w_bar and k_err < k_bar
