@@ -18,7 +18,7 @@ Units: x in c/w_p, u = gamma v / c, densities in n0, charge e, mass m_e.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 
 import numpy as np
 

@@ -7,7 +7,6 @@ import sys
 import numpy as np
 
 import oracle
-import synth
 
 
 def log(*a):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from pic_cases import gpu_run, log
+from pic_cases import log
 
 pytestmark = pytest.mark.gpu
 
