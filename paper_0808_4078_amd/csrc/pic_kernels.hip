@@ -11,6 +11,8 @@
 //                    incoming-mover reserve overflowed during the step)
 //   k_reduce_j       fixed-order FP64 sum of the overlapping tile currents
 //   k_yee_b/k_yee_e  B half step, E full step with -J, B half step
+//   k_rho/k_gauss    (only with PIC_FLAG_GAUSS_RESIDUAL, on diagnostic steps)
+//                    CIC charge of the particles and max |div E - (rho - rho_0)|
 //   k_advance        diagnostic record, counter reset, step/parity update
 //
 // The numerical scheme is the relativistic Boris push (Boris 1970), the
@@ -20,8 +22,10 @@
 // half-integer positions stored at the lower integer index, J with E.
 // Collisions follow the fluid drag of Eq. (3): each step a collisional
 // particle is scattered isotropically off the immobile ions with
-// probability 1 - exp(-nu dt), |u| kept.  Units: t in 1/w_p, x in c/w_p,
-// u = gamma v/c, fields e F/(m c w_p).
+// probability 1 - exp(-nu dt), |u| kept; or, per species, every particle is
+// turned by a small Coulomb angle whose variance scales as v^-3
+// (Takizuka-Abe), |u| kept.  Units: t in 1/w_p, x in c/w_p, u = gamma v/c,
+// fields e F/(m c w_p).
 #include <hip/hip_ext.h>
 #include <algorithm>
 #include <hip/hip_runtime.h>
