@@ -395,11 +395,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
         int key = -1, ci0 = 0, cj0 = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = 0.0;
+        // the next particle's loads are issued before the current one is
+        // processed, so they overlap its arithmetic
+        const int i0 = base + (int)threadIdx.x * kRun;
+        double nx_ = 0.0, ny_ = 0.0, nux = 0.0, nuy = 0.0, npz = 0.0;
+        if (i0 < s1) {
+            nx_ = X[i0];
+            ny_ = Y[i0];
+            nux = UX[i0];
+            nuy = UY[i0];
+            npz = PZ[i0];
+        }
 #pragma unroll 1
         for (int r = 0; r < kRun; ++r) {
-            const int idx = base + (int)threadIdx.x * kRun + r;
+            const int idx = i0 + r;
             if (idx >= s1) break;
-            double x = X[idx], y = Y[idx], ux = UX[idx], uy = UY[idx], pz = PZ[idx];
+            double x = nx_, y = ny_, ux = nux, uy = nuy, pz = npz;
+            if (r + 1 < kRun && idx + 1 < s1) {
+                nx_ = X[idx + 1];
+                ny_ = Y[idx + 1];
+                nux = UX[idx + 1];
+                nuy = UY[idx + 1];
+                npz = PZ[idx + 1];
+            }
             if (MODE == 0) {
                 const int di = wrapi((int)floor(x * P.inv_dx) - fx0, nx), dj = wrapi((int)floor(y * P.inv_dy) - fy0, ny);
                 if (di >= 1 && di <= kFw - 3 && dj >= 1 && dj <= kFw - 3)
