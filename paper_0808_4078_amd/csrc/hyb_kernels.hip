@@ -868,11 +868,23 @@ __global__ __launch_bounds__(kThreads) void k_sort_count_tiles(const Params *__r
     for (int e = threadIdx.x; e < kWinC * kWinC; e += kThreads) hist[e] = 0;
     __syncthreads();
     const int s0 = P.tile_start[cur][b], s1 = P.tile_start[cur][b + 1];
+    const double *X = P.x[cur], *Y = P.y[cur];
+    // each thread's next particle is loaded while the current one is binned
+    double nx_ = 0.0, ny_ = 0.0;
+    if (s0 + (int)threadIdx.x < s1) {
+        nx_ = X[s0 + threadIdx.x];
+        ny_ = Y[s0 + threadIdx.x];
+    }
     for (int base = s0; base < s1; base += kThreads) {
         const int i = base + (int)threadIdx.x;
         const bool valid = i < s1;
+        const double x = nx_, y = ny_;
+        if (i + kThreads < s1) {
+            nx_ = X[i + kThreads];
+            ny_ = Y[i + kThreads];
+        }
         int key = 0, bin = -1;
-        if (valid) bin = tile_bin(P.x[cur][i], P.y[cur][i], wcx, wcy, P, &key);
+        if (valid) bin = tile_bin(x, y, wcx, wcy, P, &key);
         if (valid && bin < 0) atomicAdd(P.cell_count + key, 1);
         (void)wave_lds_add(hist, valid && bin >= 0, bin);
     }
@@ -904,25 +916,32 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter_tiles(const Params *_
     }
     __syncthreads();
     const int s0 = P.tile_start[s][b], s1 = P.tile_start[s][b + 1];
+    const double *X = P.x[s], *Y = P.y[s], *UX = P.ux[s], *UY = P.uy[s], *PZ = P.pz[s];
+    const uint32_t *ID = P.id[s];
+    // each thread's next particle is loaded while the current one is placed
+    struct Part {
+        double x, y, ux, uy, pz;
+        uint32_t id;
+    };
+    auto load = [&](int i) { return Part{X[i], Y[i], UX[i], UY[i], PZ[i], ID[i]}; };
+    Part nxt{};
+    if (s0 + (int)threadIdx.x < s1) nxt = load(s0 + (int)threadIdx.x);
     for (int base = s0; base < s1; base += kThreads) {
         const int i = base + (int)threadIdx.x;
         const bool valid = i < s1;
-        double x = 0.0, y = 0.0;
+        const Part q = nxt;
+        if (i + kThreads < s1) nxt = load(i + kThreads);
         int key = 0, bin = -1;
-        if (valid) {
-            x = P.x[s][i];
-            y = P.y[s][i];
-            bin = tile_bin(x, y, wcx, wcy, P, &key);
-        }
+        if (valid) bin = tile_bin(q.x, q.y, wcx, wcy, P, &key);
         const int rank = wave_lds_add(hcur, valid && bin >= 0, bin);
         if (valid) {
             const int slot = bin >= 0 ? hbase[bin] + rank : atomicAdd(P.cell_start + key, 1);
-            P.x[d][slot] = x;
-            P.y[d][slot] = y;
-            P.ux[d][slot] = P.ux[s][i];
-            P.uy[d][slot] = P.uy[s][i];
-            P.pz[d][slot] = P.pz[s][i];
-            P.id[d][slot] = P.id[s][i];
+            P.x[d][slot] = q.x;
+            P.y[d][slot] = q.y;
+            P.ux[d][slot] = q.ux;
+            P.uy[d][slot] = q.uy;
+            P.pz[d][slot] = q.pz;
+            P.id[d][slot] = q.id;
         }
     }
 }
