@@ -1456,33 +1456,51 @@ __device__ __forceinline__ void reduce_j_body(const KParams *__restrict__ kp, in
         r[a] = idx[a] - tb[a] * T;
     }
     const GLB R *Jt = gbl((const R *)kp->Jtile);
-    double jx = 0.0, jy = 0.0, jz = 0.0;
-    const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
-        const int lz = D == 3 ? r[2] + 1 - dz * T : 0;
-        if (lz < 0 || lz >= NJ) continue;
-        int tz = tb[2] + dz;
-        tz += tz < 0 ? kp->g.nt[2] : 0;
-        tz -= tz >= kp->g.nt[2] ? kp->g.nt[2] : 0;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int ly = r[1] + 1 - dy * T;
-            if (ly < 0 || ly >= NJ) continue;
-            int ty = tb[1] + dy;
-            ty += ty < 0 ? kp->g.nt[1] : 0;
-            ty -= ty >= kp->g.nt[1] ? kp->g.nt[1] : 0;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int lx = r[0] + 1 - dx * T;
-                if (lx < 0 || lx >= NJ) continue;
-                int tx = tb[0] + dx;
-                tx += tx < 0 ? kp->g.nt[0] : 0;
-                tx -= tx >= kp->g.nt[0] ? kp->g.nt[0] : 0;
-                const int64_t t = ((int64_t)tz * kp->g.nt[1] + ty) * kp->g.nt[0] + tx;
-                const GLB R *p = Jt + t * 3 * NJ_D + ((int64_t)lz * NJ + ly) * NJ + lx;
-                jx += (double)p[0];
-                jy += (double)p[NJ_D];
-                jz += (double)p[2 * NJ_D];
+    // Per axis the tiles holding the node, in increasing tile order: the one
+    // below (local index r + 1 + T) when r <= 1, the node's own tile (r + 1),
+    // the one above (local 0) when r = T - 1; tiles are at least 8 cells, so
+    // at most two per axis.  All of a node's partials are loaded first and
+    // then summed in that fixed order.
+    int cn[3], ct[3][2], cl[3][2];
+    for (int a = 0; a < 3; ++a) {
+        cn[a] = 0;
+        if (a < D) {
+            const int ntile = kp->g.nt[a];
+            if (r[a] <= 1) {
+                ct[a][cn[a]] = tb[a] == 0 ? ntile - 1 : tb[a] - 1;
+                cl[a][cn[a]++] = r[a] + 1 + T;
             }
+            ct[a][cn[a]] = tb[a];
+            cl[a][cn[a]++] = r[a] + 1;
+            if (r[a] == T - 1 && cn[a] < 2) {
+                ct[a][cn[a]] = tb[a] + 1 == ntile ? 0 : tb[a] + 1;
+                cl[a][cn[a]++] = 0;
+            }
+        } else {
+            ct[a][0] = 0;
+            cl[a][0] = 0;
+            cn[a] = 1;
         }
+    }
+    R vx[8], vy[8], vz[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int iz = k >> 2, iy = (k >> 1) & 1, ix = k & 1;
+        vx[k] = vy[k] = vz[k] = R(0);
+        if (iz < cn[2] && iy < cn[1] && ix < cn[0]) {
+            const int64_t t = ((int64_t)ct[2][iz] * kp->g.nt[1] + ct[1][iy]) * kp->g.nt[0] + ct[0][ix];
+            const GLB R *p = Jt + t * 3 * NJ_D + ((int64_t)cl[2][iz] * NJ + cl[1][iy]) * NJ + cl[0][ix];
+            vx[k] = p[0];
+            vy[k] = p[NJ_D];
+            vz[k] = p[2 * NJ_D];
+        }
+    }
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        jx += (double)vx[k];
+        jy += (double)vy[k];
+        jz += (double)vz[k];
     }
     kp->J[o] = jx;
     kp->J[cells + o] = jy;
