@@ -168,3 +168,38 @@ def test_full_size_c4_gauss_and_counts(pic):
     assert dev > 1e-3 and worst < 1e-4 * dev
     for x in h:
         assert list(x["n_particles"][:2]) == n_expect
+
+
+def test_full_size_c5_counts_and_members(pic):
+    """C5 at its full size (256 uneven 2D runs, 1.68e9 particles) as one
+    batch, 20 steps: every member keeps all its particles, and three members
+    of different sizes match their twins stepped alone exactly (mixed
+    precision: the FP64 tile sums of FP32 terms do not depend on order)."""
+    log("case full size C5 (counts, members vs alone)")
+    members = synth.c5_members()
+
+    def make(wl):
+        g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=16, diag_every=10)
+        return pic.Run(g, sp)
+    runs = [make(wl) for wl in members]
+    batch = pic.Batch(runs)
+    batch.step(20)
+    batch.sync()
+    for r, wl in zip(runs, members):
+        n = r.diagnostics()["n_particles"][:2].tolist()
+        assert n == [wl.cells * sc.ppc for sc in wl.species], (wl.name, n)
+    picks = sorted({0, len(members) // 2, len(members) - 1} |
+                   {int(np.argmax([wl.cells for wl in members]))})
+    for i in picks:
+        alone = make(members[i])
+        alone.step(20)
+        alone.sync()
+        Ea, Ba, _ = alone.read_fields()
+        Eb, Bb, _ = runs[i].read_fields()
+        log(f"  member {i} ({members[i].n[0]}^2): max |field difference| "
+            f"{max(np.abs(Ea - Eb).max(), np.abs(Ba - Bb).max()):.1e}")
+        assert np.array_equal(Ea, Eb) and np.array_equal(Ba, Bb)
+        alone.close()
+    batch.close()
+    for r in runs:
+        r.close()
