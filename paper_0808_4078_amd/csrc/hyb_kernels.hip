@@ -354,7 +354,10 @@ __device__ __forceinline__ void deposit_terms(const Params &P, const S &star, co
 // x^(n+1)).  MODE 1 (init): deposit the exact current of the given u_z (held
 // in the p_z array).  MODE 2 (init): p_z = u_z - a^0(x), then the
 // linearised deposit about a^0.
-constexpr int kRun = 4;
+// Two particles per run: longer runs sum more terms in registers but spread
+// each load instruction over kRun x 8 bytes per lane (4: +14%, 8: x2.1 at
+// the benchmark size); one per run leaves the lane scan to do all merging.
+constexpr int kRun = 2;
 
 // (Three waves per SIMD: the register budget that keeps the DPP scan's moves
 // from pushing the step kernel to two.)
