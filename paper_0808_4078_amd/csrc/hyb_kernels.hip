@@ -598,7 +598,13 @@ __global__ __launch_bounds__(kColThreads) void k_cols(const Params *__restrict__
     extern __shared__ double2 z[];
     const Params &P = *pp;
     const int CB = P.cols_per_block, ny = P.ny, nx = P.nx, ly = P.ly;
-    const int c0 = blockIdx.x * CB;
+    // Workgroups go to the 8 XCDs in turn, and a row's CB values fill only
+    // part of a 128-byte line: consecutive workgroups on one XCD take
+    // neighbouring column groups, so both halves of a line are fetched into
+    // the same L2 (a bijection of the groups when the count divides by 8).
+    const int nbk = (int)gridDim.x, bk = (int)blockIdx.x;
+    const int grp = (nbk & 7) ? bk : (bk & 7) * (nbk >> 3) + (bk >> 3);
+    const int c0 = grp * CB;
     for (int e = threadIdx.x; e < CB * ny; e += blockDim.x) {
         const int c = e & (CB - 1), j = e / CB;
         z[c * ny + brev(j, ly)] = P.W[(int64_t)j * nx + c0 + c];
