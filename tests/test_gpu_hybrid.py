@@ -69,6 +69,28 @@ def test_hybrid_parity_fp64(pic, sort_every):
     g.close()
 
 
+@pytest.mark.parametrize("n", [(256, 128), (128, 256)])
+def test_hybrid_parity_fp64_rectangular(pic, n):
+    """Rectangular grids (4 ppc, 131 072 particles, sort every 5 steps): the
+    column transform runs 8 workgroups of several columns each, the case in
+    which the workgroups take their column groups XCD by XCD; 20 steps, the
+    state and every Eq. (7) record, FP64 to 1e-9."""
+    log(f"case hybrid parity rectangular {n}")
+    wl = replace(synth.H1, n=n, ppc=4, steps=20, name=f"H1-{n[0]}x{n[1]}")
+    orc, g = _pair(pic, wl, sort_every=5)
+    _compare(orc, g, wl, 1e-11)
+    orecs = orc.step(wl.steps, diag=True)
+    g.step(wl.steps)
+    _compare(orc, g, wl, 1e-9)
+    grecs = g.history()
+    assert [r["step"] for r in grecs] == [r["step"] for r in orecs]
+    for k in ("beam_energy", "beam_a2", "grad_energy", "a2_energy", "eq7", "W_Ez", "beam_pz", "mean_a"):
+        got = np.array([r[k] for r in grecs])
+        want = np.array([r[k] for r in orecs])
+        assert np.max(np.abs(got - want)) <= 1e-9 * max(1e-12, np.max(np.abs(want))), k
+    g.close()
+
+
 def test_hybrid_graph_matches_direct_launches(pic):
     log("case hybrid graph vs direct")
     wl = replace(synth.H1, steps=20)
