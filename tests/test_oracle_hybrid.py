@@ -213,3 +213,101 @@ def test_test_particle_invariant_in_a_static_mode():
     dev = np.max(np.abs(inv - inv[0]), axis=0)
     swing = K2 * np.max(np.abs(a_static)) ** 2 / 2
     assert np.median(dev) < 0.05 * swing and np.max(dev) < 0.3 * swing, (np.median(dev), np.max(dev), swing)
+
+
+def _self_consistent_a(h, start):
+    """a^n solving Eq. (2) with the beam current taken exactly from Eq. (6)
+    (u_z = P + a at every particle): the linearisation is repeated about the
+    latest iterate until a stops changing (Newton's method on the nonlinear
+    current), each linear solve swept to convergence."""
+    a = start.copy()
+    iters = h.iters
+    h.iters = 40
+    try:
+        for _ in range(60):
+            an = h.solve(h._deposit_linearised(h.x, h.u, a), h.psi, a)
+            change = float(np.max(np.abs(an - a)))
+            a = an
+            if change < 1e-17:
+                break
+    finally:
+        h.iters = iters
+    return a
+
+
+def _predictor_error(wl, T):
+    """Largest difference, one step after time T, between the oracle's a^n
+    (the beam current linearised about its predictor a*) and the
+    self-consistent a^n from the same state."""
+    h = _run(wl)
+    h.step(int(round(T / wl.dt)))
+    a_lin = h.solve(h.dep, h.psi, h.predict(h.a_cur, h.a_prev))
+    return float(np.max(np.abs(a_lin - _self_consistent_a(h, a_lin)))), float(np.max(np.abs(a_lin)))
+
+
+UNIFORM_DRIFT = synth.HybridWorkload("u", (16, 16), (0.2, 0.2), 0.1, 0, 0.1, 4, synth.U_BEAM, 0.0, 0.5,
+                                     lattice=True)
+
+
+def _predictor_orders(dts=(0.4, 0.2, 0.1)):
+    errs = [_predictor_error(replace(UNIFORM_DRIFT, dt=dt), 10.0)[0] for dt in dts]
+    return errs, [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+
+
+def test_predictor_linearisation_converges_at_fourth_order():
+    """dt convergence of the step's linearisation (reading H4): the beam
+    current of Eq. (2) is linearised about a* = 2 a^(n-1) - a^(n-2), so
+    a^n - a* = O(dt^2) and the step's a^n differs from the self-consistent
+    solution of Eqs. (2) and (6) by O(dt^4).  In the uniform beam's resistive
+    slow-down (Eq. 3 drives a steadily, nu = 0.5) the one-step difference at
+    t = 10 falls 15.5x per halving of dt (0.4 -> 0.2 -> 0.1; bar: 10x to 25x)
+    and stays below 1e-10 of |a|.  Linearising about a^(n-1) instead would
+    leave O(dt^2) (4x per halving, 1.5e-6 at dt = 0.4): see the mutant test
+    below."""
+    errs, ratios = _predictor_orders()
+    assert all(10.0 < r < 25.0 for r in ratios), (errs, ratios)
+    assert errs[0] < 1e-10
+
+
+def test_predictor_mutant_fails_the_order_pin(monkeypatch):
+    """The planted mistake a* = a^(n-1) fails the fourth-order pin above."""
+    monkeypatch.setattr(Hybrid, "predict", staticmethod(lambda a1, a2: a1.copy()))
+    errs, ratios = _predictor_orders()
+    assert not all(10.0 < r < 25.0 for r in ratios)
+    assert all(3.5 < r < 4.5 for r in ratios), ratios
+
+
+def test_predictor_error_small_with_a_moving_mode():
+    """With a seeded mode moving the beam across the cells (the deposit's
+    cloud-in-cell kinks make a(t) at a node only piecewise smooth), the
+    one-step linearisation error at dt = 0.1 stays below 1e-10 of |a|
+    (6e-13 measured); the a^(n-1) mutant gives 1.7e-7."""
+    wl = replace(UNIFORM_DRIFT, n=(64, 8), seed_mode=(1, 0.05))
+    err, amax = _predictor_error(wl, 10.0)
+    assert err < 1e-10 * amax, (err, amax)
+
+
+def test_record_beam_momentum_and_inductive_field_energy():
+    """Record terms of the uniform cold beam in its resistive slow-down
+    (Eqs. 2, 3, 6 at k = 0): every particle has u_z = u_b + a^n - a^0
+    (Eq. 6), so beam_pz = L_x L_y n_b (u_b + a^n - a^0) exactly; E_z = -d_t a
+    is uniform, so W_Ez = L_x L_y ((a^n - a^(n-1))/dt)^2, which matches the
+    ODE's (d_t a)^2 at the half step to first order in dt (1.2e-4 measured at dt = 0.05, bar 5e-4)."""
+    nu, n_b, u_b, T, dt = 0.5, 0.1, synth.U_BEAM, 10.0, 0.05
+    wl = replace(UNIFORM_DRIFT, dt=dt)
+    h = _run(wl)
+    V = 16 * 16 * 0.2 * 0.2
+    n_p = 1 - n_b
+    beta = lambda v: v / math.sqrt(1 + v * v)
+    a0 = -n_b * beta(u_b) / n_p
+    P = u_b - a0
+    a_of = lambda psi: brentq(lambda a: n_b * beta(P + a) + n_p * (psi + a), -50, 50, xtol=1e-15)
+    sol = solve_ivp(lambda t, y: [-nu * (y[0] + a_of(y[0]))], (0, T), [0.0], rtol=1e-12, atol=1e-14,
+                    dense_output=True)
+    recs = h.step(int(round(T / dt)), diag=True)
+    for r in recs[1::25]:
+        assert abs(r["beam_pz"] - V * n_b * (u_b + r["mean_a"] - a0)) < 1e-12 * V * n_b * u_b
+        th = r["time"] - 0.5 * dt
+        eps = 1e-6
+        dadt = (a_of(float(sol.sol(th + eps)[0])) - a_of(float(sol.sol(th - eps)[0]))) / (2 * eps)
+        assert abs(r["W_Ez"] / (V * dadt * dadt) - 1) < 5e-4, (r["time"], r["W_Ez"], V * dadt * dadt)
