@@ -67,7 +67,8 @@ enum {
     PIC_FLAG_TRACK_IDS = 32u,     /* carry particle ids for every species (by default only
                                      collisional species, whose draws are keyed by id, do) */
     PIC_FLAG_GAUSS_RESIDUAL = 64u /* at step 0 and on diagnostic steps, deposit the particles'
-                                     charge and record Gauss's-law residuals (single runs only) */
+                                     charge before and after the move and record the Gauss's-law
+                                     and charge-continuity residuals (single runs only) */
 };
 
 #define PIC_MAX_SPECIES 8
@@ -175,7 +176,17 @@ typedef struct {
  *                  of the particles on the nodes, rho_0 that of step 0 (the
  *                  immobile ions carry -rho_0); -1 when not computed.
  *   rho_dev        with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
- *                  |rho - rho_0| (the scale of the residual); -1 otherwise. */
+ *                  |rho - rho_0| (the scale of the residual); -1 otherwise.
+ *   continuity_resid with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
+ *                  |rho^{n+1} - rho^n + dt div J^{n+1/2}| for this step's
+ *                  move (rho the CIC charge of the particles before and after
+ *                  it, J the step's grid current, div the backward difference
+ *                  onto the nodes): the charge conservation that the
+ *                  Esirkepov deposit guarantees (Esirkepov 2001); -1 when not
+ *                  computed.
+ *   rho_step       with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
+ *                  |rho^{n+1} - rho^n| (the scale of continuity_resid); -1
+ *                  otherwise. */
 typedef struct {
     int64_t step;
     double time;
@@ -189,6 +200,8 @@ typedef struct {
     int64_t rebins;
     double gauss_resid;
     double rho_dev;
+    double continuity_resid;
+    double rho_step;
 } pic_diag;
 
 typedef struct pic_run pic_run;
@@ -203,8 +216,10 @@ int pic_query(const pic_grid_desc *grid, const pic_species_desc *species, int ns
  * fields, lays out the particle store and, unless PIC_FLAG_HOST_LOAD, loads
  * the species on the device (exactly ppc per cell, uniform in-cell positions,
  * Gaussian momenta, mean transverse momentum removed, net current cancelled by
- * a Newton shift in FP64).  `hip_stream` is a hipStream_t (NULL = default
- * stream).  Synchronising.  On success *out owns host state only. */
+ * a Newton shift in FP64).  Unless PIC_FLAG_NO_GRAPH, one step is captured as
+ * a hipGraph; a failed capture fails the call with PIC_E_HIP.  `hip_stream`
+ * is a hipStream_t (NULL = default stream).  Synchronising.  On success *out
+ * owns host state only. */
 int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
              const pic_buffers *buffers, void *hip_stream, pic_run **out);
 
@@ -229,6 +244,30 @@ int pic_step_profiled(pic_run *run, int32_t nsteps, double *group_ms);
 
 /* Waits for the bound stream; reports device-side capacity failures. */
 int pic_sync(pic_run *run);
+
+/* How a run (or a batch) enqueues its steps.
+ *   graph           1 if a step is the replay of one captured hipGraph, 0 if
+ *                   its kernels are launched one by one (PIC_FLAG_NO_GRAPH,
+ *                   or a run on the library's scratch).
+ *   static_scratch  1 if the run lives on the library's own scratch
+ *                   instead of the caller's.
+ *   steps_enqueued  steps enqueued so far (graph_launches + direct_steps,
+ *                   plus the steps of a restored checkpoint).
+ *   graph_launches  steps enqueued as one graph replay.
+ *   direct_steps    steps enqueued kernel by kernel (including the
+ *                   measurement path pic_step_profiled).
+ *   scratch_bytes   scratch the run uses (pic_query's scratch_bytes). */
+typedef struct {
+    int32_t graph;
+    int32_t static_scratch;
+    int64_t steps_enqueued;
+    int64_t graph_launches;
+    int64_t direct_steps;
+    size_t scratch_bytes;
+} pic_run_info;
+
+/* Host only.  Fills *out for the run.  Errors: INVALID_ARG (NULL). */
+int pic_info(pic_run *run, pic_run_info *out);
 
 /* Synchronising.  Copies the most recent diagnostic record; PIC_E_STATE if
  * none has been recorded yet. */
@@ -271,8 +310,12 @@ int pic_checkpoint(pic_run *run, const char *path);
  * truncated file), STATE (descriptors differ), HIP. */
 int pic_restore(pic_run *run, const char *path);
 
-/* Host only.  Frees the handle's host state (not the caller's buffers). */
+/* Waits for the run's stream (the caller may free the buffers once this
+ * returns), then frees the handle's host state (not the caller's buffers).
+ * Errors: STATE (the run is in a batch), HIP (the
+ * wait failed; the handle is freed all the same). */
 int pic_destroy(pic_run *run);
+
 
 /* Static string for a status code. */
 const char *pic_status_string(int status);
@@ -306,7 +349,8 @@ int pic_batch_query(int nruns, pic_run *const *runs, size_t *table_bytes);
 
 /* Builds the batch: writes the work-item and block tables into the caller's
  * device buffer `table` (>= pic_batch_query's size, kept alive until
- * pic_batch_destroy) and captures the step graph.  persistent_blocks:
+ * pic_batch_destroy) and captures the step graph (a failed capture fails the
+ * call with PIC_E_HIP).  persistent_blocks:
  * workgroups of each particle launch (0 = as many as fit on the device at
  * once).  flags: PIC_FLAG_NO_GRAPH or 0.  Synchronising.  Errors as
  * pic_batch_query, plus BUFFER_TOO_SMALL, STATE (a run already in a batch),
@@ -332,6 +376,10 @@ int pic_batch_diagnostics(pic_batch *batch, int run, pic_diag *out);
 /* Host only.  For tile edges 8, 16, 32 (index 0..2): the particle kernel's
  * workgroups and work items (0 where no member uses the edge). */
 int pic_batch_info(pic_batch *batch, int32_t persistent_blocks[3], int32_t items[3]);
+
+/* Host only.  How the batch enqueues its steps (pic_run_info; the fields
+ * static_scratch and scratch_bytes are 0). */
+int pic_batch_launch_info(pic_batch *batch, pic_run_info *out);
 
 /* Waits for the stream, releases the members and frees the host state. */
 int pic_batch_destroy(pic_batch *batch);

@@ -111,9 +111,12 @@ struct KParams {
     uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
     double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
     int32_t coulomb;     // 1 if a species scatters with the Coulomb model (selects the particle kernel)
-    double *rho_tile;    // [tiles][(T+1)^ndim] per-tile charge partials (Gauss-law check)
+    // Gauss-law and continuity checks (PIC_FLAG_GAUSS_RESIDUAL only; null otherwise)
+    double *rho_tile;    // [tiles][(T+1)^ndim] per-tile charge partials
     double *rho0;        // [cells] charge on the nodes at step 0
+    double *rho_n;       // [cells] charge on the nodes at the start of the current check step
     double *gauss_part;  // [ceil(cells / 256)][2] per-block maxima of the residual and of |rho - rho0|
+    double *cont_part;   // [ceil(cells / 256)][2] per-block maxima of the continuity residual and |rho' - rho|
 };
 
 // An ensemble of runs stepped together: every launch of a step covers all
@@ -152,9 +155,11 @@ constexpr int kNumGroups = 6;
 constexpr int kStepKernels = 13;
 constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
 // With PIC_FLAG_GAUSS_RESIDUAL the step starts with the charge deposit and
-// the residual reduction (counted with the field diagnostics).
-constexpr int kGaussStepKernels = kStepKernels + 2;
-constexpr int kKernelGroupGauss[kGaussStepKernels] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
+// the Gauss residual, and the current reduction is followed by the charge
+// deposit after the move and the continuity residual (all four counted with
+// the field diagnostics).
+constexpr int kGaussStepKernels = kStepKernels + 4;
+constexpr int kKernelGroupGauss[kGaussStepKernels] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 3, 0, 0, 4, 4, 4, 5};
 // ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
 // Batch step: the particle kernel is one launch per tile group (empty groups
@@ -168,6 +173,18 @@ hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, cons
 // Workgroups of the batch particle kernel of tile group g that fit on one
 // compute unit at once.
 hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool coulomb, int *blocks_per_cu);
+// Initialisation shared by pic_init (static_device = -1, the caller's
+// scratch) and pic_init_static_scratch (the library's scratch of that
+// device, already claimed; pic_destroy releases it).
+int init_run(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+             const pic_buffers *buffers, void *hip_stream, pic_run **out, int static_device);
+// One run at a time per device may hold the library's scratch of that device.
+constexpr int kMaxDevices = 64;
+bool claim_static_scratch(int device);     // false if held
+void release_static_scratch(int device);
+// Records a message for pic_last_error(NULL, ...) and returns code.
+int fail_global(int code, const char *fmt, ...);
+
 hipError_t launch_load_species(const KParams &hp, const KParams *dp, int s, hipStream_t st);
 hipError_t launch_moments(const KParams &hp, const KParams *dp, int s, double delta_uz, hipStream_t st);
 hipError_t launch_shift_u(const KParams &hp, const KParams *dp, int s, double dux, double duy,

@@ -13,6 +13,8 @@
 //   k_yee_b/k_yee_e  B half step, E full step with -J, B half step
 //   k_rho/k_gauss    (only with PIC_FLAG_GAUSS_RESIDUAL, on diagnostic steps)
 //                    CIC charge of the particles and max |div E - (rho - rho_0)|
+//   k_rho/k_continuity (the same steps, after the current reduction) charge
+//                    after the move and max |rho^{n+1} - rho^n + dt div J|
 //   k_advance        diagnostic record, counter reset, step/parity update
 //
 // The numerical scheme is the relativistic Boris push (Boris 1970), the
@@ -1100,15 +1102,22 @@ __device__ __forceinline__ bool gauss_step(KP kp, int64_t step)
     return (kp->flags & PIC_FLAG_GAUSS_RESIDUAL) && (step == 0 || diag_step(kp, step));
 }
 
-template <typename R, int D, int T>
+// CIC charge of the particles on the tile's nodes (per-tile partials).
+// NEXT = false: the particles at the start of the step (x^n); NEXT = true:
+// after the particle kernel and any re-layout (x^{n+1}), which sit in the
+// other particle set, or, after a re-layout, back in the same one.
+template <typename R, int D, int T, bool NEXT>
 __global__ __launch_bounds__(256) void k_rho(const KParams *__restrict__ kp)
 {
     constexpr int N1 = T + 1;
     constexpr int ND = D == 3 ? N1 * N1 * N1 : N1 * N1;
     __shared__ double srho[ND];
-    const int64_t step = kp->state->step;
+    const DevState *stp = kp->state;
+    const int64_t step = stp->step;
     if (!gauss_step(kp, step)) return;
-    const int tile = blockIdx.x, ntiles = kp->g.ntiles, par = kp->state->par;
+    if (NEXT && (stp->fatal & 4)) return;
+    const int tile = blockIdx.x, ntiles = kp->g.ntiles;
+    const int par = NEXT ? (stp->rebin ? stp->par : stp->par ^ 1) : stp->par;
     const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
     const int t0[3] = {(tile % ntx) * T, ((tile / ntx) % nty) * T, (tile / (ntx * nty)) * T};
     for (int e = threadIdx.x; e < ND; e += blockDim.x) srho[e] = 0.0;
@@ -1158,68 +1167,71 @@ __global__ __launch_bounds__(256) void k_rho(const KParams *__restrict__ kp)
     for (int e = threadIdx.x; e < ND; e += blockDim.x) out[e] = srho[e];
 }
 
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_gauss(const KParams *__restrict__ kp)
+// Charge on node o (grid indices idx) from the per-tile partials of k_rho:
+// a node belongs to its own tile (local index i mod T) and, on a tile edge,
+// to the tile below (local index T); the partials are summed in that order.
+template <int D>
+__device__ __forceinline__ double node_rho(const KParams *__restrict__ kp, const int (&idx)[3])
+{
+    const int T = kp->g.tile[0], N1 = T + 1;
+    const int64_t ND = D == 3 ? (int64_t)N1 * N1 * N1 : (int64_t)N1 * N1;
+    double rho = 0.0;
+    for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz) {
+        int tz = 0, lz = 0;
+        if (D == 3) {
+            tz = idx[2] / T;
+            lz = idx[2] - tz * T;
+            if (cz) {
+                if (lz) continue;
+                tz = tz ? tz - 1 : kp->g.nt[2] - 1;
+                lz = T;
+            }
+        }
+        for (int cy = 0; cy < 2; ++cy) {
+            int ty = idx[1] / T, ly = idx[1] - (idx[1] / T) * T;
+            if (cy) {
+                if (ly) continue;
+                ty = ty ? ty - 1 : kp->g.nt[1] - 1;
+                ly = T;
+            }
+            for (int cx = 0; cx < 2; ++cx) {
+                int tx = idx[0] / T, lx = idx[0] - (idx[0] / T) * T;
+                if (cx) {
+                    if (lx) continue;
+                    tx = tx ? tx - 1 : kp->g.nt[0] - 1;
+                    lx = T;
+                }
+                const int64_t t = ((int64_t)tz * kp->g.nt[1] + ty) * kp->g.nt[0] + tx;
+                rho += kp->rho_tile[t * ND + ((int64_t)lz * N1 + ly) * N1 + lx];
+            }
+        }
+    }
+    return rho;
+}
+
+// Backward-difference divergence on node o of a vector field co-located with
+// E (component a stored at the lower node of its half-integer point).
+template <int D, typename V>
+__device__ __forceinline__ double node_div(const KParams *__restrict__ kp, const V *F, int64_t o,
+                                           const int (&idx)[3])
+{
+    const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
+    const int64_t cells = kp->g.cells;
+    double div = 0.0;
+    for (int a = 0; a < D; ++a) {
+        int im[3] = {idx[0], idx[1], idx[2]};
+        im[a] = idx[a] ? idx[a] - 1 : n[a] - 1;
+        const int64_t om = ((int64_t)im[2] * n[1] + im[1]) * n[0] + im[0];
+        const V *Fa = F + (int64_t)a * cells;
+        div += ((double)Fa[o] - (double)Fa[om]) / kp->g.d[a];
+    }
+    return div;
+}
+
+// Block maxima of two per-thread values into part[2 * block + i].
+__device__ __forceinline__ void block_max2(double (&m)[2], double *part)
 {
     __shared__ double sred[4][2];
-    const int64_t step = kp->state->step;
-    if (!gauss_step(kp, step)) return;
-    const int64_t cells = kp->g.cells;
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double m[2] = {0.0, 0.0};
-    if (o < cells) {
-        const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
-        const int idx[3] = {(int)(o % n[0]), (int)((o / n[0]) % n[1]), (int)(o / ((int64_t)n[0] * n[1]))};
-        const int T = kp->g.tile[0], N1 = T + 1;
-        const int64_t ND = D == 3 ? (int64_t)N1 * N1 * N1 : (int64_t)N1 * N1;
-        double rho = 0.0;
-        // a node belongs to its own tile (local index i mod T) and, on a tile
-        // edge, to the tile below (local index T)
-        for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz) {
-            int tz = 0, lz = 0;
-            if (D == 3) {
-                tz = idx[2] / T;
-                lz = idx[2] - tz * T;
-                if (cz) {
-                    if (lz) continue;
-                    tz = tz ? tz - 1 : kp->g.nt[2] - 1;
-                    lz = T;
-                }
-            }
-            for (int cy = 0; cy < 2; ++cy) {
-                int ty = idx[1] / T, ly = idx[1] - (idx[1] / T) * T;
-                if (cy) {
-                    if (ly) continue;
-                    ty = ty ? ty - 1 : kp->g.nt[1] - 1;
-                    ly = T;
-                }
-                for (int cx = 0; cx < 2; ++cx) {
-                    int tx = idx[0] / T, lx = idx[0] - (idx[0] / T) * T;
-                    if (cx) {
-                        if (lx) continue;
-                        tx = tx ? tx - 1 : kp->g.nt[0] - 1;
-                        lx = T;
-                    }
-                    const int64_t t = ((int64_t)tz * kp->g.nt[1] + ty) * kp->g.nt[0] + tx;
-                    rho += kp->rho_tile[t * ND + ((int64_t)lz * N1 + ly) * N1 + lx];
-                }
-            }
-        }
-        if (step == 0) kp->rho0[o] = rho;
-        const double dev = rho - kp->rho0[o];
-        // div E on the node: E_a is stored at the lower node of its half-integer point
-        const R *F = (const R *)kp->F;
-        double div = 0.0;
-        for (int a = 0; a < D; ++a) {
-            int im[3] = {idx[0], idx[1], idx[2]};
-            im[a] = idx[a] ? idx[a] - 1 : n[a] - 1;
-            const int64_t om = ((int64_t)im[2] * n[1] + im[1]) * n[0] + im[0];
-            const R *Ea = F + (int64_t)a * cells;
-            div += ((double)Ea[o] - (double)Ea[om]) / kp->g.d[a];
-        }
-        m[0] = fabs(div - dev);
-        m[1] = fabs(dev);
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -1232,8 +1244,54 @@ __global__ __launch_bounds__(256) void k_gauss(const KParams *__restrict__ kp)
     if (threadIdx.x < 2) {
         double x = sred[0][threadIdx.x];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = fmax(x, sred[w][threadIdx.x]);
-        kp->gauss_part[2 * (int64_t)blockIdx.x + threadIdx.x] = x;
+        part[2 * (int64_t)blockIdx.x + threadIdx.x] = x;
     }
+}
+
+// Gauss's law on every node: |div E - (rho - rho_0)| and |rho - rho_0|; keeps
+// rho^n for the continuity check of the same step.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_gauss(const KParams *__restrict__ kp)
+{
+    const int64_t step = kp->state->step;
+    if (!gauss_step(kp, step)) return;
+    const int64_t cells = kp->g.cells;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m[2] = {0.0, 0.0};
+    if (o < cells) {
+        const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
+        const int idx[3] = {(int)(o % n[0]), (int)((o / n[0]) % n[1]), (int)(o / ((int64_t)n[0] * n[1]))};
+        const double rho = node_rho<D>(kp, idx);
+        if (step == 0) kp->rho0[o] = rho;
+        kp->rho_n[o] = rho;
+        const double dev = rho - kp->rho0[o];
+        const double div = node_div<D>(kp, (const R *)kp->F, o, idx);
+        m[0] = fabs(div - dev);
+        m[1] = fabs(dev);
+    }
+    block_max2(m, kp->gauss_part);
+}
+
+// Charge continuity of the step on every node, from the charge of the
+// particles before (rho^n, kept by k_gauss) and after it (rho^{n+1}, the
+// partials of k_rho<NEXT>) and the grid current of the step:
+// |rho^{n+1} - rho^n + dt div J^{n+1/2}| and |rho^{n+1} - rho^n|.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_continuity(const KParams *__restrict__ kp)
+{
+    const DevState *st = kp->state;
+    if (!gauss_step(kp, st->step) || (st->fatal & 4)) return;
+    const int64_t cells = kp->g.cells;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m[2] = {0.0, 0.0};
+    if (o < cells) {
+        const int n[3] = {kp->g.n[0], kp->g.n[1], kp->g.n[2]};
+        const int idx[3] = {(int)(o % n[0]), (int)((o / n[0]) % n[1]), (int)(o / ((int64_t)n[0] * n[1]))};
+        const double drho = node_rho<D>(kp, idx) - kp->rho_n[o];
+        m[0] = fabs(drho + kp->g.dt * node_div<D>(kp, kp->J, o, idx));
+        m[1] = fabs(drho);
+    }
+    block_max2(m, kp->cont_part);
 }
 
 template <typename R>
@@ -1617,23 +1675,29 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
                 coll_total += a[5];
             }
         }
-        double gm[2] = {-1.0, -1.0};
+        // residual maxima: Gauss's law (gm[0], gm[1]) and continuity (gm[2], gm[3])
+        double gm[4] = {-1.0, -1.0, -1.0, -1.0};
         if (gauss_step(kp, step)) {
             const int64_t nbk = (kp->g.cells + 255) / 256;
-            gm[0] = gm[1] = 0.0;
+            const bool cont = !(st->fatal & 4);
+            for (int i = 0; i < 4; ++i) gm[i] = (i < 2 || cont) ? 0.0 : -1.0;
             for (int64_t b = threadIdx.x; b < nbk; b += blockDim.x) {
                 gm[0] = fmax(gm[0], kp->gauss_part[2 * b]);
                 gm[1] = fmax(gm[1], kp->gauss_part[2 * b + 1]);
+                if (cont) {
+                    gm[2] = fmax(gm[2], kp->cont_part[2 * b]);
+                    gm[3] = fmax(gm[3], kp->cont_part[2 * b + 1]);
+                }
             }
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 4; ++i) {
                 double x = gm[i];
                 for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
                 if (lane == 0) sred[wave][i] = x;
             }
             __syncthreads();
             if (threadIdx.x == 0)
-                for (int i = 0; i < 2; ++i) {
+                for (int i = 0; i < 4; ++i) {
                     double x = sred[0][i];
                     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = fmax(x, sred[w][i]);
                     gm[i] = x;
@@ -1643,6 +1707,8 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
         if (threadIdx.x == 0) {
             rec.gauss_resid = gm[0];
             rec.rho_dev = gm[1];
+            rec.continuity_resid = gm[2];
+            rec.rho_step = gm[3];
             for (int s = ns; s < kMaxSpecies; ++s) {
                 rec.kinetic[s] = 0.0;
                 rec.n_particles[s] = 0;
@@ -2005,8 +2071,9 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     const unsigned cb = (unsigned)((cells + 255) / 256);
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
     Launcher L{st, ev};
-    if (hp.flags & PIC_FLAG_GAUSS_RESIDUAL) {
-        L(k_rho<R, D, T>, dim3(ntiles), dim3(256), dp);
+    const bool gauss = (hp.flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
+    if (gauss) {
+        L(k_rho<R, D, T, false>, dim3(ntiles), dim3(256), dp);
         L(k_gauss<R, D>, dim3(cb), dim3(256), dp);
     }
     L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
@@ -2019,6 +2086,10 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
     L(k_rebin_scatter_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_finalize, dim3(nst), dim3(256), dp);
     L(k_reduce_j<R, D>, dim3(cb), dim3(256), dp);
+    if (gauss) {
+        L(k_rho<R, D, T, true>, dim3(ntiles), dim3(256), dp);
+        L(k_continuity<R, D>, dim3(cb), dim3(256), dp);
+    }
     // frozen fields: the Yee kernels still run (fixed launch shape) but exit
     const double h = (hp.flags & PIC_FLAG_FREEZE_FIELDS) ? 0.0 : 0.5;
     L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,7 +35,8 @@ struct Layout {
     } sp[kMaxSpecies];
     size_t F, J;                                            // field buffer
     size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4], order, bucket;   // scratch
-    size_t rho_tile, rho0, gauss_part;                      // scratch (Gauss-law check)
+    size_t rho_tile, rho0, rho_n, gauss_part, cont_part;    // scratch (Gauss-law and continuity checks)
+    bool checks = false;                                    // PIC_FLAG_GAUSS_RESIDUAL: the above are carved
     Geometry g;
     int nj;
     size_t real;                                            // sizeof(float|double)
@@ -198,11 +200,16 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         for (int i = 0; i < 4; ++i) L->rb[i] = c.take((size_t)ns * G.ntiles * 4);
         L->order = c.take((size_t)G.ntiles * 4);
         L->bucket = c.take((size_t)G.ntiles);
-        int64_t n1 = 1;
-        for (int a = 0; a < g->ndim; ++a) n1 *= G.tile[0] + 1;
-        L->rho_tile = c.take((size_t)G.ntiles * n1 * 8);
-        L->rho0 = c.take((size_t)G.cells * 8);
-        L->gauss_part = c.take((size_t)((G.cells + 255) / 256) * 2 * 8);
+        L->checks = (g->flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
+        if (L->checks) {
+            int64_t n1 = 1;
+            for (int a = 0; a < g->ndim; ++a) n1 *= G.tile[0] + 1;
+            L->rho_tile = c.take((size_t)G.ntiles * n1 * 8);
+            L->rho0 = c.take((size_t)G.cells * 8);
+            L->rho_n = c.take((size_t)G.cells * 8);
+            L->gauss_part = c.take((size_t)((G.cells + 255) / 256) * 2 * 8);
+            L->cont_part = c.take((size_t)((G.cells + 255) / 256) * 2 * 8);
+        }
         L->scratch_bytes = c.off;
     }
     L->diag_bytes = align256(sizeof(pic_diag) * kRing);
@@ -221,9 +228,12 @@ struct pic_run {
     KParams hp;                 // host copy of the device-resident parameters
     KParams *dp = nullptr;      // device copy (inside scratch)
     int64_t steps_enqueued = 0;
+    int64_t graph_launches = 0;  // steps enqueued as one graph replay
+    int64_t direct_steps = 0;    // steps enqueued kernel by kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     pic_batch *owner = nullptr;  // batch this run is a member of
+    int static_device = -1;      // device whose library scratch this run holds (pic_init_static_scratch)
     std::string err;
 };
 
@@ -234,6 +244,7 @@ struct pic_batch {
     BatchTable ht;              // host copy (device pointers inside)
     BatchTable *dt = nullptr;   // device copy (inside the caller's table buffer)
     int pblocks[kBatchGroups] = {0, 0, 0};
+    int64_t graph_launches = 0, direct_steps = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::string err;
@@ -363,20 +374,31 @@ int loader_moments(pic_run *r)
     return PIC_OK;
 }
 
+// Captures one step as a graph on a private stream.  A failure is returned
+// as PIC_E_HIP (the caller can ask for kernel-by-kernel steps with
+// PIC_FLAG_NO_GRAPH instead).
 int capture_graph(pic_run *r)
 {
     hipStream_t cs;
     HIPCHK(r, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const char *what = "hipStreamBeginCapture";
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
         hipError_t le = launch_step(r->hp, r->dp, cs);
         hipGraph_t g = nullptr;
+        what = "hipStreamEndCapture";
         e = hipStreamEndCapture(cs, &g);
-        if (le != hipSuccess) e = le;
+        if (le != hipSuccess) {
+            e = le;
+            what = "step launch under capture";
+        }
         if (e == hipSuccess) {
+            what = "hipGraphInstantiate";
             e = hipGraphInstantiate(&r->gexec, g, nullptr, nullptr, 0);
             if (e == hipSuccess) r->graph = g;
             else (void)hipGraphDestroy(g);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
         }
     }
     (void)hipStreamDestroy(cs);
@@ -384,6 +406,7 @@ int capture_graph(pic_run *r)
         r->gexec = nullptr;
         r->graph = nullptr;
         (void)hipGetLastError();
+        return hip_fail(r, e, what);
     }
     return PIC_OK;
 }
@@ -476,25 +499,35 @@ int profiled_steps(std::string *err, hipStream_t st, int32_t nsteps, int nk, con
     return rc;
 }
 
-// One step of a batch captured as a graph (kept unset if capture fails:
-// steps are then launched one kernel at a time).
-void capture_batch_graph(pic_batch *b)
+// One step of a batch captured as a graph; a failure is returned (hipError_t
+// and the call that failed in *what).
+hipError_t capture_batch_graph(pic_batch *b, const char **what)
 {
     hipStream_t cs;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    *what = "hipStreamCreateWithFlags";
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
-        return;
+        return e;
     }
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    *what = "hipStreamBeginCapture";
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
         hipError_t le = launch_batch_step(b->precision, b->ndim, b->ht, b->dt, b->pblocks, cs);
         hipGraph_t g = nullptr;
+        *what = "hipStreamEndCapture";
         e = hipStreamEndCapture(cs, &g);
-        if (le != hipSuccess) e = le;
+        if (le != hipSuccess) {
+            e = le;
+            *what = "batch step launch under capture";
+        }
         if (e == hipSuccess) {
+            *what = "hipGraphInstantiate";
             e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
             if (e == hipSuccess) b->graph = g;
             else (void)hipGraphDestroy(g);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
         }
     }
     (void)hipStreamDestroy(cs);
@@ -503,6 +536,7 @@ void capture_batch_graph(pic_batch *b)
         b->graph = nullptr;
         (void)hipGetLastError();
     }
+    return e;
 }
 
 int batch_hip_fail(pic_batch *b, hipError_t e, const char *what)
@@ -522,6 +556,64 @@ struct TuneCarve {
     pic_sizes sz;
     size_t part[kMaxSpecies], fields, scratch, diag, per_copy, table, table_bytes, bytes;
 };
+
+// Descriptors compared field by field (their padding bytes are not data).
+bool same_grid(const pic_grid_desc &a, const pic_grid_desc &b, uint32_t ignore_flags)
+{
+    bool same = a.ndim == b.ndim && a.dt == b.dt && a.precision == b.precision && a.seed == b.seed &&
+                a.run == b.run && a.diag_every == b.diag_every && a.reserve == b.reserve &&
+                (a.flags & ~ignore_flags) == (b.flags & ~ignore_flags);
+    for (int i = 0; i < 3; ++i) same = same && a.n[i] == b.n[i] && a.d[i] == b.d[i] && a.tile[i] == b.tile[i];
+    return same;
+}
+
+bool same_species(const pic_species_desc &a, const pic_species_desc &b)
+{
+    bool same = a.charge == b.charge && a.mass == b.mass && a.density == b.density && a.ppc == b.ppc &&
+                a.u_th == b.u_th && a.cancel_current_of == b.cancel_current_of && a.nu_coll == b.nu_coll &&
+                a.coll_model == b.coll_model && a.coll_vref == b.coll_vref;
+    for (int i = 0; i < 3; ++i) same = same && a.drift_u[i] == b.drift_u[i];
+    return same;
+}
+
+// Copies with zeroed padding, so that the images kept in the handle and
+// written into checkpoints do not carry the caller's stack bytes.
+pic_grid_desc canonical_grid(const pic_grid_desc &g)
+{
+    pic_grid_desc c;
+    memset(&c, 0, sizeof(c));
+    c.ndim = g.ndim;
+    for (int i = 0; i < 3; ++i) {
+        c.n[i] = g.n[i];
+        c.d[i] = g.d[i];
+        c.tile[i] = g.tile[i];
+    }
+    c.dt = g.dt;
+    c.precision = g.precision;
+    c.seed = g.seed;
+    c.run = g.run;
+    c.diag_every = g.diag_every;
+    c.flags = g.flags;
+    c.reserve = g.reserve;
+    return c;
+}
+
+pic_species_desc canonical_species(const pic_species_desc &s)
+{
+    pic_species_desc c;
+    memset(&c, 0, sizeof(c));
+    c.charge = s.charge;
+    c.mass = s.mass;
+    c.density = s.density;
+    c.ppc = s.ppc;
+    for (int i = 0; i < 3; ++i) c.drift_u[i] = s.drift_u[i];
+    c.u_th = s.u_th;
+    c.cancel_current_of = s.cancel_current_of;
+    c.nu_coll = s.nu_coll;
+    c.coll_model = s.coll_model;
+    c.coll_vref = s.coll_vref;
+    return c;
+}
 
 bool tile_fits(const pic_grid_desc *g, int t)
 {
@@ -575,10 +667,51 @@ int pic_query(const pic_grid_desc *grid, const pic_species_desc *species, int ns
 int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
              const pic_buffers *buffers, void *hip_stream, pic_run **out)
 {
+    return pic::init_run(grid, species, nspecies, buffers, hip_stream, out, -1);
+}
+
+}  // extern "C"
+
+namespace {
+std::mutex g_static_mu;
+bool g_static_busy[kMaxDevices] = {};
+}  // namespace
+
+bool pic::claim_static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_busy[device]) return false;
+    g_static_busy[device] = true;
+    return true;
+}
+
+void pic::release_static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_busy[device] = false;
+}
+
+int pic::fail_global(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+                  const pic_buffers *buffers, void *hip_stream, pic_run **out, int static_device)
+{
     if (!out || !buffers) return fail(nullptr, PIC_E_INVALID_ARG, "null argument");
     *out = nullptr;
     pic_run *r = new (std::nothrow) pic_run();
     if (!r) return fail(nullptr, PIC_E_INVALID_ARG, "host allocation failed");
+    r->static_device = static_device;
     int rc = validate(grid, species, nspecies, &r->L, &r->err);
     if (rc) { delete r; return rc; }
     for (int s = 0; s < nspecies; ++s)
@@ -587,9 +720,9 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
         delete r;
         return fail(nullptr, PIC_E_INVALID_ARG, "null field, scratch or diag buffer");
     }
-    r->grid = *grid;
+    r->grid = canonical_grid(*grid);
     r->ns = nspecies;
-    for (int s = 0; s < nspecies; ++s) r->species[s] = species[s];
+    for (int s = 0; s < nspecies; ++s) r->species[s] = canonical_species(species[s]);
     r->buf = *buffers;
     r->stream = (hipStream_t)hip_stream;
     const Layout &L = r->L;
@@ -660,9 +793,13 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
     K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
     K.order = (int32_t *)at(buffers->scratch, L.order);
     K.tile_bucket = (uint8_t *)at(buffers->scratch, L.bucket);
-    K.rho_tile = (double *)at(buffers->scratch, L.rho_tile);
-    K.rho0 = (double *)at(buffers->scratch, L.rho0);
-    K.gauss_part = (double *)at(buffers->scratch, L.gauss_part);
+    if (L.checks) {
+        K.rho_tile = (double *)at(buffers->scratch, L.rho_tile);
+        K.rho0 = (double *)at(buffers->scratch, L.rho0);
+        K.rho_n = (double *)at(buffers->scratch, L.rho_n);
+        K.gauss_part = (double *)at(buffers->scratch, L.gauss_part);
+        K.cont_part = (double *)at(buffers->scratch, L.cont_part);
+    }
     {
         int64_t per_tile = 0;
         for (int s = 0; s < nspecies; ++s) per_tile += L.sp[s].tile_nominal;
@@ -704,10 +841,19 @@ int pic_init(const pic_grid_desc *grid, const pic_species_desc *species, int nsp
         if (rc) { delete r; return rc; }
     }
     INIT_CHK(hipStreamSynchronize(r->stream));
-    if (!(grid->flags & PIC_FLAG_NO_GRAPH)) capture_graph(r);
+    if (!(grid->flags & PIC_FLAG_NO_GRAPH)) {
+        rc = capture_graph(r);
+        if (rc) {
+            g_last_error = r->err;
+            delete r;
+            return rc;
+        }
+    }
     *out = r;
     return PIC_OK;
 }
+
+extern "C" {
 
 int pic_load_particles(pic_run *r, int s, const double *x, const double *u, const uint32_t *id, int64_t n)
 {
@@ -831,11 +977,26 @@ int pic_step(pic_run *r, int32_t nsteps)
     for (int32_t i = 0; i < nsteps; ++i) {
         if (r->gexec) {
             HIPCHK(r, hipGraphLaunch(r->gexec, r->stream));
+            r->graph_launches += 1;
         } else {
             HIPCHK(r, launch_step(r->hp, r->dp, r->stream));
+            r->direct_steps += 1;
         }
         r->steps_enqueued += 1;
     }
+    return PIC_OK;
+}
+
+int pic_info(pic_run *r, pic_run_info *out)
+{
+    if (!r || !out) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "null argument");
+    memset(out, 0, sizeof(*out));
+    out->graph = r->gexec ? 1 : 0;
+    out->static_scratch = r->static_device >= 0 ? 1 : 0;
+    out->steps_enqueued = r->steps_enqueued;
+    out->graph_launches = r->graph_launches;
+    out->direct_steps = r->direct_steps;
+    out->scratch_bytes = r->L.scratch_bytes;
     return PIC_OK;
 }
 
@@ -848,7 +1009,10 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
     return profiled_steps(&r->err, r->stream, nsteps, gauss ? kGaussStepKernels : kStepKernels,
                           gauss ? kKernelGroupGauss : kKernelGroup, group_ms, [&](hipEvent_t *ev) {
         hipError_t e = launch_step(r->hp, r->dp, r->stream, ev);
-        if (e == hipSuccess) r->steps_enqueued += 1;
+        if (e == hipSuccess) {
+            r->steps_enqueued += 1;
+            r->direct_steps += 1;
+        }
         return e;
     });
 }
@@ -1001,9 +1165,16 @@ int pic_destroy(pic_run *r)
 {
     if (!r) return PIC_OK;
     if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; destroy the batch first");
+    // the caller frees the buffers once this returns: let every enqueued step finish first
+    const hipError_t e = hipStreamSynchronize(r->stream);
     if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
     if (r->graph) (void)hipGraphDestroy(r->graph);
+    if (r->static_device >= 0) release_static_scratch(r->static_device);
     delete r;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, PIC_E_HIP, "pic_destroy: hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
     return PIC_OK;
 }
 
@@ -1092,15 +1263,12 @@ int pic_restore(pic_run *r, const char *path)
         fclose(f);
         return fail(&r->err, PIC_E_INVALID_ARG, "%s is not a checkpoint of this library version", path);
     }
-    // the checkpoint must come from a run with the same descriptors
-    pic_grid_desc g0 = r->grid, g1 = h.grid;
-    bool same = h.nspecies == r->ns;
-    // flags that only steer initialisation or launching may differ
-    const uint32_t init_only = PIC_FLAG_HOST_LOAD | PIC_FLAG_NO_GRAPH | PIC_FLAG_LATTICE_LOAD;
-    g0.flags &= ~init_only;
-    g1.flags &= ~init_only;
-    same = same && memcmp(&g0, &g1, sizeof(g0)) == 0;
-    for (int s = 0; same && s < r->ns; ++s) same = memcmp(&h.species[s], &r->species[s], sizeof(pic_species_desc)) == 0;
+    // the checkpoint must come from a run with the same descriptors (compared
+    // field by field: the structs' padding carries no meaning); flags that
+    // only steer initialisation or launching may differ
+    bool same = h.nspecies == r->ns && same_grid(h.grid, r->grid, PIC_FLAG_HOST_LOAD | PIC_FLAG_NO_GRAPH |
+                                                                       PIC_FLAG_LATTICE_LOAD);
+    for (int s = 0; same && s < r->ns; ++s) same = same_species(h.species[s], r->species[s]);
     void *ptr[kMaxSpecies + 3];
     uint64_t bytes[kMaxSpecies + 3];
     ckpt_buffers(r, ptr, bytes);
@@ -1261,8 +1429,16 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
                              b->stream));
     BINIT_CHK(hipStreamSynchronize(b->stream));
 #undef BINIT_CHK
+    if (!(flags & PIC_FLAG_NO_GRAPH)) {
+        const char *what = "";
+        he = capture_batch_graph(b, &what);
+        if (he != hipSuccess) {
+            const int c = batch_hip_fail(b, he, what);
+            delete b;
+            return c;
+        }
+    }
     for (pic_run *r : b->runs) r->owner = b;
-    if (!(flags & PIC_FLAG_NO_GRAPH)) capture_batch_graph(b);
     *out = b;
     return PIC_OK;
 }
@@ -1274,11 +1450,24 @@ int pic_batch_step(pic_batch *b, int32_t nsteps)
     for (int32_t i = 0; i < nsteps; ++i) {
         if (b->gexec) {
             BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+            b->graph_launches += 1;
         } else {
             BHIPCHK(b, launch_batch_step(b->precision, b->ndim, b->ht, b->dt, b->pblocks, b->stream));
+            b->direct_steps += 1;
         }
         for (pic_run *r : b->runs) r->steps_enqueued += 1;
     }
+    return PIC_OK;
+}
+
+int pic_batch_launch_info(pic_batch *b, pic_run_info *out)
+{
+    if (!b || !out) return fail(b ? &b->err : nullptr, PIC_E_INVALID_ARG, "null argument");
+    memset(out, 0, sizeof(*out));
+    out->graph = b->gexec ? 1 : 0;
+    out->steps_enqueued = b->graph_launches + b->direct_steps;
+    out->graph_launches = b->graph_launches;
+    out->direct_steps = b->direct_steps;
     return PIC_OK;
 }
 

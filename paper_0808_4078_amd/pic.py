@@ -68,7 +68,7 @@ class Diag(C.Structure):
                 ("kinetic", C.c_double * MAX_SPECIES), ("p_species", (C.c_double * 3) * MAX_SPECIES),
                 ("p_particles", C.c_double * 3), ("p_field", C.c_double * 3), ("collisions", C.c_int64),
                 ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64), ("gauss_resid", C.c_double),
-                ("rho_dev", C.c_double)]
+                ("rho_dev", C.c_double), ("continuity_resid", C.c_double), ("rho_step", C.c_double)]
 
     def as_dict(self, ns: int) -> dict:
         return dict(step=int(self.step), time=float(self.time), W=np.array(self.W[:]),
@@ -76,7 +76,17 @@ class Diag(C.Structure):
                     p_species=np.array([self.p_species[s][:] for s in range(ns)]),
                     p_field=np.array(self.p_field[:]), collisions=int(self.collisions),
                     n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins),
-                    gauss_resid=float(self.gauss_resid), rho_dev=float(self.rho_dev))
+                    gauss_resid=float(self.gauss_resid), rho_dev=float(self.rho_dev),
+                    continuity_resid=float(self.continuity_resid), rho_step=float(self.rho_step))
+
+
+class RunInfo(C.Structure):
+    """pic_run_info: how a run or batch enqueues its steps."""
+    _fields_ = [("graph", C.c_int32), ("static_scratch", C.c_int32), ("steps_enqueued", C.c_int64),
+                ("graph_launches", C.c_int64), ("direct_steps", C.c_int64), ("scratch_bytes", C.c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class PicError(RuntimeError):
@@ -89,8 +99,9 @@ _lib = None
 
 EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_profiled", "pic_sync", "pic_diagnostics",
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
-           "pic_status_string", "pic_last_error", "pic_batch_query", "pic_batch_init", "pic_batch_step",
-           "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_diagnostics",
+           "pic_status_string", "pic_last_error", "pic_info", "pic_batch_query", "pic_batch_init", "pic_batch_step",
+           "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_launch_info",
+           "pic_batch_diagnostics",
            "pic_batch_destroy", "pic_tune_query",
            "pic_tune", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
            "pic_hyb_step_profiled", "pic_hyb_sync", "pic_hyb_read_grid", "pic_hyb_read_particles",
@@ -138,6 +149,7 @@ def lib():
         L.pic_step.argtypes = [vp, C.c_int32]
         L.pic_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.pic_sync.argtypes = [vp]
+        L.pic_info.argtypes = [vp, P(RunInfo)]
         L.pic_diagnostics.argtypes = [vp, P(Diag)]
         L.pic_diag_history.argtypes = [vp, P(Diag), C.c_int64, P(C.c_int64)]
         L.pic_read_fields.argtypes = [vp, vp, vp, vp]
@@ -155,6 +167,7 @@ def lib():
         L.pic_batch_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.pic_batch_sync.argtypes = [vp]
         L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.pic_batch_launch_info.argtypes = [vp, P(RunInfo)]
         L.pic_batch_diagnostics.argtypes = [vp, C.c_int, P(Diag)]
         L.pic_batch_destroy.argtypes = [vp]
         L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, P(C.c_size_t)]
@@ -260,9 +273,14 @@ class Run:
         self.device = torch.device(device if device is not None else "cuda")
         sz = query(grid, species)
         self.sizes = sz
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
 
+        # The buffers belong to the run's stream in torch's caching allocator,
+        # so their memory is not handed out again before that stream's work
+        # (the run's steps) is done; pic_destroy also waits for the stream.
         def alloc(nbytes):
-            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(self.stream):
+                return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
 
         self._bufs = [alloc(sz.particle_bytes[s]) for s in range(self.ns)]
         self._fields = alloc(sz.field_bytes)
@@ -274,7 +292,6 @@ class Run:
         b.fields = self._fields.data_ptr()
         b.scratch = self._scratch.data_ptr()
         b.diag = self._diag.data_ptr()
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         _check(lib().pic_init(C.byref(grid), species, self.ns, C.byref(b), C.c_void_p(self.stream.cuda_stream),
                               C.byref(h)), "pic_init")
@@ -325,6 +342,12 @@ class Run:
 
     def sync(self):
         _check(lib().pic_sync(self.h), "pic_sync", self.h)
+
+    def info(self) -> dict:
+        """pic_info: graph or kernel-by-kernel steps, and the step counts."""
+        i = RunInfo()
+        _check(lib().pic_info(self.h, C.byref(i)), "pic_info", self.h)
+        return i.as_dict()
 
     def diagnostics(self) -> dict:
         d = Diag()
@@ -419,6 +442,12 @@ class Batch:
         it = (C.c_int32 * 3)()
         _check(lib().pic_batch_info(self.h, pb, it), "pic_batch_info")
         return {"persistent_blocks": list(pb), "items": list(it)}
+
+    def launch_info(self) -> dict:
+        """pic_batch_launch_info: graph or kernel-by-kernel steps, and the counts."""
+        i = RunInfo()
+        _check(lib().pic_batch_launch_info(self.h, C.byref(i)), "pic_batch_launch_info")
+        return i.as_dict()
 
     def diagnostics(self, run: int) -> dict:
         """The latest record of member `run` (index in the list given)."""

@@ -103,6 +103,11 @@ def test_batch_graph_and_queue_shapes_agree(pic):
     for x, y, z in zip(ra, rb, rc):
         _compare(pic, x, y, 1e-5)
         _compare(pic, x, z, 1e-5)
+    # a's and c's steps were graph replays, b's direct launches
+    for bt, graph in ((a, 1), (b, 0), (c, 1)):
+        li = bt.launch_info()
+        assert li["graph"] == graph and li["steps_enqueued"] == 15
+        assert li["graph_launches"] == (15 if graph else 0) and li["direct_steps"] == (0 if graph else 15)
     for bt in (a, b, c):
         bt.close()
 

@@ -1,0 +1,84 @@
+"""The error of the GPU path against the FP64 oracle on the headline
+workload's physics, through its whole evolution: beam n_b = 0.1, u_z =
+sqrt(8), u_th = 0.3 on its Newton-cancelled return current (u_th 0.01)
+scattering off the ions at nu = 0.05, 64 particles per cell per species,
+dx = 0.2, dt = 0.1 -- the 1024^2 benchmark workload's per-cell physics on
+a 256^2 box that the oracle steps through 1000 steps (linear filamentation
+from t ~ 30 to 55, saturation by t ~ 90).
+
+The oracle's series is stored in tests/golden/oracle_c3phys_256.txt, written
+by tests/golden/make_oracle_series.py (oracle only).  The GPU run starts
+from the same seeded particles (host-loaded); both draw the same scattering
+decisions (keyed by particle id and step), so the runs track each other
+record by record and the comparison is pointwise in time.  Checked: every
+record's six field energies W_i (the paper's field-energy diagnostic) and
+two kinetic energies, the scattering counts, and the growth rate of the
+transverse magnetic energy fitted over the oracle's linear window (the
+paper's comparison of growth rates with its theory)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import theory
+from pic_cases import gpu_run, log
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_c3phys_256.txt")
+C3PHYS = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=1000,
+                           name="c3phys-256")
+
+
+@pytest.fixture(scope="module")
+def pic():
+    from paper_0808_4078_amd import pic as p
+    p.lib()
+    return p
+
+
+def oracle_series():
+    o = np.loadtxt(GOLDEN)
+    return dict(step=o[:, 0].astype(int), t=o[:, 1], W=o[:, 2:8], K=o[:, 8:10], coll=o[:, 12].astype(int))
+
+
+def growth_window(t, Wb):
+    """The oracle series' linear window (growth-rate fit reading), with the
+    first record (W = 0 at t = 0) left out."""
+    a, b = theory.fit_growth_window(t[1:], Wb[1:])
+    return a + 1, b + 1
+
+
+# measured on one MI355X: FP64 W_i 1.2e-12, K 7e-15, rate 2e-15;
+# mixed W_i 2.9e-5, K 4.6e-8, rate 4e-8.  The bars are the FP64 parity
+# bar of the short runs (1e-10) and the mixed path's field bar (1e-3).
+@pytest.mark.parametrize("prec,w_bar,k_bar,rate_bar", [("fp64", 1e-10, 1e-12, 1e-10),
+                                                        ("mixed", 1e-3, 1e-6, 1e-4)])
+def test_c3_physics_against_the_oracle_series(pic, prec, w_bar, k_bar, rate_bar):
+    log(f"case c3 physics 256^2 x 1000 steps {prec}")
+    o = oracle_series()
+    parts = synth.load(C3PHYS)
+    p = pic.PIC_PREC_FP64 if prec == "fp64" else pic.PIC_PREC_MIXED
+    g = gpu_run(C3PHYS, parts, p, diag_every=10)
+    g.step(C3PHYS.steps)
+    h = g.history()
+    g.close()
+    assert [x["step"] for x in h] == list(o["step"])
+    W = np.array([x["W"] for x in h])
+    K = np.array([x["kinetic"][:2] for x in h])
+    assert [x["collisions"] for x in h] == list(o["coll"])
+    w_err = float(np.max(np.abs(W - o["W"])[1:] / np.abs(o["W"])[1:]))
+    k_err = float(np.max(np.abs(K - o["K"]) / o["K"]))
+    Wb, Wbo = W[:, 3] + W[:, 4], o["W"][:, 3] + o["W"][:, 4]
+    win = growth_window(o["t"], Wbo)
+    assert o["t"][win[0]] > 20 and o["t"][win[1] - 1] < 70 and win[1] - win[0] >= 15
+    rate_o = theory.fit_growth_rate(o["t"], Wbo, win)
+    rate_g = theory.fit_growth_rate(o["t"], Wb, win)
+    log(f"  worst record: W_i {w_err:.2e}, kinetic {k_err:.2e}; growth rate over t = "
+        f"{o['t'][win[0]]:.0f}..{o['t'][win[1] - 1]:.0f}: gpu {rate_g:.6f} oracle {rate_o:.6f} "
+        f"({rate_g / rate_o - 1:.1e})")
+    assert 0.05 < rate_o < 0.12                  # a growing transverse field
+    assert Wbo[-1] > 1e3 * Wbo[1]                # saturated far above the initial noise
+    assert w_err < w_bar and k_err < k_bar
+    assert abs(rate_g / rate_o - 1) < rate_bar

@@ -91,3 +91,38 @@ def test_restore_continues_a_3d_run(pic, prec, tmp_path):
         assert np.max(np.abs(xa[:, oa] - xb[:, ob])) < 1e-12
     for r in (a, b):
         r.close()
+
+
+def test_restore_ignores_descriptor_padding(pic, tmp_path):
+    """The descriptors' padding bytes (after precision, run, ppc, ...) carry
+    no data: a run whose descriptors were built over garbage bytes (as a C
+    caller's uninitialised stack would leave them) writes a checkpoint that a
+    run with zeroed descriptors restores."""
+    import ctypes as C
+    log("case checkpoint padding")
+    wl = synth.beam_plasma((32, 32), ppc=8, u_th_beam=0.2, name="pad")
+    g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, diag_every=5)
+    g_dirty = pic.GridDesc()
+    C.memset(C.byref(g_dirty), 0xAB, C.sizeof(g_dirty))
+    sp_dirty = (pic.SpeciesDesc * len(sp))()
+    C.memset(sp_dirty, 0xCD, C.sizeof(sp_dirty))
+    for name, _ in pic.GridDesc._fields_:
+        setattr(g_dirty, name, getattr(g, name))
+    for i in range(len(sp)):
+        for name, _ in pic.SpeciesDesc._fields_:
+            setattr(sp_dirty[i], name, getattr(sp[i], name))
+    assert bytes(g_dirty) != bytes(g)           # the padding differs
+    a = pic.Run(g_dirty, sp_dirty)
+    a.step(5)
+    path = str(tmp_path / "pad.ckpt")
+    a.checkpoint(path)
+    g2, sp2 = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, diag_every=5, flags=pic.PIC_FLAG_HOST_LOAD)
+    b = pic.Run(g2, sp2)
+    b.restore(path)
+    a.step(5)
+    b.step(5)
+    Ea, Ba, _ = a.read_fields()
+    Eb, Bb, _ = b.read_fields()
+    assert rel_err(stack(Eb, Bb), stack(Ea, Ba)) == 0.0
+    for r in (a, b):
+        r.close()

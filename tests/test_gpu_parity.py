@@ -178,6 +178,13 @@ def test_graph_replay_matches_direct_launches(pic):
         Eb, Bb, Jb = b.read_fields()
         assert rel_err(stack(Ea, Ba), stack(Eb, Bb)) < 1e-12
         assert rel_err(Ja, Jb) < 1e-12
+    # every step of `a` was one graph replay, every step of `b` direct launches
+    ia, ib = a.info(), b.info()
+    assert ia["graph"] == 1 and ia["graph_launches"] == 30 and ia["direct_steps"] == 0
+    assert ib["graph"] == 0 and ib["graph_launches"] == 0 and ib["direct_steps"] == 30
+    assert ia["steps_enqueued"] == ib["steps_enqueued"] == 30 and ia["static_scratch"] == 0
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
