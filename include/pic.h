@@ -250,7 +250,7 @@ int pic_sync(pic_run *run);
  *                   its kernels are launched one by one (PIC_FLAG_NO_GRAPH,
  *                   or a run on the library's scratch).
  *   static_scratch  1 if the run lives on the library's own scratch
- *                   instead of the caller's.
+ *                   (pic_init_static_scratch).
  *   steps_enqueued  steps enqueued so far (graph_launches + direct_steps,
  *                   plus the steps of a restored checkpoint).
  *   graph_launches  steps enqueued as one graph replay.
@@ -311,11 +311,36 @@ int pic_checkpoint(pic_run *run, const char *path);
 int pic_restore(pic_run *run, const char *path);
 
 /* Waits for the run's stream (the caller may free the buffers once this
- * returns), then frees the handle's host state (not the caller's buffers).
- * Errors: STATE (the run is in a batch), HIP (the
+ * returns), then frees the handle's host state (not the caller's buffers)
+ * and, for a run made by pic_init_static_scratch, releases the library's
+ * scratch of its device.  Errors: STATE (the run is in a batch), HIP (the
  * wait failed; the handle is freed all the same). */
 int pic_destroy(pic_run *run);
 
+/* ---- Initialisation without a scratch allocation ---------------------------
+ * For callers that cannot allocate device memory (code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * pic_init, but the scratch buffer is not the caller's -- buffers->scratch
+ * must be NULL -- and the run uses a scratch array that the library holds on
+ * each device (PIC_STATIC_SCRATCH_BYTES, reserved on every device the
+ * library runs on until the process ends).  The caller still allocates the
+ * particle, field and diagnostic buffers.  This call allocates no device
+ * memory and creates no stream or graph: steps are launched kernel by
+ * kernel (pic_info reports graph = 0), so a caller may capture pic_step
+ * into a graph of its own.
+ * The array is shared by every run on a device: at most one run per device
+ * holds it at a time, from this call to pic_destroy; a second call on the
+ * same device returns PIC_E_STATE until then (two runs on it would race).
+ * Everything the step reads before writing it is cleared here, so the
+ * contents a previous run left behind do not matter.
+ * Errors: those of pic_init; INVALID_ARG (buffers->scratch not NULL);
+ * BUFFER_TOO_SMALL (pic_query's scratch_bytes exceeds
+ * PIC_STATIC_SCRATCH_BYTES: a grid of up to ~1M cells with 16^2 tiles fits);
+ * STATE (the device's scratch is held by another run); UNSUPPORTED (device
+ * index >= 64). */
+#define PIC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int pic_init_static_scratch(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+                            const pic_buffers *buffers, void *hip_stream, pic_run **out);
 
 /* Static string for a status code. */
 const char *pic_status_string(int status);

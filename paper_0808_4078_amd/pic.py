@@ -99,7 +99,7 @@ _lib = None
 
 EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_profiled", "pic_sync", "pic_diagnostics",
            "pic_diag_history", "pic_read_fields", "pic_write_fields", "pic_read_particles", "pic_destroy",
-           "pic_status_string", "pic_last_error", "pic_info", "pic_batch_query", "pic_batch_init", "pic_batch_step",
+           "pic_status_string", "pic_last_error", "pic_info", "pic_init_static_scratch", "pic_batch_query", "pic_batch_init", "pic_batch_step",
            "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_launch_info",
            "pic_batch_diagnostics",
            "pic_batch_destroy", "pic_tune_query",
@@ -145,6 +145,7 @@ def lib():
         vp = C.c_void_p
         L.pic_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(Sizes)]
         L.pic_init.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(Buffers), vp, P(vp)]
+        L.pic_init_static_scratch.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(Buffers), vp, P(vp)]
         L.pic_load_particles.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int64]
         L.pic_step.argtypes = [vp, C.c_int32]
         L.pic_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
@@ -259,7 +260,9 @@ class Run:
     """A PIC run on the current CUDA (HIP) device.  Buffers are torch
     tensors owned by this object; the stream is torch's current stream."""
 
-    def __init__(self, grid: GridDesc, species, device=None, stream=None):
+    def __init__(self, grid: GridDesc, species, device=None, stream=None, static_scratch: bool = False):
+        """static_scratch: initialise with pic_init_static_scratch (the run
+        uses the library's own scratch on its device; no scratch tensor)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a ROCm GPU is required for the PIC library")
@@ -284,17 +287,18 @@ class Run:
 
         self._bufs = [alloc(sz.particle_bytes[s]) for s in range(self.ns)]
         self._fields = alloc(sz.field_bytes)
-        self._scratch = alloc(sz.scratch_bytes)
+        self._scratch = None if static_scratch else alloc(sz.scratch_bytes)
         self._diag = alloc(sz.diag_bytes)
         b = Buffers()
         for s in range(self.ns):
             b.particles[s] = self._bufs[s].data_ptr()
         b.fields = self._fields.data_ptr()
-        b.scratch = self._scratch.data_ptr()
+        b.scratch = None if static_scratch else self._scratch.data_ptr()
         b.diag = self._diag.data_ptr()
         h = C.c_void_p()
-        _check(lib().pic_init(C.byref(grid), species, self.ns, C.byref(b), C.c_void_p(self.stream.cuda_stream),
-                              C.byref(h)), "pic_init")
+        init = lib().pic_init_static_scratch if static_scratch else lib().pic_init
+        _check(init(C.byref(grid), species, self.ns, C.byref(b), C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+               "pic_init_static_scratch" if static_scratch else "pic_init")
         self.h = h
 
     # ------------------------------------------------------------------
@@ -317,8 +321,8 @@ class Run:
 
     @property
     def device_bytes(self) -> int:
-        return sum(int(t.numel()) for t in self._bufs) + int(self._fields.numel() + self._scratch.numel()
-                                                             + self._diag.numel())
+        scratch = int(self._scratch.numel()) if self._scratch is not None else 0
+        return sum(int(t.numel()) for t in self._bufs) + int(self._fields.numel() + self._diag.numel()) + scratch
 
     def load_particles(self, s: int, x: np.ndarray, u: np.ndarray, ids: np.ndarray):
         x = np.ascontiguousarray(x, dtype=np.float64)
