@@ -24,42 +24,63 @@ _SRC = os.path.join(_HERE, "pic_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
+_FLAGS = ["-O3", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+          "-fno-fast-math"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (-O3, OpenMP, no fast-math, no FMA
+    contraction; portable code, since the library travels between hosts)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
-               "-ffp-contract=off", "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
+        subprocess.run(["gcc", *_FLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"], check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def build_native() -> list:
+    """Recompile the oracle for the host this process runs on (-march=native
+    added; the arithmetic is unchanged: no contraction, no fast-math, and the
+    summation order is fixed by the code) and load that build.  Used for the
+    CPU timing baseline.  Returns the compiler flags."""
+    global _lib
+    flags = _FLAGS + ["-march=native"]
+    out = _LIB.replace(".so", "_native.so")
+    subprocess.run(["gcc", *flags, "-o", out + ".tmp", _SRC, "-lm"], check=True)
+    os.replace(out + ".tmp", out)
+    _lib = None
+    lib(out)
+    return flags
 
 
 class _Grid(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("E", C.POINTER(C.c_double) * 3), ("B", C.POINTER(C.c_double) * 3),
-                ("J", C.POINTER(C.c_double) * 3)]
+                ("J", C.POINTER(C.c_double) * 3), ("nu_ee", C.c_double), ("ee_vref", C.c_double)]
 
 
 class _Species(C.Structure):
     _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double), ("nu", C.c_double),
                 ("n", C.c_int64), ("x", C.POINTER(C.c_double) * 3), ("u", C.POINTER(C.c_double) * 3),
-                ("id", C.POINTER(C.c_uint32)), ("model", C.c_int), ("vref", C.c_double)]
+                ("id", C.POINTER(C.c_uint32)), ("model", C.c_int), ("vref", C.c_double), ("ee", C.c_int)]
 
 
 class _Diag(C.Structure):
     _fields_ = [("W", C.c_double * 6), ("kinetic", C.c_double * 8), ("p_particles", C.c_double * 3),
-                ("p_species", (C.c_double * 3) * 8), ("p_field", C.c_double * 3), ("collisions", C.c_int64)]
+                ("p_species", (C.c_double * 3) * 8), ("p_field", C.c_double * 3), ("collisions", C.c_int64),
+                ("ee_pairs", C.c_int64)]
 
 
 _lib = None
 
 
-def lib():
+def lib(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        if path is None:
+            if not os.path.exists(_LIB):
+                build()
+            path = _LIB
+        L = C.CDLL(path)
         P = C.POINTER
         dp = P(C.c_double)
         L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -84,6 +105,11 @@ def lib():
         L.orc_divergence.argtypes = [P(_Grid), dp * 3, dp]
         L.orc_step.argtypes = [P(_Grid), P(_Species), C.c_int, C.c_int64, C.c_uint64, C.c_uint32, P(_Diag)]
         L.orc_step.restype = C.c_int
+        L.orc_ee_pair.argtypes = [dp, C.c_double, C.c_double, C.c_uint32, dp, C.c_double, C.c_double, C.c_double,
+                                  C.c_int64, C.c_uint64, C.c_uint32, C.c_double, C.c_double, C.c_double]
+        L.orc_ee_pair.restype = C.c_int
+        L.orc_ee_collide.argtypes = [P(_Grid), P(_Species), C.c_int, C.c_int64, C.c_uint64, C.c_uint32]
+        L.orc_ee_collide.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -134,6 +160,15 @@ def coulomb(u, pid: int, step: int, seed: int, run: int, nu: float, vref: float,
     return uu, bool(hit)
 
 
+def ee_pair(ua, ma, wa, ida, ub, mb, wb, f, step, seed, run, nu, vref, dt):
+    """One binary collision of the pair (a, b) (a first in the pair): returns
+    (u_a', u_b', scattered)."""
+    a = np.ascontiguousarray(ua, dtype=np.float64).copy()
+    b = np.ascontiguousarray(ub, dtype=np.float64).copy()
+    hit = lib().orc_ee_pair(_dp(a), ma, wa, ida, _dp(b), mb, wb, f, step, seed, run, nu, vref, dt)
+    return a, b, bool(hit)
+
+
 def boris(u, E, B, qmdt2: float) -> np.ndarray:
     uu = np.ascontiguousarray(u, dtype=np.float64).copy()
     e = np.ascontiguousarray(E, dtype=np.float64)
@@ -154,6 +189,7 @@ class SpeciesState:
     id: np.ndarray         # (N,) uint32
     model: int = 0         # 0: isotropic scattering at rate nu; 1: Coulomb small-angle, nu at speed vref
     vref: float = 0.0
+    ee: bool = False       # takes part in the binary (pairwise) collisions
 
     @property
     def n(self) -> int:
@@ -206,6 +242,7 @@ def _cspecies(sp: list[SpeciesState], ndim: int):
         c.id = s.id.ctypes.data_as(C.POINTER(C.c_uint32))
         c.model = int(s.model)
         c.vref = float(s.vref)
+        c.ee = 1 if s.ee else 0
     return arr
 
 
@@ -219,10 +256,12 @@ class OracleRun:
     events in the step.
     """
 
-    def __init__(self, ndim, n, d, dt, species: list[SpeciesState], seed: int, run: int = 0):
+    def __init__(self, ndim, n, d, dt, species: list[SpeciesState], seed: int, run: int = 0,
+                 nu_ee: float = 0.0, ee_vref: float = 0.0):
         n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
         d = tuple(float(v) for v in d) + (1.0,) * (3 - len(d))
         self.f = Fields(ndim, n, d, float(dt))
+        self.nu_ee, self.ee_vref = float(nu_ee), float(ee_vref)
         self.species = species
         for s in species:
             s.x = np.ascontiguousarray(s.x, dtype=np.float64)
@@ -232,6 +271,8 @@ class OracleRun:
         self.run = int(run)
         self.step_index = 0
         self._g = self.f.cgrid()
+        self._g.nu_ee = self.nu_ee
+        self._g.ee_vref = self.ee_vref
         self._sp = _cspecies(species, ndim)
 
     @property
@@ -253,9 +294,19 @@ class OracleRun:
                                 p_particles=np.array(d.p_particles[:]),
                                 p_species=np.array([d.p_species[s][:] for s in range(len(self.species))]),
                                 p_field=np.array(d.p_field[:]),
-                                collisions=int(d.collisions)))
+                                collisions=int(d.collisions), ee_pairs=int(d.ee_pairs)))
             self.step_index += 1
         return out
+
+    def ee_collide(self, step: int | None = None) -> int:
+        """The binary-collision stage alone, at the current positions, for time
+        level `step` (default: the run's current step); returns the number
+        of pairs that scattered."""
+        st = self.step_index if step is None else int(step)
+        n = lib().orc_ee_collide(C.byref(self._g), self._sp, len(self.species), st, self.seed, self.run)
+        if n < 0:
+            raise MemoryError("oracle binary collisions failed")
+        return int(n)
 
     def field_energy(self) -> np.ndarray:
         W = np.zeros(6)

@@ -60,6 +60,8 @@ typedef struct {
     double d[3];          /* cell size per axis in c/w_p (d[2] unused in 2D) */
     double dt;            /* time step in 1/w_p */
     double *E[3], *B[3], *J[3];   /* caller-owned planes, n[0]*n[1]*n[2] each */
+    double nu_ee;         /* electron-electron binary collisions: rate at relative speed ee_vref (0 = off) */
+    double ee_vref;       /* reference relative speed of nu_ee, units of c */
 } orc_grid;
 
 typedef struct {
@@ -73,6 +75,7 @@ typedef struct {
                              1: Coulomb small-angle scattering, momentum-transfer
                                 rate nu at speed vref, scaling as v^-3 */
     double vref;          /* reference speed of model 1, units of c */
+    int ee;               /* takes part in the binary (pairwise) collisions */
 } orc_species;
 
 typedef struct {
@@ -82,6 +85,7 @@ typedef struct {
     double p_species[8][3];/* dV sum w u^n per species */
     double p_field[3];    /* dV sum E x B (each product at the E component's point) */
     int64_t collisions;   /* number of scattering events in the step */
+    int64_t ee_pairs;     /* binary-collision pairs that scattered in the step */
 } orc_diag;
 
 /* ------------------------------------------------------------------ */
@@ -363,6 +367,208 @@ int orc_collide(double u[3], uint32_t id, int64_t step, uint64_t seed, uint32_t 
 }
 
 /* ------------------------------------------------------------------ */
+/* Binary collisions between the particles of the species that take part
+ * (the paper's "binary collision module", velocity-dependent variant):
+ * Takizuka & Abe (1977) pairing inside each cell, with the scattering done
+ * in the pair's centre-of-momentum frame so that relativistic pairs (the
+ * beam on the return current) keep their total four-momentum.
+ *
+ * Pairing (at the positions x^{n+1}, after the push, move, deposit and the
+ * scattering off the ions): the participants of a cell are ordered by the
+ * sort key word 0 of Philox4x32-10 on counter (id, step, 4, run), key
+ * (seed lo, seed hi) -- a random permutation that does not depend on the
+ * storage order -- with ties broken by id.  Pairs are (0,1), (2,3), ...;
+ * with an odd count N >= 3 the first three form the pairs (0,1), (1,2),
+ * (2,0), each at half the variance (Takizuka and Abe's rule), and the pairs
+ * continue from the fourth.
+ *
+ * One pair (a, b), a the first of the two: draws from Philox4x32-10 on
+ * counter (id_a, step, 5, run), key (seed lo, seed hi).  With the
+ * lab-frame relative velocity v_rel = |u_a/gamma_a - u_b/gamma_b| the
+ * deflection of the relative momentum in the centre-of-momentum frame is
+ * tan(theta/2) = delta, delta = s sqrt(-2 ln U0) cos(2 pi U1),
+ * s^2 = f (nu dt / 2) (vref / v_rel)^3 (f = 1, or 1/2 in the triple): the
+ * rate nu at relative speed vref with Coulomb's v^-3 law; the azimuth is
+ * phi = 2 pi U2.  The momentum p*_a of a in that frame is turned by
+ * (theta, phi) about itself (the rotation of Takizuka and Abe), p*_b =
+ * -p*_a, and both are boosted back.  Equal weights: both particles take the
+ * new momenta, so the pair keeps its momentum and energy.  Unequal weights
+ * (Nanbu and Yonemura 1998): the particle of smaller weight always takes its
+ * new momentum, the other only if U3 < w_small / w_large, which keeps
+ * momentum and energy in expectation.  A pair with v_rel = 0 is left alone.
+ * Returns the number of pairs that scattered.                            */
+typedef struct {
+    int64_t cell;
+    uint32_t key, id;
+    int s;
+    int64_t p;
+} orc_ee_entry;
+
+static int ee_cmp(const void *x, const void *y)
+{
+    const orc_ee_entry *a = (const orc_ee_entry *)x, *b = (const orc_ee_entry *)y;
+    if (a->cell != b->cell) return a->cell < b->cell ? -1 : 1;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->id != b->id) return a->id < b->id ? -1 : 1;
+    return 0;
+}
+
+/* Lorentz boost of a four-momentum (e, p) by velocity bv (|bv| < 1):
+ * sign +1 to the frame moving with bv, -1 back from it. */
+static void boost(const double bv[3], double gc, double sign, double *e, double p[3])
+{
+    const double b2 = bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
+    if (!(b2 > 0.0)) return;
+    const double bp = bv[0] * p[0] + bv[1] * p[1] + bv[2] * p[2];
+    const double c = (gc - 1.0) * bp / b2 - sign * gc * (*e);
+    const double en = gc * ((*e) - sign * bp);
+    for (int i = 0; i < 3; ++i) p[i] += c * bv[i];
+    *e = en;
+}
+
+int orc_ee_pair(double ua[3], double ma, double wa, uint32_t ida, double ub[3], double mb, double wb,
+                double f, int64_t step, uint64_t seed, uint32_t run, double nu, double vref, double dt)
+{
+    const double ga = sqrt(1.0 + ua[0] * ua[0] + ua[1] * ua[1] + ua[2] * ua[2]);
+    const double gb = sqrt(1.0 + ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+    double dv[3];
+    for (int i = 0; i < 3; ++i) dv[i] = ua[i] / ga - ub[i] / gb;
+    const double vrel = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (!(vrel > 0.0)) return 0;
+    uint32_t ctr[4] = {ida, (uint32_t)step, 5u, run};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    const double s2 = f * 0.5 * nu * dt * (vref / vrel) * (vref / vrel) * (vref / vrel);
+    const double delta = sqrt(s2) * sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
+    const double d2 = delta * delta;
+    const double st = 2.0 * delta / (1.0 + d2), omc = 2.0 * d2 / (1.0 + d2);
+    const double ph = 2.0 * M_PI * u01(r[2]);
+    const double cp = cos(ph), sp = sin(ph);
+    /* which of the two take the new momenta */
+    int take_a = 1, take_b = 1;
+    if (wa != wb) {
+        const int a_heavy = wa > wb;
+        const double ratio = a_heavy ? wb / wa : wa / wb;
+        const int heavy_scatters = u01(r[3]) < ratio;
+        if (a_heavy) take_a = heavy_scatters;
+        else take_b = heavy_scatters;
+    }
+    /* centre-of-momentum frame */
+    const double E = ma * ga + mb * gb;
+    double P[3], bv[3];
+    for (int i = 0; i < 3; ++i) {
+        P[i] = ma * ua[i] + mb * ub[i];
+        bv[i] = P[i] / E;
+    }
+    const double gc = E / sqrt(E * E - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]));
+    double ea = ma * ga, pa[3] = {ma * ua[0], ma * ua[1], ma * ua[2]};
+    boost(bv, gc, 1.0, &ea, pa);
+    /* turn p*_a by (theta, phi) about itself */
+    const double pm = sqrt(pa[0] * pa[0] + pa[1] * pa[1] + pa[2] * pa[2]);
+    const double pp = sqrt(pa[0] * pa[0] + pa[1] * pa[1]);
+    double dp[3];
+    if (pp > 0.0) {
+        dp[0] = (pa[0] * pa[2] / pp) * st * cp - (pa[1] * pm / pp) * st * sp - pa[0] * omc;
+        dp[1] = (pa[1] * pa[2] / pp) * st * cp + (pa[0] * pm / pp) * st * sp - pa[1] * omc;
+        dp[2] = -pp * st * cp - pa[2] * omc;
+    } else {
+        dp[0] = pm * st * cp;
+        dp[1] = pm * st * sp;
+        dp[2] = -pa[2] * omc;
+    }
+    double qa[3], qb[3];
+    for (int i = 0; i < 3; ++i) {
+        qa[i] = pa[i] + dp[i];
+        qb[i] = -qa[i];
+    }
+    const double eas = sqrt(ma * ma + qa[0] * qa[0] + qa[1] * qa[1] + qa[2] * qa[2]);
+    const double ebs = sqrt(mb * mb + qb[0] * qb[0] + qb[1] * qb[1] + qb[2] * qb[2]);
+    double e1 = eas;
+    boost(bv, gc, -1.0, &e1, qa);
+    if (take_a && take_b) {
+        for (int i = 0; i < 3; ++i) {
+            const double pb = P[i] - qa[i];
+            ua[i] = qa[i] / ma;
+            ub[i] = pb / mb;
+        }
+    } else if (take_a) {
+        for (int i = 0; i < 3; ++i) ua[i] = qa[i] / ma;
+    } else {
+        double e2 = ebs;
+        boost(bv, gc, -1.0, &e2, qb);
+        for (int i = 0; i < 3; ++i) ub[i] = qb[i] / mb;
+    }
+    return 1;
+}
+
+int64_t orc_ee_collide(const orc_grid *g, orc_species *sp, int ns, int64_t step, uint64_t seed, uint32_t run)
+{
+    int64_t total = 0;
+    for (int s = 0; s < ns; ++s)
+        if (sp[s].ee) total += sp[s].n;
+    if (total < 2 || !(g->nu_ee > 0.0)) return 0;
+    orc_ee_entry *ent = (orc_ee_entry *)malloc((size_t)total * sizeof(orc_ee_entry));
+    if (!ent) return -1;
+    int64_t k = 0;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int s = 0; s < ns; ++s) {
+        if (!sp[s].ee) continue;
+        for (int64_t p = 0; p < sp[s].n; ++p) {
+            int c[3] = {0, 0, 0};
+            for (int a = 0; a < g->ndim; ++a) c[a] = wrapi((int)floor(sp[s].x[a][p] / g->d[a]), g->n[a]);
+            uint32_t ctr[4] = {sp[s].id[p], (uint32_t)step, 4u, run}, r[4];
+            orc_philox4x32_10(ctr, key, r);
+            ent[k].cell = ((int64_t)c[2] * g->n[1] + c[1]) * g->n[0] + c[0];
+            ent[k].key = r[0];
+            ent[k].id = sp[s].id[p];
+            ent[k].s = s;
+            ent[k].p = p;
+            ++k;
+        }
+    }
+    qsort(ent, (size_t)total, sizeof(orc_ee_entry), ee_cmp);
+    int64_t pairs = 0;
+    for (int64_t i0 = 0; i0 < total;) {
+        int64_t i1 = i0;
+        while (i1 < total && ent[i1].cell == ent[i0].cell) ++i1;
+        const int64_t N = i1 - i0;
+        int64_t start = i0;
+        if (N >= 3 && (N & 1)) {
+            static const int tri[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+            for (int t = 0; t < 3; ++t) {
+                const orc_ee_entry *A = &ent[i0 + tri[t][0]], *B = &ent[i0 + tri[t][1]];
+                orc_species *SA = &sp[A->s], *SB = &sp[B->s];
+                double ua[3] = {SA->u[0][A->p], SA->u[1][A->p], SA->u[2][A->p]};
+                double ub[3] = {SB->u[0][B->p], SB->u[1][B->p], SB->u[2][B->p]};
+                pairs += orc_ee_pair(ua, SA->m, SA->w, A->id, ub, SB->m, SB->w, 0.5, step, seed, run, g->nu_ee,
+                                     g->ee_vref, g->dt);
+                for (int c = 0; c < 3; ++c) {
+                    SA->u[c][A->p] = ua[c];
+                    SB->u[c][B->p] = ub[c];
+                }
+            }
+            start = i0 + 3;
+        }
+        for (int64_t i = start; i + 1 < i1; i += 2) {
+            const orc_ee_entry *A = &ent[i], *B = &ent[i + 1];
+            orc_species *SA = &sp[A->s], *SB = &sp[B->s];
+            double ua[3] = {SA->u[0][A->p], SA->u[1][A->p], SA->u[2][A->p]};
+            double ub[3] = {SB->u[0][B->p], SB->u[1][B->p], SB->u[2][B->p]};
+            pairs += orc_ee_pair(ua, SA->m, SA->w, A->id, ub, SB->m, SB->w, 1.0, step, seed, run, g->nu_ee,
+                                 g->ee_vref, g->dt);
+            for (int c = 0; c < 3; ++c) {
+                SA->u[c][A->p] = ua[c];
+                SB->u[c][B->p] = ub[c];
+            }
+        }
+        i0 = i1;
+    }
+    free(ent);
+    return pairs;
+}
+
+/* ------------------------------------------------------------------ */
 /* Yee (1966) updates.  h = fraction of dt for the B half steps.         */
 void orc_yee_b(const orc_grid *g, double h)
 {
@@ -550,6 +756,10 @@ int orc_step(const orc_grid *g, orc_species *sp, int ns, int64_t step,
         }
     }
     free(part);
+    /* binary collisions at the new positions, after the scattering off the ions */
+    const int64_t ee = orc_ee_collide(g, sp, ns, step, seed, run);
+    if (ee < 0) return -1;
+    if (diag) diag->ee_pairs = ee;
     if (diag) {
         for (int ch = 0; ch < ORC_CHUNKS; ++ch) {
             for (int s = 0; s < ns && s < 8; ++s) diag->kinetic[s] += ke[ch][s] * dv;
