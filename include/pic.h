@@ -98,7 +98,28 @@ enum {
  *             tile whose population outgrows its spare capacity triggers a
  *             re-layout of the store at the end of the step; spare slots are
  *             never read, so a larger reserve costs device memory only.
- *             Must be in [0, 8]. */
+ *             Must be in [0, 8].
+ *   nu_ee, ee_vref  binary (pairwise) collisions among the particles of the
+ *             species with pic_species_desc.binary set (the paper's binary
+ *             collision module between electrons: beam-plasma and
+ *             plasma-plasma).  Each step, after the push, move, deposit and
+ *             the scattering off the ions, the participants of every cell
+ *             (at x^{n+1}) are put in the order of word 0 of Philox4x32-10 on
+ *             counter (id, step, 4, run), key (seed lo, seed hi), ties by id,
+ *             and paired (0,1), (2,3), ...; an odd count N >= 3 starts with
+ *             the triple (0,1), (1,2), (2,0) at half the variance (Takizuka
+ *             and Abe 1977).  A pair (a, b) turns its relative momentum in its
+ *             centre-of-momentum frame by theta, tan(theta/2) ~ N(0, s^2),
+ *             s^2 = (nu_ee dt/2) (ee_vref / v_rel)^3 (v_rel = |v_a - v_b| in
+ *             the lab; rate nu_ee at relative speed ee_vref, Coulomb's v^-3
+ *             law), uniform azimuth (draws: Philox4x32-10 on (id_a, step, 5,
+ *             run)); equal weights keep the pair's four-momentum, unequal
+ *             weights keep it in expectation (the heavier particle takes its
+ *             new momentum with probability w_small/w_large; Nanbu and
+ *             Yonemura 1998).  nu_ee = 0: off.  With nu_ee > 0, ee_vref must
+ *             be in (0, 1) and the participants need ids (they are tracked).
+ *             Limit: 4096 participants in one cell (PIC_E_CAPACITY beyond);
+ *             not available in ensembles. */
 typedef struct {
     int32_t ndim;
     int32_t n[3];
@@ -111,6 +132,8 @@ typedef struct {
     int32_t diag_every;
     uint32_t flags;
     double reserve;
+    double nu_ee;
+    double ee_vref;
 } pic_grid_desc;
 
 /* One particle species.
@@ -134,7 +157,9 @@ typedef struct {
  *                       kept, with momentum-transfer rate nu_m(v) =
  *                       nu_coll (coll_vref / v)^3 (v = |u|/gamma).
  *   coll_vref           reference speed of PIC_COLL_COULOMB in c (> 0 when
- *                       nu_coll > 0); ignored otherwise. */
+ *                       nu_coll > 0); ignored otherwise.
+ *   binary              1: the species takes part in the binary collisions
+ *                       of pic_grid_desc.nu_ee; 0: not. */
 typedef struct {
     double charge, mass, density;
     int32_t ppc;
@@ -144,6 +169,7 @@ typedef struct {
     double nu_coll;
     int32_t coll_model;
     double coll_vref;
+    int32_t binary;
 } pic_species_desc;
 
 /* Sizes in bytes of the caller-owned device buffers. */
@@ -168,7 +194,8 @@ typedef struct {
  *   p_particles[3] dV sum w u, time-centred, all species.
  *   p_field[3]     dV sum E x B, each product at its E component's point (B
  *                  averaged over the two points around it).
- *   collisions     scattering events during the step.
+ *   collisions     scattering events off the ions during the step.
+ *   ee_pairs       binary-collision pairs that scattered during the step.
  *   n_particles[s] particles of species s.
  *   rebins         particle-store re-layouts performed so far.
  *   gauss_resid    with PIC_FLAG_GAUSS_RESIDUAL: max over nodes of
@@ -202,6 +229,7 @@ typedef struct {
     double rho_dev;
     double continuity_resid;
     double rho_step;
+    int64_t ee_pairs;
 } pic_diag;
 
 typedef struct pic_run pic_run;

@@ -28,12 +28,16 @@ constexpr int kMomentVals = 6;
 constexpr uint32_t kPurposeCollide = 1u;
 constexpr uint32_t kPurposeLoad = 2u;
 constexpr uint32_t kPurposeCoulomb = 3u;
+constexpr uint32_t kPurposeBinaryKey = 4u;     // pairing order of the binary collisions
+constexpr uint32_t kPurposeBinaryPair = 5u;    // one pair's deflection
 
 struct DevState {
     int64_t step;        // index n of the step about to run
     int32_t par;         // particle set holding the current particles (0/1)
     int32_t rebin;       // an incoming-mover reserve overflowed during this step
-    int32_t fatal;       // sticky: the overflow list itself was exhausted
+    int32_t fatal;       // sticky: 1 overflow list exhausted, 2 particle off the grid, 4 store reserve
+                         // exhausted, 8 particle outside its bin, 16 binary collisions: a cell above the
+                         // participant limit
     int32_t pad;
     int64_t rebins;      // re-layouts performed so far
     int64_t ring_head;   // diagnostic records written so far
@@ -68,6 +72,7 @@ struct SpeciesDev {
     int32_t id_base;
     double drift[3];     // loader: mean momentum
     double uth;          // loader: Gaussian spread per component
+    int32_t binary;      // takes part in the binary (pairwise) collisions
 };
 
 struct Geometry {
@@ -111,6 +116,10 @@ struct KParams {
     uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
     double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
     int32_t coulomb;     // 1 if a species scatters with the Coulomb model (selects the particle kernel)
+    double nu_ee;        // binary collisions: rate at relative speed ee_vref (0 = off)
+    double ee_vref;
+    int32_t binary;      // 1 if the binary-collision kernel runs (nu_ee > 0 and a species takes part)
+    int64_t *ee_tile;    // [tiles] binary-collision pairs scattered in the tile this step
     // Gauss-law and continuity checks (PIC_FLAG_GAUSS_RESIDUAL only; null otherwise)
     double *rho_tile;    // [tiles][(T+1)^ndim] per-tile charge partials
     double *rho0;        // [cells] charge on the nodes at step 0
@@ -154,12 +163,12 @@ constexpr int kBatchRebinBlocks = 256;
 constexpr int kNumGroups = 6;
 constexpr int kStepKernels = 13;
 constexpr int kKernelGroup[kStepKernels] = {0, 1, 2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5};
-// With PIC_FLAG_GAUSS_RESIDUAL the step starts with the charge deposit and
-// the Gauss residual, and the current reduction is followed by the charge
-// deposit after the move and the continuity residual (all four counted with
-// the field diagnostics).
-constexpr int kGaussStepKernels = kStepKernels + 4;
-constexpr int kKernelGroupGauss[kGaussStepKernels] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 3, 0, 0, 4, 4, 4, 5};
+// A single run's step is kStepKernels launches, plus four with
+// PIC_FLAG_GAUSS_RESIDUAL (the charge deposits and residuals of the Gauss
+// and continuity checks, group 0) and one with binary collisions (group 1).
+// step_kernel_groups fills groups[] with each launch's group and returns the
+// number of launches.
+int step_kernel_groups(const KParams &hp, int *groups);
 // ev: NULL, or 2 * kStepKernels events (start/stop of each dispatch)
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t s, hipEvent_t *ev = nullptr);
 // Batch step: the particle kernel is one launch per tile group (empty groups

@@ -1294,6 +1294,303 @@ __global__ __launch_bounds__(256) void k_continuity(const KParams *__restrict__ 
     block_max2(m, kp->cont_part);
 }
 
+// ---------------------------------------------------------------------------
+// Binary (pairwise) collisions among the species that take part, after the
+// particles of the step have been binned (the paper's binary collision
+// module between electrons).  In each cell the participants are ordered by
+// a Philox key on (id, step) -- ties by id -- and paired (0,1), (2,3), ...;
+// an odd count N >= 3 starts with the triple (0,1), (1,2), (2,0) at half the
+// variance (Takizuka and Abe 1977).  A pair turns its relative momentum in
+// its centre-of-momentum frame by theta, tan(theta/2) = delta ~ N(0, s^2),
+// s^2 = f (nu dt/2)(vref/v_rel)^3, at a uniform azimuth, and is boosted back:
+// equal weights keep the pair's four-momentum; with unequal weights the
+// heavier particle takes its new momentum with probability w_small/w_large
+// (Nanbu and Yonemura 1998).
+//
+// One workgroup per tile.  The tile's participants are counted per cell,
+// then handled in ranges of consecutive cells holding at most kBinCap of
+// them: their sort keys, ids and slots go to LDS in cell order, each cell's
+// segment is ordered by rank (key, id), and the pairs (a triple counts as
+// one unit, done by one thread in order) are spread over the threads; the
+// momenta are read and written in the particle store in place.
+constexpr int kBinCap = 4096;
+
+template <typename R>
+__device__ __forceinline__ void boost_frame(const R (&bv)[3], R b2, R gc, R sign, R &e, R (&p)[3])
+{
+    if (!(b2 > R(0))) return;
+    const R bp = bv[0] * p[0] + bv[1] * p[1] + bv[2] * p[2];
+    const R c = (gc - R(1)) * bp / b2 - sign * gc * e;
+    const R en = gc * (e - sign * bp);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] += c * bv[i];
+    e = en;
+}
+
+// One pair (a first).  Returns true if the pair scattered; ua, ub hold the
+// momenta (gamma v / c) of the particles that take their new momenta.
+template <typename R>
+__device__ bool binary_pair(R (&ua)[3], R ma, R wa, uint32_t ida, R (&ub)[3], R mb, R wb, R f, uint32_t step,
+                            uint32_t seed0, uint32_t seed1, uint32_t run, R cee)
+{
+    const R ga = sqrt(R(1) + ua[0] * ua[0] + ua[1] * ua[1] + ua[2] * ua[2]);
+    const R gb = sqrt(R(1) + ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+    R dv[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dv[i] = ua[i] / ga - ub[i] / gb;
+    const R vrel = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (!(vrel > R(0))) return false;
+    const uint4 r = philox10(make_uint4(ida, step, kPurposeBinaryPair, run), seed0, seed1);
+    const R iv = R(1) / vrel;
+    const R s2 = f * cee * iv * iv * iv;
+    R sn, cs;
+    const R delta = sqrt(s2) * sqrt(R(-2) * Arith<R>::ln(R(u01d(r.x)))) *
+                    Arith<R>::cs(R(6.283185307179586) * R(u01d(r.y)));
+    const R d2 = delta * delta;
+    const R st = R(2) * delta / (R(1) + d2), omc = R(2) * d2 / (R(1) + d2);
+    Arith<R>::sc(R(6.283185307179586) * R(u01d(r.z)), &sn, &cs);
+    bool take_a = true, take_b = true;
+    if (wa != wb) {
+        const bool a_heavy = wa > wb;
+        const R ratio = a_heavy ? wb / wa : wa / wb;
+        const bool heavy = R(u01d(r.w)) < ratio;
+        if (a_heavy) take_a = heavy;
+        else take_b = heavy;
+    }
+    const R E = ma * ga + mb * gb;
+    R P[3], bv[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        P[i] = ma * ua[i] + mb * ub[i];
+        bv[i] = P[i] / E;
+    }
+    const R b2 = bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
+    const R gc = E / sqrt(E * E - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]));
+    R ea = ma * ga, pa[3] = {ma * ua[0], ma * ua[1], ma * ua[2]};
+    boost_frame<R>(bv, b2, gc, R(1), ea, pa);
+    const R pm = sqrt(pa[0] * pa[0] + pa[1] * pa[1] + pa[2] * pa[2]);
+    const R pp = sqrt(pa[0] * pa[0] + pa[1] * pa[1]);
+    R dp[3];
+    if (pp > R(0)) {
+        dp[0] = (pa[0] * pa[2] / pp) * st * cs - (pa[1] * pm / pp) * st * sn - pa[0] * omc;
+        dp[1] = (pa[1] * pa[2] / pp) * st * cs + (pa[0] * pm / pp) * st * sn - pa[1] * omc;
+        dp[2] = -pp * st * cs - pa[2] * omc;
+    } else {
+        dp[0] = pm * st * cs;
+        dp[1] = pm * st * sn;
+        dp[2] = -pa[2] * omc;
+    }
+    R qa[3], qb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        qa[i] = pa[i] + dp[i];
+        qb[i] = -qa[i];
+    }
+    R e1 = sqrt(ma * ma + qa[0] * qa[0] + qa[1] * qa[1] + qa[2] * qa[2]);
+    boost_frame<R>(bv, b2, gc, R(-1), e1, qa);
+    if (take_a && take_b) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const R pb = P[i] - qa[i];
+            ua[i] = qa[i] / ma;
+            ub[i] = pb / mb;
+        }
+    } else if (take_a) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ua[i] = qa[i] / ma;
+    } else {
+        R e2 = sqrt(mb * mb + qb[0] * qb[0] + qb[1] * qb[1] + qb[2] * qb[2]);
+        boost_frame<R>(bv, b2, gc, R(-1), e2, qb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ub[i] = qb[i] / mb;
+    }
+    return true;
+}
+
+template <typename R, int D, int T>
+__global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
+{
+    constexpr int TC = D == 3 ? T * T * T : T * T;      // cells of the tile
+    __shared__ uint32_t s_cnt[TC];                       // participants per cell, then fill cursors
+    __shared__ uint32_t s_off[TC + 1];                   // tile-wide exclusive prefix of the counts
+    __shared__ uint32_t s_unit[TC + 1];                  // prefix of the work units of the range's cells
+    __shared__ uint32_t s_key[kBinCap], s_id[kBinCap], s_slot[kBinCap];
+    __shared__ uint16_t s_cell[kBinCap], s_perm[kBinCap];
+    __shared__ uint8_t s_sp[kBinCap];
+    __shared__ uint32_t s_range[2];
+    __shared__ uint32_t s_pairs;
+    const DevState *st = kp->state;
+    DevState *stw = kp->state;
+    if (st->fatal & 4) return;                           // the store was not re-laid out
+    const uint32_t step = (uint32_t)st->step;
+    const int par = st->rebin ? st->par : st->par ^ 1;   // where this step's particles now are
+    const int tile = blockIdx.x, ntiles = kp->g.ntiles;
+    const int ntx = kp->g.nt[0], nty = kp->g.nt[1];
+    const int t0[3] = {(tile % ntx) * T, ((tile / ntx) % nty) * T, (tile / (ntx * nty)) * T};
+    const uint32_t seed0 = (uint32_t)kp->seed, seed1 = (uint32_t)(kp->seed >> 32), run = kp->run;
+    const R cee = R(0.5 * kp->nu_ee * kp->g.dt * kp->ee_vref * kp->ee_vref * kp->ee_vref);
+
+    // local cell of a stored particle (-1 if outside the tile)
+    auto local_cell = [&](const SpeciesDev &S, int64_t slot) {
+        int l[3] = {0, 0, 0};
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            int ic;
+            if constexpr (sizeof(R) == 4) ic = (int)((S.cell[par][slot] >> kp->g.csh[a]) & kp->g.cmask[a]);
+            else ic = (int)floor(((const double *)S.pos[par][a])[slot]);
+            l[a] = ic - t0[a];
+            inside = inside && l[a] >= 0 && l[a] < T;
+        }
+        return inside ? (l[2] * T + l[1]) * T + l[0] : -1;
+    };
+    auto slot_of = [&](const SpeciesDev &S, int64_t k, int64_t nf, int64_t nb) {
+        return k < nf ? (int64_t)S.start[tile] + k : (int64_t)S.start[tile] + S.cap[tile] - nb + (k - nf);
+    };
+
+    for (int c = threadIdx.x; c < TC; c += blockDim.x) s_cnt[c] = 0;
+    if (threadIdx.x == 0) s_pairs = 0;
+    __syncthreads();
+    for (int s = 0; s < kp->nspecies; ++s) {
+        const SpeciesDev &S = kp->sp[s];
+        if (!S.binary) continue;
+        const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
+        for (int64_t k = threadIdx.x; k < nf + nb; k += blockDim.x) {
+            const int lc = local_cell(S, slot_of(S, k, nf, nb));
+            if (lc < 0) atomicOr(&stw->fatal, 8);
+            else atomicAdd(&s_cnt[lc], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run_total = 0;
+        for (int c = 0; c < TC; ++c) {
+            s_off[c] = run_total;
+            run_total += s_cnt[c];
+        }
+        s_off[TC] = run_total;
+    }
+    __syncthreads();
+    uint32_t my_pairs = 0;
+    int c0 = 0;
+    while (c0 < TC) {
+        if (threadIdx.x == 0) {
+            int c1 = c0;
+            while (c1 < TC && s_off[c1 + 1] - s_off[c0] <= (uint32_t)kBinCap) ++c1;
+            if (c1 == c0) {                                  // one cell above the limit: left alone
+                atomicOr(&stw->fatal, 16);
+                c1 = c0 + 1;
+                s_range[1] = 1;
+            } else {
+                s_range[1] = 0;
+            }
+            s_range[0] = (uint32_t)c1;
+        }
+        __syncthreads();
+        const int c1 = (int)s_range[0];
+        const bool skip = s_range[1] != 0;
+        const uint32_t base = s_off[c0], n_in = s_off[c1] - base;
+        if (!skip && n_in >= 2) {
+            for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) s_cnt[c] = s_off[c] - base;
+            __syncthreads();
+            // the range's participants, grouped by cell
+            for (int s = 0; s < kp->nspecies; ++s) {
+                const SpeciesDev &S = kp->sp[s];
+                if (!S.binary) continue;
+                const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
+                for (int64_t k = threadIdx.x; k < nf + nb; k += blockDim.x) {
+                    const int64_t slot = slot_of(S, k, nf, nb);
+                    const int lc = local_cell(S, slot);
+                    if (lc < c0 || lc >= c1) continue;
+                    const uint32_t pos = atomicAdd(&s_cnt[lc], 1u);
+                    const uint32_t id = S.id[par][slot];
+                    s_key[pos] = philox10(make_uint4(id, step, kPurposeBinaryKey, run), seed0, seed1).x;
+                    s_id[pos] = id;
+                    s_slot[pos] = (uint32_t)slot;
+                    s_sp[pos] = (uint8_t)s;
+                    s_cell[pos] = (uint16_t)lc;
+                }
+            }
+            __syncthreads();
+            // order inside each cell by (key, id): rank of every entry
+            for (uint32_t i = threadIdx.x; i < n_in; i += blockDim.x) {
+                const int c = s_cell[i];
+                const uint32_t j0 = s_off[c] - base, j1 = s_off[c + 1] - base;
+                const uint32_t ki = s_key[i], ii = s_id[i];
+                uint32_t rank = 0;
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const uint32_t kj = s_key[j];
+                    rank += (kj < ki || (kj == ki && s_id[j] < ii)) ? 1u : 0u;
+                }
+                s_perm[j0 + rank] = (uint16_t)i;
+            }
+            // work units per cell: N/2 pairs, or the triple and (N-3)/2 pairs
+            if (threadIdx.x == 0) {
+                uint32_t u = 0;
+                for (int c = c0; c < c1; ++c) {
+                    s_unit[c - c0] = u;
+                    const uint32_t N = s_off[c + 1] - s_off[c];
+                    u += (N & 1u) ? (N >= 3 ? 1u + (N - 3) / 2 : 0u) : N / 2;
+                }
+                s_unit[c1 - c0] = u;
+            }
+            __syncthreads();
+            const uint32_t units = s_unit[c1 - c0];
+            for (uint32_t w = threadIdx.x; w < units; w += blockDim.x) {
+                int lo = 0, hi = c1 - c0 - 1;                    // cell holding unit w
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_unit[mid] <= w) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int c = c0 + lo;
+                const uint32_t N = s_off[c + 1] - s_off[c], seg = s_off[c] - base, ui = w - s_unit[lo];
+                int np;
+                uint32_t ea[3], eb[3];
+                R fct;
+                if ((N & 1u) && ui == 0) {                       // the triple
+                    np = 3;
+                    fct = R(0.5);
+                    ea[0] = s_perm[seg]; eb[0] = s_perm[seg + 1];
+                    ea[1] = s_perm[seg + 1]; eb[1] = s_perm[seg + 2];
+                    ea[2] = s_perm[seg + 2]; eb[2] = s_perm[seg];
+                } else {
+                    np = 1;
+                    fct = R(1);
+                    const uint32_t k = (N & 1u) ? 3 + 2 * (ui - 1) : 2 * ui;
+                    ea[0] = s_perm[seg + k];
+                    eb[0] = s_perm[seg + k + 1];
+                }
+                for (int q = 0; q < np; ++q) {
+                    const SpeciesDev &SA = kp->sp[s_sp[ea[q]]];
+                    const SpeciesDev &SB = kp->sp[s_sp[eb[q]]];
+                    const uint32_t sa = s_slot[ea[q]], sb = s_slot[eb[q]];
+                    R ua[3], ub[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        ua[i] = ((const R *)SA.u[par][i])[sa];
+                        ub[i] = ((const R *)SB.u[par][i])[sb];
+                    }
+                    if (binary_pair<R>(ua, R(SA.m), R(SA.w), s_id[ea[q]], ub, R(SB.m), R(SB.w), fct, step, seed0,
+                                       seed1, run, cee)) {
+                        ++my_pairs;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            ((R *)SA.u[par][i])[sa] = ua[i];
+                            ((R *)SB.u[par][i])[sb] = ub[i];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();                                     // the LDS lists are rebuilt for the next range
+        c0 = c1;
+    }
+    atomicAdd(&s_pairs, my_pairs);
+    __syncthreads();
+    if (threadIdx.x == 0) kp->ee_tile[tile] = (int64_t)s_pairs;
+}
+
 template <typename R>
 __device__ __forceinline__ void rebin_count_ovf_body(const KParams *__restrict__ kp, int bid, int nb)
 {
@@ -1704,11 +2001,19 @@ __device__ __forceinline__ void advance_body(const KParams *__restrict__ kp, int
                 }
             __syncthreads();
         }
+        double ee = 0.0;
+        if (kp->binary) {
+            double a[1] = {0.0};
+            for (int t = threadIdx.x; t < ntiles; t += blockDim.x) a[0] += (double)kp->ee_tile[t];
+            block_sum<1>(a, (double(*)[1])sred);
+            ee = a[0];
+        }
         if (threadIdx.x == 0) {
             rec.gauss_resid = gm[0];
             rec.rho_dev = gm[1];
             rec.continuity_resid = gm[2];
             rec.rho_step = gm[3];
+            rec.ee_pairs = (int64_t)ee;
             for (int s = ns; s < kMaxSpecies; ++s) {
                 rec.kinetic[s] = 0.0;
                 rec.n_particles[s] = 0;
@@ -2050,53 +2355,71 @@ __global__ __launch_bounds__(256) void k_shift_u(const KParams *__restrict__ kp,
 struct Launcher {
     hipStream_t st;
     hipEvent_t *ev;
+    int *groups = nullptr;   // if set: the kernel group of each launch is recorded here
+    bool dry = false;        // record only, launch nothing
+    int grp = 0;             // group of the next launches
     int k = 0;
     template <typename... KArgs, typename... A>
     void operator()(void (*kern)(KArgs...), dim3 g, dim3 b, A... args)
     {
-        if (ev) hipExtLaunchKernelGGL(kern, g, b, 0, st, ev[2 * k], ev[2 * k + 1], 0, args...);
-        else hipLaunchKernelGGL(kern, g, b, 0, st, args...);
+        if (groups) groups[k] = grp;
+        if (!dry) {
+            if (ev) hipExtLaunchKernelGGL(kern, g, b, 0, st, ev[2 * k], ev[2 * k + 1], 0, args...);
+            else hipLaunchKernelGGL(kern, g, b, 0, st, args...);
+        }
         ++k;
     }
 };
 
-// Kernel order of a step (kStepKernels entries; kernel -> group map in
-// kKernelGroup): field diag | particle | 6 x re-layout | J reduction |
-// 3 x Yee | advance.
+// Kernel order of a step (groups in brackets): [0 Gauss checks: charge,
+// residual] | [0] field diag | [1] particle | [2] 6 x re-layout | [1] binary
+// collisions (if any) | [3] J reduction | [0 continuity check: charge,
+// residual] | [4] 3 x Yee | [5] advance.
 template <typename R, typename A, int D, int T>
-static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
+static hipError_t step_kernels(const KParams &hp, const KParams *dp, Launcher &L)
 {
     const int ntiles = hp.g.ntiles;
     const int64_t cells = hp.g.cells;
     const unsigned cb = (unsigned)((cells + 255) / 256);
     const unsigned nst = (unsigned)((hp.nspecies * ntiles + 255) / 256);
-    Launcher L{st, ev};
     const bool gauss = (hp.flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
     if (gauss) {
+        L.grp = 0;
         L(k_rho<R, D, T, false>, dim3(ntiles), dim3(256), dp);
         L(k_gauss<R, D>, dim3(cb), dim3(256), dp);
     }
+    L.grp = 0;
     L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
+    L.grp = 1;
     if (hp.coulomb) L(k_particle<R, A, D, T, true>, dim3(ntiles), dim3(kBlock), dp);
     else L(k_particle<R, A, D, T, false>, dim3(ntiles), dim3(kBlock), dp);
+    L.grp = 2;
     L(k_rebin_count, dim3(nst), dim3(256), dp);
     L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_scan, dim3(hp.nspecies), dim3(256), dp);
     L(k_rebin_scatter<R>, dim3(1024), dim3(256), dp);
     L(k_rebin_scatter_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_finalize, dim3(nst), dim3(256), dp);
+    if (hp.binary) {
+        L.grp = 1;
+        L(k_binary<R, D, T>, dim3(ntiles), dim3(256), dp);
+    }
+    L.grp = 3;
     L(k_reduce_j<R, D>, dim3(cb), dim3(256), dp);
     if (gauss) {
+        L.grp = 0;
         L(k_rho<R, D, T, true>, dim3(ntiles), dim3(256), dp);
         L(k_continuity<R, D>, dim3(cb), dim3(256), dp);
     }
     // frozen fields: the Yee kernels still run (fixed launch shape) but exit
     const double h = (hp.flags & PIC_FLAG_FREEZE_FIELDS) ? 0.0 : 0.5;
+    L.grp = 4;
     L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
     L(k_yee_e<R, D>, dim3(cb), dim3(256), dp);
     L(k_yee_b<R, D>, dim3(cb), dim3(256), dp, h);
+    L.grp = 5;
     L(k_advance, dim3(1), dim3(kAdvanceThreads), dp);
-    return hipGetLastError();
+    return L.dry ? hipSuccess : hipGetLastError();
 }
 
 // The tile current is accumulated in FP64 in LDS in both modes: on gfx950 an
@@ -2104,24 +2427,35 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, hipStream_t
 // (ds_add_f64) in this kernel (C3, 14.7 ms against 2.7 ms per launch).  The
 // partial written to HBM is in the run's precision (FP32 in mixed mode).
 template <typename R>
-static hipError_t step_prec(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
+static hipError_t step_prec(const KParams &hp, const KParams *dp, Launcher &L)
 {
     using A = double;
     if (hp.g.ndim == 3) {
-        if (hp.g.tile[0] == 8) return step_kernels<R, A, 3, 8>(hp, dp, st, ev);
+        if (hp.g.tile[0] == 8) return step_kernels<R, A, 3, 8>(hp, dp, L);
         return hipErrorInvalidValue;
     }
     switch (hp.g.tile[0]) {
-    case 8: return step_kernels<R, A, 2, 8>(hp, dp, st, ev);
-    case 16: return step_kernels<R, A, 2, 16>(hp, dp, st, ev);
-    case 32: return step_kernels<R, A, 2, 32>(hp, dp, st, ev);
+    case 8: return step_kernels<R, A, 2, 8>(hp, dp, L);
+    case 16: return step_kernels<R, A, 2, 16>(hp, dp, L);
+    case 32: return step_kernels<R, A, 2, 32>(hp, dp, L);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step(const KParams &hp, const KParams *dp, hipStream_t st, hipEvent_t *ev)
 {
-    return hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, dp, st, ev) : step_prec<double>(hp, dp, st, ev);
+    Launcher L{st, ev};
+    return hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, dp, L) : step_prec<double>(hp, dp, L);
+}
+
+int step_kernel_groups(const KParams &hp, int *groups)
+{
+    Launcher L{nullptr, nullptr};
+    L.groups = groups;
+    L.dry = true;
+    const hipError_t e = hp.precision == PIC_PREC_MIXED ? step_prec<float>(hp, nullptr, L)
+                                                       : step_prec<double>(hp, nullptr, L);
+    return e == hipSuccess ? L.k : -1;
 }
 
 // The same kernel sequence over a whole ensemble (kBatchKernels launches):

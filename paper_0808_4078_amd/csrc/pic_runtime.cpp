@@ -36,6 +36,7 @@ struct Layout {
     size_t F, J;                                            // field buffer
     size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4], order, bucket;   // scratch
     size_t rho_tile, rho0, rho_n, gauss_part, cont_part;    // scratch (Gauss-law and continuity checks)
+    size_t ee_tile;                                         // scratch (binary-collision counts per tile)
     bool checks = false;                                    // PIC_FLAG_GAUSS_RESIDUAL: the above are carved
     Geometry g;
     int nj;
@@ -85,6 +86,9 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
     if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(err, PIC_E_INVALID_ARG, "dt must be positive");
     if (g->diag_every < 0) return fail(err, PIC_E_INVALID_ARG, "diag_every < 0");
     if (!(g->reserve >= 0.0 && g->reserve <= 8.0)) return fail(err, PIC_E_INVALID_ARG, "reserve out of [0, 8]");
+    if (!(g->nu_ee >= 0.0) || !std::isfinite(g->nu_ee)) return fail(err, PIC_E_INVALID_ARG, "nu_ee must be >= 0");
+    if (g->nu_ee > 0.0 && !(g->ee_vref > 0.0 && g->ee_vref < 1.0))
+        return fail(err, PIC_E_INVALID_ARG, "binary collisions need 0 < ee_vref < 1");
     const double reserve = g->reserve > 0.0 ? g->reserve : 1.0;
     Geometry &G = L->g;
     memset(&G, 0, sizeof(G));
@@ -147,6 +151,7 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
             return fail(err, PIC_E_INVALID_ARG, "species %d: coll_model %d", s, S.coll_model);
         if (S.coll_model == PIC_COLL_COULOMB && S.nu_coll > 0.0 && !(S.coll_vref > 0.0 && S.coll_vref < 1.0))
             return fail(err, PIC_E_INVALID_ARG, "species %d: Coulomb scattering needs 0 < coll_vref < 1", s);
+        if (S.binary != 0 && S.binary != 1) return fail(err, PIC_E_INVALID_ARG, "species %d: binary %d", s, S.binary);
         if (S.cancel_current_of >= ns || S.cancel_current_of < -1)
             return fail(err, PIC_E_INVALID_ARG, "species %d: cancel_current_of %d", s, S.cancel_current_of);
         Layout::Sp &P = L->sp[s];
@@ -200,6 +205,7 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         for (int i = 0; i < 4; ++i) L->rb[i] = c.take((size_t)ns * G.ntiles * 4);
         L->order = c.take((size_t)G.ntiles * 4);
         L->bucket = c.take((size_t)G.ntiles);
+        L->ee_tile = c.take((size_t)G.ntiles * 8);
         L->checks = (g->flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
         if (L->checks) {
             int64_t n1 = 1;
@@ -309,6 +315,10 @@ int check_fatal(pic_run *r, const DevState &st)
     if (st.fatal & 4) { r->err = "particle store reserve exhausted"; return PIC_E_CAPACITY; }
     if (st.fatal & 2) { r->err = "particle left the grid (corrupt state)"; return PIC_E_HIP; }
     if (st.fatal & 8) { r->err = "particle outside its tile's bin (corrupt state)"; return PIC_E_HIP; }
+    if (st.fatal & 16) {
+        r->err = "binary collisions: a cell holds more than 4096 participants";
+        return PIC_E_CAPACITY;
+    }
     return PIC_OK;
 }
 
@@ -453,6 +463,8 @@ int batch_layout(int nruns, pic_run *const *runs, BatchLayout *B, std::string *e
             return fail(err, PIC_E_UNSUPPORTED, "run %d: members must share precision and ndim", i);
         if (r->grid.flags & PIC_FLAG_GAUSS_RESIDUAL)
             return fail(err, PIC_E_UNSUPPORTED, "run %d: PIC_FLAG_GAUSS_RESIDUAL is for single runs", i);
+        if (r->hp.binary)
+            return fail(err, PIC_E_UNSUPPORTED, "run %d: binary collisions are for single runs", i);
         for (int j = 0; j < i; ++j)
             if (runs[j] == r) return fail(err, PIC_E_INVALID_ARG, "run %d listed twice", i);
         ncb += (r->L.g.cells + 255) / 256;
@@ -562,6 +574,7 @@ bool same_grid(const pic_grid_desc &a, const pic_grid_desc &b, uint32_t ignore_f
 {
     bool same = a.ndim == b.ndim && a.dt == b.dt && a.precision == b.precision && a.seed == b.seed &&
                 a.run == b.run && a.diag_every == b.diag_every && a.reserve == b.reserve &&
+                a.nu_ee == b.nu_ee && a.ee_vref == b.ee_vref &&
                 (a.flags & ~ignore_flags) == (b.flags & ~ignore_flags);
     for (int i = 0; i < 3; ++i) same = same && a.n[i] == b.n[i] && a.d[i] == b.d[i] && a.tile[i] == b.tile[i];
     return same;
@@ -571,7 +584,7 @@ bool same_species(const pic_species_desc &a, const pic_species_desc &b)
 {
     bool same = a.charge == b.charge && a.mass == b.mass && a.density == b.density && a.ppc == b.ppc &&
                 a.u_th == b.u_th && a.cancel_current_of == b.cancel_current_of && a.nu_coll == b.nu_coll &&
-                a.coll_model == b.coll_model && a.coll_vref == b.coll_vref;
+                a.coll_model == b.coll_model && a.coll_vref == b.coll_vref && a.binary == b.binary;
     for (int i = 0; i < 3; ++i) same = same && a.drift_u[i] == b.drift_u[i];
     return same;
 }
@@ -595,6 +608,8 @@ pic_grid_desc canonical_grid(const pic_grid_desc &g)
     c.diag_every = g.diag_every;
     c.flags = g.flags;
     c.reserve = g.reserve;
+    c.nu_ee = g.nu_ee;
+    c.ee_vref = g.ee_vref;
     return c;
 }
 
@@ -612,6 +627,7 @@ pic_species_desc canonical_species(const pic_species_desc &s)
     c.nu_coll = s.nu_coll;
     c.coll_model = s.coll_model;
     c.coll_vref = s.coll_vref;
+    c.binary = s.binary;
     return c;
 }
 
@@ -737,6 +753,8 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
     K.seed = grid->seed;
     K.run = grid->run;
     K.nj = L.nj;
+    K.nu_ee = grid->nu_ee;
+    K.ee_vref = grid->ee_vref;
     int64_t id_base = 0;
     for (int s = 0; s < nspecies; ++s) {
         const pic_species_desc &S = species[s];
@@ -757,7 +775,9 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
         D.nominal = P.nominal;
         D.ovf_cap = P.ovf_cap;
         D.collide = (S.nu_coll > 0.0 && !(grid->flags & PIC_FLAG_NO_COLLIDE)) ? 1 : 0;
-        D.track_id = (D.collide || (grid->flags & PIC_FLAG_TRACK_IDS)) ? 1 : 0;
+        D.binary = (S.binary && grid->nu_ee > 0.0 && !(grid->flags & PIC_FLAG_NO_COLLIDE)) ? 1 : 0;
+        if (D.binary) K.binary = 1;
+        D.track_id = (D.collide || D.binary || (grid->flags & PIC_FLAG_TRACK_IDS)) ? 1 : 0;
         const double P_coll = 1.0 - std::exp(-S.nu_coll * grid->dt);
         const double thr = std::floor(P_coll * 4294967296.0);
         D.coll_thr = D.collide ? (uint32_t)std::min(4294967295.0, std::max(0.0, thr)) : 0u;
@@ -792,6 +812,7 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
     r->dp = (KParams *)at(buffers->scratch, L.kparams);
     K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
     K.order = (int32_t *)at(buffers->scratch, L.order);
+    K.ee_tile = (int64_t *)at(buffers->scratch, L.ee_tile);
     K.tile_bucket = (uint8_t *)at(buffers->scratch, L.bucket);
     if (L.checks) {
         K.rho_tile = (double *)at(buffers->scratch, L.rho_tile);
@@ -1005,9 +1026,10 @@ int pic_step_profiled(pic_run *r, int32_t nsteps, double *group_ms)
     if (!r || !group_ms) return fail(r ? &r->err : nullptr, PIC_E_INVALID_ARG, "bad argument");
     if (nsteps < 0) return fail(&r->err, PIC_E_INVALID_ARG, "nsteps < 0");
     if (r->owner) return fail(&r->err, PIC_E_STATE, "run is a member of a batch; step the batch");
-    const bool gauss = (r->hp.flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
-    return profiled_steps(&r->err, r->stream, nsteps, gauss ? kGaussStepKernels : kStepKernels,
-                          gauss ? kKernelGroupGauss : kKernelGroup, group_ms, [&](hipEvent_t *ev) {
+    int groups[32];
+    const int nk = step_kernel_groups(r->hp, groups);
+    if (nk <= 0 || nk > 32) return fail(&r->err, PIC_E_UNSUPPORTED, "no kernel sequence for this run");
+    return profiled_steps(&r->err, r->stream, nsteps, nk, groups, group_ms, [&](hipEvent_t *ev) {
         hipError_t e = launch_step(r->hp, r->dp, r->stream, ev);
         if (e == hipSuccess) {
             r->steps_enqueued += 1;

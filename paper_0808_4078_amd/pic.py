@@ -44,13 +44,14 @@ class GridDesc(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("run", C.c_uint32),
                 ("tile", C.c_int32 * 3), ("diag_every", C.c_int32), ("flags", C.c_uint32),
-                ("reserve", C.c_double)]
+                ("reserve", C.c_double), ("nu_ee", C.c_double), ("ee_vref", C.c_double)]
 
 
 class SpeciesDesc(C.Structure):
     _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("density", C.c_double), ("ppc", C.c_int32),
                 ("drift_u", C.c_double * 3), ("u_th", C.c_double), ("cancel_current_of", C.c_int32),
-                ("nu_coll", C.c_double), ("coll_model", C.c_int32), ("coll_vref", C.c_double)]
+                ("nu_coll", C.c_double), ("coll_model", C.c_int32), ("coll_vref", C.c_double),
+                ("binary", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -68,7 +69,8 @@ class Diag(C.Structure):
                 ("kinetic", C.c_double * MAX_SPECIES), ("p_species", (C.c_double * 3) * MAX_SPECIES),
                 ("p_particles", C.c_double * 3), ("p_field", C.c_double * 3), ("collisions", C.c_int64),
                 ("n_particles", C.c_int64 * MAX_SPECIES), ("rebins", C.c_int64), ("gauss_resid", C.c_double),
-                ("rho_dev", C.c_double), ("continuity_resid", C.c_double), ("rho_step", C.c_double)]
+                ("rho_dev", C.c_double), ("continuity_resid", C.c_double), ("rho_step", C.c_double),
+                ("ee_pairs", C.c_int64)]
 
     def as_dict(self, ns: int) -> dict:
         return dict(step=int(self.step), time=float(self.time), W=np.array(self.W[:]),
@@ -77,7 +79,8 @@ class Diag(C.Structure):
                     p_field=np.array(self.p_field[:]), collisions=int(self.collisions),
                     n_particles=np.array(self.n_particles[:ns]), rebins=int(self.rebins),
                     gauss_resid=float(self.gauss_resid), rho_dev=float(self.rho_dev),
-                    continuity_resid=float(self.continuity_resid), rho_step=float(self.rho_step))
+                    continuity_resid=float(self.continuity_resid), rho_step=float(self.rho_step),
+                    ee_pairs=int(self.ee_pairs))
 
 
 class RunInfo(C.Structure):
@@ -200,9 +203,10 @@ def _check(rc: int, what: str, handle=None):
 
 
 def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0, tile=0,
-               diag_every=0, flags=0, reserve=0.0):
+               diag_every=0, flags=0, reserve=0.0, nu_ee=0.0, ee_vref=0.0):
     """Descriptors from plain values.  species: list of dicts with keys
-    charge, mass, density, ppc, drift_u, u_th, cancel_current_of, nu_coll."""
+    charge, mass, density, ppc, drift_u, u_th, cancel_current_of, nu_coll
+    (optional: coll_model, coll_vref, binary)."""
     g = GridDesc()
     g.ndim = ndim
     for a in range(3):
@@ -216,6 +220,8 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
     g.diag_every = int(diag_every)
     g.flags = int(flags)
     g.reserve = float(reserve)
+    g.nu_ee = float(nu_ee)
+    g.ee_vref = float(ee_vref)
     arr = (SpeciesDesc * len(species))()
     for i, s in enumerate(species):
         arr[i].charge = float(s.get("charge", -1.0))
@@ -230,6 +236,7 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
         arr[i].nu_coll = float(s.get("nu_coll", 0.0))
         arr[i].coll_model = int(s.get("coll_model", PIC_COLL_ISOTROPIC))
         arr[i].coll_vref = float(s.get("coll_vref", 0.0))
+        arr[i].binary = 1 if s.get("binary", False) else 0
     return g, arr
 
 
@@ -239,11 +246,13 @@ def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, 
     optionally coll_model, coll_vref])."""
     sp = [dict(charge=s.q, mass=s.m, density=s.density, ppc=s.ppc, drift_u=s.drift_u, u_th=s.u_th,
                cancel_current_of=s.cancel_current_of, nu_coll=s.nu,
-               coll_model=getattr(s, "coll_model", PIC_COLL_ISOTROPIC), coll_vref=getattr(s, "coll_vref", 0.0))
+               coll_model=getattr(s, "coll_model", PIC_COLL_ISOTROPIC), coll_vref=getattr(s, "coll_vref", 0.0),
+               binary=getattr(s, "binary", False))
           for s in wl.species]
     if getattr(wl, "lattice", False):
         flags |= PIC_FLAG_LATTICE_LOAD
-    return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags, reserve)
+    return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags, reserve,
+                      getattr(wl, "nu_ee", 0.0), getattr(wl, "ee_vref", 0.0))
 
 
 def query(grid: GridDesc, species) -> Sizes:

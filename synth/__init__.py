@@ -38,6 +38,7 @@ class SpeciesCfg:
     cancel_current_of: int = -1   # shift this species' u_z so the net J_z is zero
     coll_model: int = 0      # 0: isotropic scattering at rate nu; 1: Coulomb small-angle
     coll_vref: float = 0.0   # Coulomb model: speed (c) at which the momentum-transfer rate is nu
+    binary: bool = False     # takes part in the binary (electron-electron) collisions of the workload
 
     @property
     def weight(self) -> float:
@@ -55,6 +56,8 @@ class Workload:
     species: tuple
     seed: int = SEED
     lattice: bool = False    # regular sub-lattice positions instead of random
+    nu_ee: float = 0.0       # binary collisions among the `binary` species: rate at relative speed ee_vref
+    ee_vref: float = 0.0
 
     @property
     def cells(self) -> int:
@@ -71,18 +74,21 @@ U_BEAM = math.sqrt(GAMMA_BEAM ** 2 - 1.0)     # 2.8284271...
 
 def beam_plasma(n, d=None, dt=0.1, steps=200, ppc=16, u_th_beam=0.1, u_th_plasma=0.01,
                 nu=0.0, n_b=0.1, u_beam=U_BEAM, name="custom", seed=SEED, lattice=False,
-                coll_model=0, coll_vref=0.0) -> Workload:
+                coll_model=0, coll_vref=0.0, nu_ee=0.0, ee_vref=0.0, binary=(True, True)) -> Workload:
     """Beam (index 0) along +z and return-current plasma (index 1); the plasma
     scatters off the ions at rate nu (coll_model 0: isotropic at a fixed
-    rate; 1: Coulomb small-angle, rate nu at speed coll_vref)."""
+    rate; 1: Coulomb small-angle, rate nu at speed coll_vref).  nu_ee > 0:
+    binary electron-electron collisions (rate nu_ee at relative speed
+    ee_vref) among the species flagged in `binary` (beam, plasma)."""
     n = tuple(int(v) for v in n)
     ndim = len(n)
     if d is None:
         d = (0.2,) * ndim
-    beam = SpeciesCfg("beam", n_b, ppc, (0.0, 0.0, u_beam), u_th_beam)
+    on = nu_ee > 0.0
+    beam = SpeciesCfg("beam", n_b, ppc, (0.0, 0.0, u_beam), u_th_beam, binary=on and binary[0])
     plasma = SpeciesCfg("plasma", 1.0 - n_b, ppc, (0.0, 0.0, 0.0), u_th_plasma, nu=nu,
-                        cancel_current_of=0, coll_model=coll_model, coll_vref=coll_vref)
-    return Workload(name, ndim, n, tuple(d), dt, steps, (beam, plasma), seed, lattice)
+                        cancel_current_of=0, coll_model=coll_model, coll_vref=coll_vref, binary=on and binary[1])
+    return Workload(name, ndim, n, tuple(d), dt, steps, (beam, plasma), seed, lattice, nu_ee, ee_vref)
 
 
 # The five workloads: 2D 64^2 FP64 parity case; 2D 1024^2 64 ppc collisional

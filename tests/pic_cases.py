@@ -16,12 +16,13 @@ def log(*a):
 
 def oracle_species(wl, parts):
     return [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x.copy(), p.u.copy(), p.id.copy(),
-                                sc.coll_model, sc.coll_vref)
+                                sc.coll_model, sc.coll_vref, getattr(sc, "binary", False))
             for sc, p in zip(wl.species, parts)]
 
 
 def oracle_run(wl, parts, run_index=0):
-    return oracle.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, oracle_species(wl, parts), wl.seed, run_index)
+    return oracle.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, oracle_species(wl, parts), wl.seed, run_index,
+                            nu_ee=getattr(wl, "nu_ee", 0.0), ee_vref=getattr(wl, "ee_vref", 0.0))
 
 
 def gpu_run(wl, parts, precision, tile=0, flags=0, diag_every=0, run_index=0):

@@ -31,10 +31,11 @@ def test_library_exports_every_declared_entry_point():
 def test_ctypes_structs_match_the_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include "pic.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc),'
                     'sizeof(pic_species_desc), sizeof(pic_sizes), sizeof(pic_buffers), sizeof(pic_diag),'
                     'offsetof(pic_grid_desc, flags), offsetof(pic_diag, rebins), sizeof(pic_hyb_desc),'
-                    'offsetof(pic_hyb_desc, flags), sizeof(pic_hyb_diag), offsetof(pic_hyb_diag, mean_psi));'
+                    'offsetof(pic_hyb_desc, flags), sizeof(pic_hyb_diag), offsetof(pic_hyb_diag, mean_psi),'
+                    'offsetof(pic_grid_desc, ee_vref), offsetof(pic_diag, ee_pairs));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -42,7 +43,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
     import ctypes as C
     want = [C.sizeof(pic.GridDesc), C.sizeof(pic.SpeciesDesc), C.sizeof(pic.Sizes), C.sizeof(pic.Buffers),
             C.sizeof(pic.Diag), pic.GridDesc.flags.offset, pic.Diag.rebins.offset, C.sizeof(pic.HybDesc),
-            pic.HybDesc.flags.offset, C.sizeof(pic.HybDiag), pic.HybDiag.mean_psi.offset]
+            pic.HybDesc.flags.offset, C.sizeof(pic.HybDiag), pic.HybDiag.mean_psi.offset,
+            pic.GridDesc.ee_vref.offset, pic.Diag.ee_pairs.offset]
     assert got == want
 
 
