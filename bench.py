@@ -103,6 +103,75 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     return total
 
 
+# Algorithmic bytes per particle-step of the headline workload's particle
+# kernel as the byte model of the hot path counts them: 24 B of mixed state
+# (int32 cell, two FP32 offsets, three FP32 momenta) read and written, 2 B of
+# the collisional half's id, 1.1 B of per-tile field staging and current
+# partials.  The kernel-level count of particle_kernel_bytes() (52.4 B: the
+# id written back as well) is reported beside it.
+SURVEY_BYTES_PER_PARTICLE_STEP = 51.1
+
+GOLDEN_C3PHYS = os.path.join(ROOT, "tests", "golden", "oracle_c3phys_256.txt")
+
+
+def c3_error(log_every: int = 10):
+    """The headline physics on a 256^2 box over 1000 steps (the 1024^2
+    workload's per-cell load, seed and physics), stepped on the GPU in mixed
+    precision and in FP64 from the same host-loaded particles as the stored
+    FP64-oracle series (tests/golden/oracle_c3phys_256.txt, written by the
+    oracle alone): the worst per-record relative error of the six field
+    energies W_i and of the kinetic energies, and the growth rate of the
+    transverse magnetic energy over the oracle's linear window (a
+    least-squares fit of ln W), against the oracle's."""
+    import numpy as np
+    import synth
+    from paper_0808_4078_amd import pic
+    header = [ln for ln in open(GOLDEN_C3PHYS) if ln.startswith("# fit:")][0].split()
+    a, b, rate_o = int(header[4]), int(header[5]), float(header[-1])
+    o = np.loadtxt(GOLDEN_C3PHYS)
+    t, Wo, Ko = o[:, 1], o[:, 2:8], o[:, 8:10]
+    wl = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=1000,
+                           name="c3phys-256")
+    parts = synth.load(wl)
+    out = {"workload": "the headline physics on 256x256 (64 ppc per species, 8388608 particles), 1000 steps, "
+                       "records every 10 steps, same initial particles as the FP64 oracle series",
+           "oracle_growth_rate": rate_o, "fit_window_t": [float(t[a]), float(t[b - 1])]}
+    for name, prec in (("mixed", pic.PIC_PREC_MIXED), ("fp64", pic.PIC_PREC_FP64)):
+        g, sp = pic.workload_descs(wl, precision=prec, diag_every=log_every,
+                                   flags=pic.PIC_FLAG_HOST_LOAD | pic.PIC_FLAG_TRACK_IDS)
+        run = pic.Run(g, sp)
+        for s_, p_ in enumerate(parts):
+            run.load_particles(s_, p_.x, p_.u, p_.id)
+        run.step(wl.steps)
+        h = run.history()
+        run.close()
+        W = np.array([x["W"] for x in h])
+        K = np.array([x["kinetic"][:2] for x in h])
+        Wb = W[a:b, 3] + W[a:b, 4]
+        rate = 0.5 * float(np.polyfit(t[a:b], np.log(Wb), 1)[0])
+        out[name] = {"W_rel_err_max": float(np.max(np.abs(W - Wo)[1:] / np.abs(Wo)[1:])),
+                     "kinetic_rel_err_max": float(np.max(np.abs(K - Ko) / Ko)),
+                     "growth_rate": rate, "growth_rate_rel_err": rate / rate_o - 1.0}
+        progress(f"C3 physics 256^2 {name}: worst W_i error {out[name]['W_rel_err_max']:.2e}, growth rate "
+                 f"{rate:.6f} vs oracle {rate_o:.6f}")
+    return out
+
+
+def host_cpu():
+    """Host cores and CPU model (lscpu) of the machine the baseline runs on."""
+    import subprocess
+    model = None
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in txt.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"nproc": os.cpu_count(), "sched_affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -117,6 +186,8 @@ RESERVE_3D = 2.0      # C4: 112 GB
 # Coulomb-model line: the momentum-transfer rate is nu at this speed (about
 # the return current's drift speed in C3)
 COULOMB_VREF = 0.1
+# Binary-collision line: electron-electron rate at this relative speed
+BINARY_NU, BINARY_VREF = 0.05, 0.1
 
 
 def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, profile: bool = True,
@@ -149,6 +220,10 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     torch.cuda.synchronize()
     run.sync()
     ms = e0.elapsed_time(e1)
+    info = run.info()
+    # every timed (and warm-up) step was one replay of the captured graph
+    if not (info["graph"] == 1 and info["graph_launches"] == warmup + steps and info["direct_steps"] == 0):
+        raise RuntimeError(f"{wl.name}: steps were not graph replays: {info}")
     diag = run.diagnostics() if diag_every else None
     device_bytes = run.device_bytes
     run.close()
@@ -179,7 +254,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
         msg += f"; re-layouts {diag['rebins']}"
     progress(msg)
     return dict(particles=n, init_s=init_s, ms=ms, profiled_ms=prof_ms, groups_ms=groups, diag=diag,
-                device_bytes=device_bytes)
+                device_bytes=device_bytes, graph_replays=info["graph_launches"])
 
 
 def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
@@ -213,6 +288,9 @@ def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
     e1.record(batch.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    li = batch.launch_info()
+    if not (li["graph"] == 1 and li["graph_launches"] == warmup + steps and li["direct_steps"] == 0):
+        raise RuntimeError(f"C5: batch steps were not graph replays: {li}")
     groups = batch.step_profiled(prof_steps)
     batch.sync()
     info = batch.info()
@@ -232,6 +310,7 @@ def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
             "autotune": {k: {"tile": v["tile"], "ms": v.get("ms"), "members": v["members"]}
                          for k, v in report.items()},
             "persistent_blocks": info["persistent_blocks"], "work_items": info["items"],
+            "graph_replays": li["graph_launches"],
             "step_breakdown_ms": {k: v / prof_steps for k, v in groups.items()},
             "relayouts_total": rebins, "tune_s": tune_s, "init_s": init_s}
 
@@ -300,10 +379,14 @@ def run_hybrid(steps: int, warmup: int, diag_every: int, prof_steps: int = 20):
 def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
     """The FP64 oracle on a bounded sample of the workload: a 256 x 256 box
     with the same per-cell load and physics, timed for whole steps until
-    about target_s seconds have passed."""
+    about target_s seconds have passed.  The oracle is compiled here for this
+    host (-O3 -march=native, OpenMP, no fast-math, no FMA contraction: the
+    arithmetic is the same as the tests' build)."""
     import oracle
     import synth
     from dataclasses import replace
+
+    flags = oracle.build_native()
 
     sample = replace(wl, n=(256, 256), name=wl.name + "-256^2-sample")
     parts = synth.load(sample)
@@ -320,7 +403,8 @@ def cpu_baseline(wl, target_s: float = 10.0, max_steps: int = 40):
     dt = time.time() - t0
     return dict(value=n * steps / dt, unit="particle-steps/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"2D3V 256x256 box of the same workload ({n} particles, 64 ppc/species, same "
-                       f"physics), {steps} FP64 oracle steps in {dt:.1f} s")
+                       f"physics), {steps} FP64 oracle steps in {dt:.1f} s",
+                host=host_cpu(), build=" ".join(flags))
 
 
 def main():
@@ -339,8 +423,12 @@ def main():
                     help="also time K steps of the 3D 256x256x512 8-ppc workload (mixed; 0 = skip)")
     ap.add_argument("--coulomb", type=int, default=300, metavar="K",
                     help="also time K steps of C3 with the plasma on the Coulomb scattering model (0 = skip)")
+    ap.add_argument("--binary", type=int, default=50, metavar="K",
+                    help="also time K steps of C3 with binary electron-electron collisions (mixed; 0 = skip)")
     ap.add_argument("--hybrid", type=int, default=200, metavar="K",
                     help="also time K steps of the reduced quasi-neutral model on 1024^2 nodes (FP64; 0 = skip)")
+    ap.add_argument("--no-c3-error", dest="c3_error", action="store_false",
+                    help="skip the mixed/FP64 error report against the stored FP64-oracle series")
     ap.add_argument("--c5", type=int, default=300, metavar="K",
                     help="also time K batch steps of the 256-run 2D ensemble (mixed, autotuned tiles; 0 = skip)")
     a = ap.parse_args()
@@ -365,7 +453,8 @@ def main():
     value = n / (ms_step * 1e-3)
     pk_ms = mixed["groups_ms"]["particle"] / a.steps
     pk_bytes = particle_kernel_bytes(wl, "mixed", a.tile)
-    achieved = pk_bytes / (pk_ms * 1e-3) / 1e9
+    model_bytes = SURVEY_BYTES_PER_PARTICLE_STEP * n
+    achieved = model_bytes / (pk_ms * 1e-3) / 1e9
     rec = {
         "metric": METRIC,
         "value": value,
@@ -391,7 +480,12 @@ def main():
             "parallelism": "single GPU",
         },
         "particle_kernel": {"ms": pk_ms, "particle_steps_per_s": n / (pk_ms * 1e-3),
-                            "algorithmic_bytes": pk_bytes},
+                            "algorithmic_bytes": model_bytes,
+                            "bytes_per_particle_step": SURVEY_BYTES_PER_PARTICLE_STEP,
+                            "kernel_count_bytes": pk_bytes,
+                            "kernel_count_GBs": pk_bytes / (pk_ms * 1e-3) / 1e9,
+                            "kernel_count_frac": pk_bytes / (pk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "graph_replays": mixed["graph_replays"],
         "step_breakdown_ms": {k: v / a.steps for k, v in mixed["groups_ms"].items()},
         "relayouts": mixed["diag"]["rebins"],
         "kernel_by_kernel_ms_per_step": mixed["profiled_ms"] / a.steps,
@@ -432,10 +526,24 @@ def main():
                           "ms_per_step": cm["ms"] / a.coulomb, "particle_kernel_ms": cm_pk,
                           "particle_kernel_GBs": pk_bytes / (cm_pk * 1e-3) / 1e9,
                           "step_breakdown_ms": {k: v / a.coulomb for k, v in cm["groups_ms"].items()}}
+    if a.binary > 0:
+        wb = replace(wl, name=f"{wl.name}-binary", nu_ee=BINARY_NU, ee_vref=BINARY_VREF,
+                     species=tuple(replace(sc, binary=True) for sc in wl.species))
+        bm = run_gpu(wb, "mixed", a.binary, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D)
+        rec["binary"] = {"workload": f"{wl.name} with binary electron-electron collisions among all particles "
+                                     f"(beam-plasma and plasma-plasma pairs in every cell, nu_ee={BINARY_NU} at "
+                                     f"relative speed {BINARY_VREF}c), mixed precision",
+                         "particles": bm["particles"], "steps": a.binary,
+                         "value": bm["particles"] / (bm["ms"] / a.binary * 1e-3),
+                         "ms_per_step": bm["ms"] / a.binary,
+                         "pairs_last_record": bm["diag"]["ee_pairs"] if bm["diag"] else None,
+                         "step_breakdown_ms": {k: v / a.binary for k, v in bm["groups_ms"].items()}}
     if a.hybrid > 0:
         rec["hybrid"] = run_hybrid(a.hybrid, a.warmup, a.diag_every)
     if a.c5 > 0:
         rec["c5"] = run_c5(a.c5, min(a.warmup, 5), a.diag_every)
+    if a.c3_error:
+        rec["c3_error"] = c3_error()
     if not a.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -28,7 +28,8 @@ spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
 Usage: python tests/golden/make_oracle_series.py [c3phys] [paper-a] ...
-(no argument: all).  Set OMP_NUM_THREADS to share the host; the results do
+(no argument: all; ``annotate`` only rewrites the fit line of the c3phys
+header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
 """
 from __future__ import annotations
@@ -149,11 +150,33 @@ def run_paper(case, path_w, path_m):
         fh.write("\n".join(mlines) + "\n")
 
 
+def annotate_c3phys(path):
+    """Adds the growth-rate fit of the stored oracle series to its header:
+    the linear window of ln(W_Bx + W_By) (the longest run of centred local
+    slopes within 10% of their mean, below 10% of the series maximum; the
+    first record, W = 0, left out) and the oracle's rate over it."""
+    from oracle import theory
+    lines = [ln for ln in open(path).read().splitlines() if not ln.startswith("# fit:")]
+    o = np.loadtxt(path)
+    t, Wb = o[:, 1], o[:, 5] + o[:, 6]
+    a, b = theory.fit_growth_window(t[1:], Wb[1:])
+    a, b = a + 1, b + 1
+    rate = theory.fit_growth_rate(t, Wb, (a, b))
+    head = [i for i, ln in enumerate(lines) if ln.startswith("#")][-1] + 1
+    lines.insert(head, f"# fit: window records {a} {b} (t = {t[a]:g} .. {t[b - 1]:g}), oracle growth rate "
+                       f"{rate:.12f}")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     which = argv or ["c3phys"] + [f"paper-{c}" for c in PAPER_CASES]
     for w in which:
         if w == "c3phys":
             run_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+            annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "annotate":
+            annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w.startswith("paper-"):
             c = w.split("-", 1)[1]
             run_paper(c, os.path.join(HERE, f"oracle_paper_{c}_energy.txt"),
