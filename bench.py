@@ -84,8 +84,8 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     """Algorithmic HBM bytes of one particle-kernel launch.
 
     Every particle's state is read once and written once:
-      mixed: int32 cell + one FP32 offset per resolved axis + 3 FP32 momenta
-             (2D: 24 B, 3D: 28 B);
+      mixed: 16-bit cell within the tile + one FP32 offset per resolved axis
+             + 3 FP32 momenta (2D: 22 B, 3D: 26 B);
       FP64:  one FP64 position per resolved axis + 3 FP64 momenta (2D: 40 B);
     a collisional particle's state also holds its 4-byte id, which keys its
     scattering draw and therefore travels with it (read and written).
@@ -93,7 +93,7 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     (T+3)^D nodes."""
     r = 4 if precision == "mixed" else 8
     d = wl.ndim
-    state = (4 + d * 4 + 3 * 4) if precision == "mixed" else (d * 8 + 3 * 8)
+    state = (2 + d * 4 + 3 * 4) if precision == "mixed" else (d * 8 + 3 * 8)
     total = 0.0
     for sc in wl.species:
         n = wl.cells * sc.ppc
@@ -107,8 +107,9 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
 # kernel as the byte model of the hot path counts them: 24 B of mixed state
 # (int32 cell, two FP32 offsets, three FP32 momenta) read and written, 2 B of
 # the collisional half's id, 1.1 B of per-tile field staging and current
-# partials.  The kernel-level count of particle_kernel_bytes() (52.4 B: the
-# id written back as well) is reported beside it.
+# partials.  The kernel's own count of what its layout moves,
+# particle_kernel_bytes() (a 16-bit in-tile cell; the id written back as
+# well), is reported beside it.
 SURVEY_BYTES_PER_PARTICLE_STEP = 51.1
 
 GOLDEN_C3PHYS = os.path.join(ROOT, "tests", "golden", "oracle_c3phys_256.txt")

@@ -46,10 +46,13 @@ struct DevState {
 
 // Particle arrays of one species.  Sets 0 and 1 alternate as source and
 // destination from step to step; set 2 is the overflow list.
-//  mixed: cell (packed ix | iy << sh1 | iz << sh2), pos = FP32 in-cell offset
-//  fp64 : cell unused, pos = absolute FP64 position in cell units
+//  mixed: sets 0, 1: cell within the tile of the particle's bin, 16 bits
+//         (lx | ly << ts | lz << 2 ts, ts = log2 T); set 2: global packed
+//         cell (ix | iy << sh1 | iz << sh2); pos = FP32 in-cell offset
+//  fp64 : no cell array, pos = absolute FP64 position in cell units
 struct SpeciesDev {
-    uint32_t *cell[3];
+    uint16_t *cell[2];
+    uint32_t *ovf_cell;
     void *pos[3][3];     // [set][axis]
     void *u[3][3];       // [set][component]
     uint32_t *id[3];

@@ -115,6 +115,19 @@ template <> struct Arith<double> {
     static __device__ __forceinline__ double cs(double a) { return cos(a); }
 };
 
+// Mixed precision: a particle in a bin keeps its cell within the tile (16
+// bits, lx | ly << ts | lz << 2 ts with ts = log2 T; the tile follows from
+// the bin, and a tile's origin is a multiple of T on every axis), the
+// overflow list the global packed cell (ix | iy << csh[1] | iz << csh[2]).
+__device__ __forceinline__ uint32_t local_of_global(const Geometry &g, uint32_t c)
+{
+    const int ts = g.tshift[0];
+    const uint32_t m = (uint32_t)g.tile[0] - 1u;
+    uint32_t l = 0;
+    for (int a = 0; a < g.ndim; ++a) l |= (((c >> g.csh[a]) & g.cmask[a]) & m) << (a * ts);
+    return l;
+}
+
 // The step counter and particle-set parity live in memory that kernels also
 // update; reading them through readfirstlane tells the compiler they are
 // uniform, so everything indexed by them stays in scalar registers.
@@ -490,6 +503,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
     constexpr int NF_D = D == 3 ? NF * NF * NF : NF * NF;
     constexpr int NJ_D = D == 3 ? NJ * NJ * NJ : NJ * NJ;
     constexpr int SJ_Y = NJ, SJ_Z = NJ * NJ;        // LDS strides of the current tile
+    constexpr int TS = T == 8 ? 3 : T == 16 ? 4 : 5; // log2 T: bit width of an in-tile cell coordinate
     __shared__ R sF[6 * NF_D];
     __shared__ A sJ[3 * NJ_D];
     constexpr int QC = kQueue<D>;
@@ -576,7 +590,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         const R csig2 = R(S.coll_sig2);
         const bool track = S.track_id != 0;
         const uint32_t thr = S.coll_thr;
-        const GLB uint32_t *__restrict__ icell = gbl(S.cell[src]);
+        const GLB uint16_t *__restrict__ icell = gbl(S.cell[src]);
         const GLB R *__restrict__ ipos[3] = {gbl((const R *)S.pos[src][0]), gbl((const R *)S.pos[src][1]),
                                              gbl((const R *)S.pos[src][2])};
         const GLB R *__restrict__ iu0 = gbl((const R *)S.u[src][0]);
@@ -589,7 +603,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         const GLB uint32_t *__restrict__ cb_src = gbl(S.cnt_back + src * ntiles);
         GLB uint32_t *cb_dst = gbl(S.cnt_back + dst * ntiles);
 
-        GLB uint32_t *__restrict__ ocell = gbl(S.cell[dst]);
+        GLB uint16_t *__restrict__ ocell = gbl(S.cell[dst]);
         GLB R *__restrict__ opos_a[3] = {gbl((R *)S.pos[dst][0]), gbl((R *)S.pos[dst][1]), gbl((R *)S.pos[dst][2])};
         GLB R *__restrict__ ou0 = gbl((R *)S.u[dst][0]);
         GLB R *__restrict__ ou1 = gbl((R *)S.u[dst][1]);
@@ -611,7 +625,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         };
         auto fetch = [&](uint32_t k, Raw &r) {
             const uint32_t slot = k < nf ? (uint32_t)bstart + k : (uint32_t)(bstart + bcap) - nb + (k - nf);
-            if constexpr (sizeof(R) == 4) r.c = ld(icell, slot);
+            if constexpr (sizeof(R) == 4) r.c = (uint32_t)ld(icell, slot);
 #pragma unroll
             for (int a = 0; a < D; ++a) r.p[a] = ld(ipos[a], slot);
             r.u[0] = ld(iu0, slot);
@@ -651,7 +665,12 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         auto emit_mover = [&](uint32_t slot, int32_t room, int32_t top, const Raw &m) {
             if ((int64_t)slot < (int64_t)room) {
                 const uint32_t o = (uint32_t)top - slot;
-                if constexpr (sizeof(R) == 4) st(ocell, o, m.c);
+                if constexpr (sizeof(R) == 4) {
+                    uint32_t lc = 0;                             // the cell within the new tile
+#pragma unroll
+                    for (int a = 0; a < D; ++a) lc |= (((m.c >> csh[a]) & cmask[a]) & (uint32_t)(T - 1)) << (a * TS);
+                    st(ocell, o, (uint16_t)lc);
+                }
 #pragma unroll
                 for (int a = 0; a < D; ++a) st(opos_a[a], o, m.p[a]);
                 st(ou0, o, m.u[0]);
@@ -664,7 +683,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 const uint32_t oi = atomicAdd(&state->ovf_count[s], 1u);
                 state->rebin = 1;
                 if (oi < S.ovf_cap) {
-                    if constexpr (sizeof(R) == 4) gbl(S.cell[2])[oi] = m.c;
+                    if constexpr (sizeof(R) == 4) gbl(S.ovf_cell)[oi] = m.c;
                     for (int a = 0; a < D; ++a) gbl((R *)S.pos[2][a])[oi] = m.p[a];
                     gbl((R *)S.u[2][0])[oi] = m.u[0];
                     gbl((R *)S.u[2][1])[oi] = m.u[1];
@@ -758,7 +777,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                 if constexpr (sizeof(R) == 4) {
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        ic[a] = (int)((cur.c >> csh[a]) & cmask[a]);
+                        ic[a] = t0[a] + (int)((cur.c >> (a * TS)) & (uint32_t)(T - 1));
                         off[a] = cur.p[a];
                     }
                 } else {
@@ -965,10 +984,13 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
                     wr = true;
                 }
             }
-            uint32_t cpack = 0;
+            uint32_t cpack = 0, lpack = 0;             // global (movers) and in-tile (stayers) cell
             if constexpr (sizeof(R) == 4) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) cpack |= (uint32_t)ic1[a] << csh[a];
+                for (int a = 0; a < D; ++a) {
+                    cpack |= (uint32_t)ic1[a] << csh[a];
+                    lpack |= ((uint32_t)ic1[a] & (uint32_t)(T - 1)) << (a * TS);
+                }
             }
             {
                 const bool mover = active && !stay;
@@ -1019,7 +1041,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             }
             if (wr) {
                 if constexpr (sizeof(R) == 4) {
-                    st(ocell, opos, cpack);
+                    st(ocell, opos, (uint16_t)lpack);
 #pragma unroll
                     for (int a = 0; a < D; ++a) st(opos_a[a], opos, off1[a]);
                 } else {
@@ -1082,8 +1104,9 @@ __device__ __forceinline__ int tile_of(const KParams *kp, const SpeciesDev &S, i
     int t = 0;
     for (int a = kp->g.ndim - 1; a >= 0; --a) {
         int i;
-        if constexpr (sizeof(R) == 4) i = (int)((S.cell[set][p] >> kp->g.csh[a]) & kp->g.cmask[a]);
-        else i = (int)floor(((const double *)S.pos[set][a])[p]);
+        (void)set;   // the overflow list (set 2): global cells
+        if constexpr (sizeof(R) == 4) i = (int)((S.ovf_cell[p] >> kp->g.csh[a]) & kp->g.cmask[a]);
+        else i = (int)floor(((const double *)S.pos[2][a])[p]);
         i = min(max(i, 0), kp->g.n[a] - 1);
         t = t * kp->g.nt[a] + (i >> kp->g.tshift[a]);
     }
@@ -1136,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_rho(const KParams *__restrict__ kp)
             for (int a = 0; a < D; ++a) {
                 int ic;
                 if constexpr (sizeof(R) == 4) {
-                    ic = (int)((S.cell[par][slot] >> kp->g.csh[a]) & kp->g.cmask[a]);
+                    ic = t0[a] + (int)(((uint32_t)S.cell[par][slot] >> (a * kp->g.tshift[0])) & (uint32_t)(T - 1));
                     o[a] = (double)((const float *)S.pos[par][a])[slot];
                 } else {
                     const double X = ((const double *)S.pos[par][a])[slot];
@@ -1437,8 +1460,10 @@ __global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             int ic;
-            if constexpr (sizeof(R) == 4) ic = (int)((S.cell[par][slot] >> kp->g.csh[a]) & kp->g.cmask[a]);
-            else ic = (int)floor(((const double *)S.pos[par][a])[slot]);
+            if constexpr (sizeof(R) == 4)
+                ic = t0[a] + (int)(((uint32_t)S.cell[par][slot] >> (a * kp->g.tshift[0])) & (uint32_t)(T - 1));
+            else
+                ic = (int)floor(((const double *)S.pos[par][a])[slot]);
             l[a] = ic - t0[a];
             inside = inside && l[a] >= 0 && l[a] < T;
         }
@@ -1684,7 +1709,7 @@ struct StoredParticle {
 template <typename R>
 __device__ __forceinline__ void load_stored(const SpeciesDev &S, int nd, int set, int64_t a, StoredParticle<R> &v)
 {
-    if constexpr (sizeof(R) == 4) v.c = gbl(S.cell[set])[a];
+    if constexpr (sizeof(R) == 4) v.c = set == 2 ? gbl(S.ovf_cell)[a] : (uint32_t)gbl(S.cell[set & 1])[a];
     for (int c = 0; c < 3; ++c)
         if (c < nd) v.p[c] = gbl((const R *)S.pos[set][c])[a];
     for (int c = 0; c < 3; ++c) v.u[c] = gbl((const R *)S.u[set][c])[a];
@@ -1693,7 +1718,7 @@ __device__ __forceinline__ void load_stored(const SpeciesDev &S, int nd, int set
 template <typename R>
 __device__ __forceinline__ void store_stored(const SpeciesDev &S, int nd, int set, int64_t b, const StoredParticle<R> &v)
 {
-    if constexpr (sizeof(R) == 4) gbl(S.cell[set])[b] = v.c;
+    if constexpr (sizeof(R) == 4) gbl(S.cell[set & 1])[b] = (uint16_t)v.c;   // bins only (set 0 or 1)
     for (int c = 0; c < 3; ++c)
         if (c < nd) gbl((R *)S.pos[set][c])[b] = v.p[c];
     for (int c = 0; c < 3; ++c) gbl((R *)S.u[set][c])[b] = v.u[c];
@@ -1749,6 +1774,7 @@ __device__ __forceinline__ void rebin_scatter_ovf_body(const KParams *__restrict
             const int32_t slot = atomicAdd(&kp->rb_fill[idx], 1);
             StoredParticle<R> v;
             load_stored<R>(S, kp->g.ndim, 2, p, v);
+            if constexpr (sizeof(R) == 4) v.c = local_of_global(kp->g, v.c);
             store_stored<R>(S, kp->g.ndim, src, (int64_t)kp->rb_start[idx] + slot, v);
         }
     }
@@ -2279,10 +2305,10 @@ __global__ __launch_bounds__(256) void k_load(const KParams *__restrict__ kp, in
     if constexpr (sizeof(R) == 4) {
         uint32_t c = 0;
         for (int a = 0; a < D; ++a) {
-            c |= (uint32_t)ic[a] << kp->g.csh[a];
+            c |= ((uint32_t)ic[a] & (uint32_t)(kp->g.tile[0] - 1)) << (a * kp->g.tshift[0]);
             ((float *)S.pos[0][a])[pos] = (float)off[a];
         }
-        S.cell[0][pos] = c;
+        S.cell[0][pos] = (uint16_t)c;
     } else {
         for (int a = 0; a < D; ++a) ((double *)S.pos[0][a])[pos] = (double)ic[a] + off[a];
     }

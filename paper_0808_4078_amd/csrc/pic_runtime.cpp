@@ -175,7 +175,8 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         Carver c;
         for (int set = 0; set < 3; ++set) {
             const size_t n = set < 2 ? (size_t)P.ncap : P.ovf_cap;
-            P.cell[set] = L->real == 4 ? c.take(n * 4) : 0;
+            // mixed: 16-bit in-tile cells in the bins, global 32-bit cells in the overflow list
+            P.cell[set] = L->real == 4 ? c.take(n * (set < 2 ? 2 : 4)) : 0;
             for (int a = 0; a < 3; ++a) P.pos[set][a] = a < g->ndim ? c.take(n * L->real) : 0;
             for (int a = 0; a < 3; ++a) P.u[set][a] = c.take(n * L->real);
             P.id[set] = c.take(n * 4);
@@ -762,7 +763,8 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
         SpeciesDev &D = K.sp[s];
         void *b = buffers->particles[s];
         for (int set = 0; set < 3; ++set) {
-            D.cell[set] = L.real == 4 ? (uint32_t *)at(b, P.cell[set]) : nullptr;
+            if (set < 2) D.cell[set] = L.real == 4 ? (uint16_t *)at(b, P.cell[set]) : nullptr;
+            else D.ovf_cell = L.real == 4 ? (uint32_t *)at(b, P.cell[set]) : nullptr;
             for (int a = 0; a < 3; ++a) D.pos[set][a] = a < grid->ndim ? at(b, P.pos[set][a]) : nullptr;
             for (int a = 0; a < 3; ++a) D.u[set][a] = at(b, P.u[set][a]);
             D.id[set] = (uint32_t *)at(b, P.id[set]);
@@ -962,7 +964,8 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
     std::vector<int64_t> fill(start.begin(), start.end());
     const size_t R = L.real;
     const size_t ncap = (size_t)P.ncap;
-    std::vector<uint32_t> hcell(R == 4 ? ncap : 0), hid(ncap, 0xFFFFFFFFu);
+    std::vector<uint16_t> hcell(R == 4 ? ncap : 0);
+    std::vector<uint32_t> hid(ncap, 0xFFFFFFFFu);
     std::vector<char> hpos[3], hu[3];
     for (int a = 0; a < nd; ++a) hpos[a].assign(ncap * R, 0);
     for (int c = 0; c < 3; ++c) hu[c].assign(ncap * R, 0);
@@ -970,9 +973,10 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
         const int64_t p = order[o];
         const int64_t slot = fill[tile[p]]++;
         if (R == 4) {
-            uint32_t c = 0;
-            for (int a = 0; a < nd; ++a) c |= (uint32_t)cellc[(size_t)p * nd + a] << G.csh[a];
-            hcell[slot] = c;
+            uint32_t c = 0;     // cell within the tile
+            for (int a = 0; a < nd; ++a)
+                c |= ((uint32_t)cellc[(size_t)p * nd + a] & (uint32_t)(G.tile[a] - 1)) << (a * G.tshift[0]);
+            hcell[slot] = (uint16_t)c;
             for (int a = 0; a < nd; ++a) ((float *)hpos[a].data())[slot] = (float)off[(size_t)p * nd + a];
             for (int c3 = 0; c3 < 3; ++c3) ((float *)hu[c3].data())[slot] = (float)u[(size_t)c3 * n + p];
         } else {
@@ -983,7 +987,7 @@ int pic_load_particles(pic_run *r, int s, const double *x, const double *u, cons
         hid[slot] = id[p];
     }
     void *b = r->buf.particles[s];
-    if (R == 4) HIPCHK(r, hipMemcpy(at(b, P.cell[0]), hcell.data(), ncap * 4, hipMemcpyHostToDevice));
+    if (R == 4) HIPCHK(r, hipMemcpy(at(b, P.cell[0]), hcell.data(), ncap * 2, hipMemcpyHostToDevice));
     for (int a = 0; a < nd; ++a) HIPCHK(r, hipMemcpy(at(b, P.pos[0][a]), hpos[a].data(), ncap * R, hipMemcpyHostToDevice));
     for (int c3 = 0; c3 < 3; ++c3) HIPCHK(r, hipMemcpy(at(b, P.u[0][c3]), hu[c3].data(), ncap * R, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemcpy(at(b, P.id[0]), hid.data(), ncap * 4, hipMemcpyHostToDevice));
@@ -1145,9 +1149,10 @@ int pic_read_particles(pic_run *r, int s, double *x, double *u, uint32_t *id, in
                              (long long)cap);
     if (!x || !u) return fail(&r->err, PIC_E_INVALID_ARG, "null output arrays");
     const size_t ncap = (size_t)P.ncap, R = L.real;
-    std::vector<uint32_t> hcell(R == 4 ? ncap : 0), hid(ncap);
+    std::vector<uint16_t> hcell(R == 4 ? ncap : 0);
+    std::vector<uint32_t> hid(ncap);
     std::vector<char> hpos[3], hu[3];
-    if (R == 4) HIPCHK(r, hipMemcpy(hcell.data(), at(b, P.cell[par]), ncap * 4, hipMemcpyDeviceToHost));
+    if (R == 4) HIPCHK(r, hipMemcpy(hcell.data(), at(b, P.cell[par]), ncap * 2, hipMemcpyDeviceToHost));
     for (int a = 0; a < nd; ++a) {
         hpos[a].resize(ncap * R);
         HIPCHK(r, hipMemcpy(hpos[a].data(), at(b, P.pos[par][a]), ncap * R, hipMemcpyDeviceToHost));
@@ -1161,13 +1166,15 @@ int pic_read_particles(pic_run *r, int s, double *x, double *u, uint32_t *id, in
     int64_t k = 0;
     for (int t = 0; t < nt; ++t) {
         const int64_t nf = cf[(size_t)par * nt + t], nb = cb[(size_t)par * nt + t];
+        const int t0[3] = {(t % G.nt[0]) * G.tile[0], ((t / G.nt[0]) % G.nt[1]) * G.tile[1],
+                           (t / (G.nt[0] * G.nt[1])) * G.tile[2]};
         for (int64_t j = 0; j < nf + nb; ++j, ++k) {
             const int64_t slot = j < nf ? start[t] + j : start[t] + tcap[t] - nb + (j - nf);
             for (int a = 0; a < nd; ++a) {
                 double X;
                 if (R == 4) {
                     const uint32_t c = hcell[slot];
-                    const int ic = (int)((c >> G.csh[a]) & G.cmask[a]);
+                    const int ic = t0[a] + (int)((c >> (a * G.tshift[0])) & (uint32_t)(G.tile[a] - 1));
                     X = ic + (double)((const float *)hpos[a].data())[slot];
                 } else {
                     X = ((const double *)hpos[a].data())[slot];
