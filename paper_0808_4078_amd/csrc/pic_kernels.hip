@@ -1332,10 +1332,12 @@ __global__ __launch_bounds__(256) void k_continuity(const KParams *__restrict__ 
 //
 // One workgroup per tile.  The tile's participants are counted per cell,
 // then handled in ranges of consecutive cells holding at most kBinCap of
-// them: their sort keys, ids and slots go to LDS in cell order, each cell's
-// segment is ordered by rank (key, id), and the pairs (a triple counts as
-// one unit, done by one thread in order) are spread over the threads; the
-// momenta are read and written in the particle store in place.
+// them: their slots go to LDS with a 64-bit sort key (cell in the range,
+// Philox key, low id bits), a bitonic sort puts them in (cell, key)
+// order (equal keys, about 2^-32 per pair, are then ordered by the full id),
+// and the pairs (a triple counts as one unit, done by one thread in order)
+// are spread over the threads; the momenta are read and written in the
+// particle store in place.
 constexpr int kBinCap = 4096;
 
 template <typename R>
@@ -1430,18 +1432,21 @@ __device__ bool binary_pair(R (&ua)[3], R ma, R wa, uint32_t ida, R (&ub)[3], R 
     return true;
 }
 
+constexpr int kBinThreads = 512;
+
 template <typename R, int D, int T>
-__global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
+__global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restrict__ kp)
 {
     constexpr int TC = D == 3 ? T * T * T : T * T;      // cells of the tile
-    __shared__ uint32_t s_cnt[TC];                       // participants per cell, then fill cursors
+    __shared__ uint32_t s_cnt[TC];                       // participants per cell
     __shared__ uint32_t s_off[TC + 1];                   // tile-wide exclusive prefix of the counts
     __shared__ uint32_t s_unit[TC + 1];                  // prefix of the work units of the range's cells
-    __shared__ uint32_t s_key[kBinCap], s_id[kBinCap], s_slot[kBinCap];
-    __shared__ uint16_t s_cell[kBinCap], s_perm[kBinCap];
-    __shared__ uint8_t s_sp[kBinCap];
+    __shared__ uint64_t s_k64[kBinCap];                  // sort key: cell in range | Philox key | low id bits
+    __shared__ uint16_t s_idx[kBinCap];                  // entry of each sorted position
+    __shared__ uint32_t s_slot[kBinCap];                 // store slot of each entry
+    __shared__ uint8_t s_sp[kBinCap];                    // species of each entry
     __shared__ uint32_t s_range[2];
-    __shared__ uint32_t s_pairs;
+    __shared__ uint32_t s_fill, s_pairs, s_tie;
     const DevState *st = kp->state;
     DevState *stw = kp->state;
     if (st->fatal & 4) return;                           // the store was not re-laid out
@@ -1452,6 +1457,7 @@ __global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
     const int t0[3] = {(tile % ntx) * T, ((tile / ntx) % nty) * T, (tile / (ntx * nty)) * T};
     const uint32_t seed0 = (uint32_t)kp->seed, seed1 = (uint32_t)(kp->seed >> 32), run = kp->run;
     const R cee = R(0.5 * kp->nu_ee * kp->g.dt * kp->ee_vref * kp->ee_vref * kp->ee_vref);
+    const int lane = threadIdx.x & 63;
 
     // local cell of a stored particle (-1 if outside the tile)
     auto local_cell = [&](const SpeciesDev &S, int64_t slot) {
@@ -1510,44 +1516,88 @@ __global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
                 s_range[1] = 0;
             }
             s_range[0] = (uint32_t)c1;
+            s_fill = 0;
+            s_tie = 0;
         }
         __syncthreads();
         const int c1 = (int)s_range[0];
         const bool skip = s_range[1] != 0;
         const uint32_t base = s_off[c0], n_in = s_off[c1] - base;
         if (!skip && n_in >= 2) {
-            for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) s_cnt[c] = s_off[c] - base;
-            __syncthreads();
-            // the range's participants, grouped by cell
+            // the range's participants, in any order, with their sort keys
             for (int s = 0; s < kp->nspecies; ++s) {
                 const SpeciesDev &S = kp->sp[s];
                 if (!S.binary) continue;
                 const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
-                for (int64_t k = threadIdx.x; k < nf + nb; k += blockDim.x) {
-                    const int64_t slot = slot_of(S, k, nf, nb);
-                    const int lc = local_cell(S, slot);
-                    if (lc < c0 || lc >= c1) continue;
-                    const uint32_t pos = atomicAdd(&s_cnt[lc], 1u);
-                    const uint32_t id = S.id[par][slot];
-                    s_key[pos] = philox10(make_uint4(id, step, kPurposeBinaryKey, run), seed0, seed1).x;
-                    s_id[pos] = id;
-                    s_slot[pos] = (uint32_t)slot;
-                    s_sp[pos] = (uint8_t)s;
-                    s_cell[pos] = (uint16_t)lc;
+                for (int64_t k0 = 0; k0 < nf + nb; k0 += blockDim.x) {
+                    const int64_t k = k0 + threadIdx.x;
+                    int64_t slot = 0;
+                    int lc = -1;
+                    if (k < nf + nb) {
+                        slot = slot_of(S, k, nf, nb);
+                        lc = local_cell(S, slot);
+                    }
+                    const bool in = lc >= c0 && lc < c1;
+                    const uint64_t m = __ballot(in);
+                    if (!m) continue;
+                    const int leader = __ffsll((unsigned long long)m) - 1;
+                    uint32_t b0 = 0;
+                    if (lane == leader) b0 = atomicAdd(&s_fill, (uint32_t)__popcll(m));
+                    b0 = __builtin_amdgcn_readlane(b0, leader);
+                    if (in) {
+                        const uint32_t pos = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        const uint32_t id = S.id[par][slot];
+                        const uint32_t key = philox10(make_uint4(id, step, kPurposeBinaryKey, run), seed0, seed1).x;
+                        s_k64[pos] = ((uint64_t)(uint32_t)(lc - c0) << 48) | ((uint64_t)key << 16) | (id & 0xFFFFu);
+                        s_idx[pos] = (uint16_t)pos;
+                        s_slot[pos] = (uint32_t)slot;
+                        s_sp[pos] = (uint8_t)s;
+                    }
                 }
             }
+            // bitonic sort of (key, entry) over the next power of two, padded with the largest key
+            uint32_t P2 = 2;
+            while (P2 < n_in) P2 <<= 1;
             __syncthreads();
-            // order inside each cell by (key, id): rank of every entry
-            for (uint32_t i = threadIdx.x; i < n_in; i += blockDim.x) {
-                const int c = s_cell[i];
-                const uint32_t j0 = s_off[c] - base, j1 = s_off[c + 1] - base;
-                const uint32_t ki = s_key[i], ii = s_id[i];
-                uint32_t rank = 0;
-                for (uint32_t j = j0; j < j1; ++j) {
-                    const uint32_t kj = s_key[j];
-                    rank += (kj < ki || (kj == ki && s_id[j] < ii)) ? 1u : 0u;
+            for (uint32_t i = n_in + threadIdx.x; i < P2; i += blockDim.x) {
+                s_k64[i] = ~0ull;
+                s_idx[i] = (uint16_t)i;
+            }
+            __syncthreads();
+            for (uint32_t kk = 2; kk <= P2; kk <<= 1) {
+                for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) {
+                        const uint32_t l = i ^ j;
+                        if (l > i) {
+                            const uint64_t a = s_k64[i], b = s_k64[l];
+                            const bool up = (i & kk) == 0;
+                            if ((a > b) == up) {
+                                s_k64[i] = b;
+                                s_k64[l] = a;
+                                const uint16_t t = s_idx[i];
+                                s_idx[i] = s_idx[l];
+                                s_idx[l] = t;
+                            }
+                        }
+                    }
+                    __syncthreads();
                 }
-                s_perm[j0 + rank] = (uint16_t)i;
+            }
+            // equal Philox keys in one cell (~2^-32 per pair): the low id bits
+            // ordered them; the full ids decide, put in order by one thread
+            for (uint32_t i = threadIdx.x; i + 1 < n_in; i += blockDim.x)
+                if ((s_k64[i] >> 16) == (s_k64[i + 1] >> 16)) s_tie = 1;
+            __syncthreads();
+            auto id_of = [&](uint32_t e) { return kp->sp[s_sp[e]].id[par][s_slot[e]]; };
+            if (s_tie && threadIdx.x == 0) {
+                for (uint32_t i = 1; i < n_in; ++i)
+                    for (uint32_t j = i; j > 0 && (s_k64[j - 1] >> 16) == (s_k64[j] >> 16) &&
+                                         id_of(s_idx[j - 1]) > id_of(s_idx[j]); --j) {
+                        const uint16_t t = s_idx[j];
+                        s_idx[j] = s_idx[j - 1];
+                        s_idx[j - 1] = t;
+                    }
             }
             // work units per cell: N/2 pairs, or the triple and (N-3)/2 pairs
             if (threadIdx.x == 0) {
@@ -1576,15 +1626,15 @@ __global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
                 if ((N & 1u) && ui == 0) {                       // the triple
                     np = 3;
                     fct = R(0.5);
-                    ea[0] = s_perm[seg]; eb[0] = s_perm[seg + 1];
-                    ea[1] = s_perm[seg + 1]; eb[1] = s_perm[seg + 2];
-                    ea[2] = s_perm[seg + 2]; eb[2] = s_perm[seg];
+                    ea[0] = s_idx[seg]; eb[0] = s_idx[seg + 1];
+                    ea[1] = s_idx[seg + 1]; eb[1] = s_idx[seg + 2];
+                    ea[2] = s_idx[seg + 2]; eb[2] = s_idx[seg];
                 } else {
                     np = 1;
                     fct = R(1);
                     const uint32_t k = (N & 1u) ? 3 + 2 * (ui - 1) : 2 * ui;
-                    ea[0] = s_perm[seg + k];
-                    eb[0] = s_perm[seg + k + 1];
+                    ea[0] = s_idx[seg + k];
+                    eb[0] = s_idx[seg + k + 1];
                 }
                 for (int q = 0; q < np; ++q) {
                     const SpeciesDev &SA = kp->sp[s_sp[ea[q]]];
@@ -1596,7 +1646,7 @@ __global__ __launch_bounds__(256) void k_binary(const KParams *__restrict__ kp)
                         ua[i] = ((const R *)SA.u[par][i])[sa];
                         ub[i] = ((const R *)SB.u[par][i])[sb];
                     }
-                    if (binary_pair<R>(ua, R(SA.m), R(SA.w), s_id[ea[q]], ub, R(SB.m), R(SB.w), fct, step, seed0,
+                    if (binary_pair<R>(ua, R(SA.m), R(SA.w), SA.id[par][sa], ub, R(SB.m), R(SB.w), fct, step, seed0,
                                        seed1, run, cee)) {
                         ++my_pairs;
 #pragma unroll
@@ -2428,7 +2478,7 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, Launcher &L
     L(k_rebin_finalize, dim3(nst), dim3(256), dp);
     if (hp.binary) {
         L.grp = 1;
-        L(k_binary<R, D, T>, dim3(ntiles), dim3(256), dp);
+        L(k_binary<R, D, T>, dim3(ntiles), dim3(kBinThreads), dp);
     }
     L.grp = 3;
     L(k_reduce_j<R, D>, dim3(cb), dim3(256), dp);
