@@ -27,6 +27,12 @@ constexpr int kWin = kMaxTile + 2 * kMargin + 1;   // nodes per axis of a tile's
 constexpr int kFw = kMaxTile + 2 * kMargin + 4;    // nodes per axis of a tile's field window (gathers)
 constexpr int kWinC = kMaxTile + 2 * kMargin;      // cells per axis of a tile's sort bins
 
+// Deposit planes hold 64-bit fixed point: kDepScale units per unit
+// (integer sums are exact in any order; see the particle kernel).
+using Fix = long long;
+constexpr double kDepScale = 562949953421312.0;   // 2^49
+constexpr double kDepUnit = 1.0 / kDepScale;
+
 struct State {
     int64_t step;        // time level n of the next step
     int32_t cur;         // particle set in use (the cell sort alternates 0/1)
@@ -51,7 +57,7 @@ struct Params {
     double *psi;                   // plasma canonical momentum beta_pz - a
     double *it[2];                 // solve result (it[(iters-1) & 1] holds a^n after the solve)
     double *rhsR, *rhsC;           // per step: J - Y + n_p psi, and n_p + X - c0 (the sweeps' coefficients)
-    double *dep[2][4];             // deposit sets: n_b, J at a*, chi, chi a*
+    Fix *dep[2][4];                // deposit sets (fixed point): n_b, J at a*, chi, chi a*
     double2 *W;                    // complex FFT plane [ny][nx]
     double2 *twx, *twy;            // exp(-2 pi i t / n), t < n/2
     double *lapx, *lapy;           // (4/d^2) sin^2(pi k / n)

@@ -160,10 +160,23 @@ __device__ __forceinline__ int sort_key(int i, int j, const Params &P)
     return (tile << (2 * lt)) + ((j & m) << lt) + (i & m);
 }
 
+// The deposit is accumulated in 64-bit fixed point (kDepScale units per
+// unit of density or current): each particle's terms are rounded once, and
+// every later sum -- in registers, across lanes, in LDS and in the grid --
+// is an integer sum, exact in any order.  The deposit, and with it the whole
+// run, therefore does not depend on the order in which particles are stored
+// or atomics land.  |node value| < 2^15 (far above any density or current of
+// this model), rounding 2^-49 per term.
+__device__ __forceinline__ Fix to_fix(double v) { return (Fix)llrint(v * kDepScale); }
+__device__ __forceinline__ void fix_add(Fix *p, Fix v)
+{
+    if (v != 0) atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
 // Adds the four quantities acc[k][n] of one cell's run of particles (node n
 // of cell (i0, j0)) into the tile's LDS window when the cell lies inside it,
 // else straight into the global deposit.
-__device__ __forceinline__ void flush_run(double (*win)[kWin * kWin], double *const *dst, const double acc[4][4],
+__device__ __forceinline__ void flush_run(Fix (*win)[kWin * kWin], Fix *const *dst, const Fix acc[4][4],
                                           int i0, int j0, int wx0, int wy0, const Params &P)
 {
     const int di = wrapi(i0 - wx0, P.nx), dj = wrapi(j0 - wy0, P.ny);
@@ -171,10 +184,10 @@ __device__ __forceinline__ void flush_run(double (*win)[kWin * kWin], double *co
         const int e = dj * kWin + di;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            atomicAdd(&win[k][e], acc[k][0]);
-            atomicAdd(&win[k][e + 1], acc[k][1]);
-            atomicAdd(&win[k][e + kWin], acc[k][2]);
-            atomicAdd(&win[k][e + kWin + 1], acc[k][3]);
+            fix_add(&win[k][e], acc[k][0]);
+            fix_add(&win[k][e + 1], acc[k][1]);
+            fix_add(&win[k][e + kWin], acc[k][2]);
+            fix_add(&win[k][e + kWin + 1], acc[k][3]);
         }
     } else {
         const int i1 = wrapi(i0 + 1, P.nx), j1 = wrapi(j0 + 1, P.ny);
@@ -182,7 +195,7 @@ __device__ __forceinline__ void flush_run(double (*win)[kWin * kWin], double *co
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) unsafeAtomicAdd(dst[k] + off[n], acc[k][n]);
+            for (int n = 0; n < 4; ++n) fix_add(dst[k] + off[n], acc[k][n]);
     }
 }
 
@@ -201,21 +214,21 @@ __device__ __forceinline__ int dpp_int(int v, int old)
 }
 
 template <int CTRL, int ROWS>
-__device__ __forceinline__ void scan_step(double v[16], int sid)
+__device__ __forceinline__ void scan_step(Fix v[16], int sid)
 {
     const bool same = dpp_int<CTRL, ROWS>(sid, -1) == sid;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const long long b = __double_as_longlong(v[k]);
+        const long long b = v[k];
         const int lo = dpp_int<CTRL, ROWS>((int)(b & 0xffffffffll), 0);
         const int hi = dpp_int<CTRL, ROWS>((int)(b >> 32), 0);
-        const double o = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        const Fix o = ((long long)hi << 32) | (unsigned int)lo;
         if (same) v[k] += o;
         __builtin_amdgcn_sched_barrier(0);     // keep the moves of one value at a time live
     }
 }
 
-__device__ __forceinline__ bool segment_sums(double v[16], int key)
+__device__ __forceinline__ bool segment_sums(Fix v[16], int key)
 {
     constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
     const int lane = threadIdx.x & 63;
@@ -364,7 +377,7 @@ constexpr int kRun = 2;
 template <int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_particle(const Params *__restrict__ pp)
 {
-    __shared__ double win[4][kWin * kWin];
+    __shared__ Fix win[4][kWin * kWin];
     __shared__ double fw[3][kFw * kFw];        // a^n, a* = 2 a^n - a^(n-1), psi on the field window
     const Params &P = *pp;
     const int64_t step = P.state->step;
@@ -373,13 +386,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const int nx = P.nx, ny = P.ny;
     const double *an = MODE == 0 ? P.it[(P.iters - 1) & 1] : P.a1;   // a^n
     const double *aold = MODE == 0 ? P.a1 : P.a2;                     // a^(n-1)
-    double *const *dst = MODE == 0 ? P.dep[1 - (int)(step & 1)] : P.dep[0];
+    Fix *const *dst = MODE == 0 ? P.dep[1 - (int)(step & 1)] : P.dep[0];
     double *X = P.x[cur], *Y = P.y[cur], *UX = P.ux[cur], *UY = P.uy[cur], *PZ = P.pz[cur];
     const int b = blockIdx.x;
     const int tx0 = (b % P.tiles_x) << P.ltile, ty0 = (b / P.tiles_x) << P.ltile;
     const int wx0 = tx0 - kMargin, wy0 = ty0 - kMargin;               // deposit window origin
     const int fx0 = tx0 - kMargin - 1, fy0 = ty0 - kMargin - 1;       // field window origin
-    for (int e = threadIdx.x; e < 4 * kWin * kWin; e += kThreads) (&win[0][0])[e] = 0.0;
+    for (int e = threadIdx.x; e < 4 * kWin * kWin; e += kThreads) (&win[0][0])[e] = 0;
     if (MODE != 1) {
         for (int e = threadIdx.x; e < kFw * kFw; e += kThreads) {
             const int node = wrapi(fy0 + e / kFw, ny) * nx + wrapi(fx0 + e % kFw, nx);
@@ -394,10 +407,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const int s0 = P.tile_start[cur][b], s1 = P.tile_start[cur][b + 1];
     double dacc[kPDiag] = {0.0, 0.0, 0.0};
     for (int base = s0; base < s1; base += kThreads * kRun) {
-        double v[16];
+        Fix v[16];
         int key = -1, ci0 = 0, cj0 = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = 0.0;
+        for (int k = 0; k < 16; ++k) v[k] = 0;
         // the next particle's loads are issued before the current one is
         // processed, so they overlap its arithmetic
         const int i0 = base + (int)threadIdx.x * kRun;
@@ -441,26 +454,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
             if (MODE == 2) PZ[idx] = pz;
             const int k2 = c.j0 * nx + c.i0;
             if (k2 != key) {
-                if (key >= 0) flush_run(win, dst, (const double(*)[4])v, ci0, cj0, wx0, wy0, P);
+                if (key >= 0) flush_run(win, dst, (const Fix(*)[4])v, ci0, cj0, wx0, wy0, P);
                 key = k2;
                 ci0 = c.i0;
                 cj0 = c.j0;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) v[k] = 0.0;
+                for (int k = 0; k < 16; ++k) v[k] = 0;
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] += vv[k];
+            for (int k = 0; k < 16; ++k) v[k] += to_fix(vv[k]);
         }
-        if (segment_sums(v, key) && key >= 0) flush_run(win, dst, (const double(*)[4])v, ci0, cj0, wx0, wy0, P);
+        if (segment_sums(v, key) && key >= 0) flush_run(win, dst, (const Fix(*)[4])v, ci0, cj0, wx0, wy0, P);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kWin * kWin; e += kThreads) {
         const int node = wrapi(wy0 + e / kWin, ny) * nx + wrapi(wx0 + e % kWin, nx);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double val = win[k][e];
-            if (val != 0.0) unsafeAtomicAdd(dst[k] + node, val);
-        }
+        for (int k = 0; k < 4; ++k) fix_add(dst[k] + node, win[k][e]);
     }
     if (diag) block_sums<kPDiag>(dacc, P.pdiag + (size_t)b * kPDiag);
 }
@@ -548,13 +558,13 @@ __global__ __launch_bounds__(kThreads) void k_rows_first(const Params *__restric
     const Params &P = *pp;
     const int j = blockIdx.x, nx = P.nx;
     const int p = (int)(P.state->step & 1);
-    const double *nb = P.dep[p][0], *J = P.dep[p][1], *Xc = P.dep[p][2], *Yc = P.dep[p][3];
+    const Fix *nb = P.dep[p][0], *J = P.dep[p][1], *Xc = P.dep[p][2], *Yc = P.dep[p][3];
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
         const int64_t o = (int64_t)j * nx + i;
         const double ap = 2.0 * P.a1[o] - P.a2[o];
-        const double n_p = fmax(P.n0 - nb[o], 0.0);
-        const double c = n_p + Xc[o];
-        const double R = J[o] - Yc[o] + n_p * P.psi[o];
+        const double n_p = fmax(P.n0 - (double)nb[o] * kDepUnit, 0.0);
+        const double c = n_p + (double)Xc[o] * kDepUnit;
+        const double R = (double)J[o] * kDepUnit - (double)Yc[o] * kDepUnit + n_p * P.psi[o];
         const double C = c - P.c0;
         P.rhsR[o] = R;
         P.rhsC[o] = C;
@@ -674,7 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_nodes(const Params *__restrict__ p
         P.a2[o] = a_old;
         P.a1[o] = a;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) P.dep[p][k][o] = 0.0;
+        for (int k = 0; k < 4; ++k) P.dep[p][k][o] = 0;
         P.cell_count[o] = 0;
     }
     if (diag) block_sums<kGDiag>(acc, P.gdiag + (size_t)blockIdx.x * kGDiag);
@@ -689,7 +699,7 @@ __global__ __launch_bounds__(kThreads) void k_init_nodes(const Params *__restric
         P.a1[o] = an[o];
         P.a2[o] = an[o];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) P.dep[0][k][o] = 0.0;
+        for (int k = 0; k < 4; ++k) P.dep[0][k][o] = 0;
     }
 }
 

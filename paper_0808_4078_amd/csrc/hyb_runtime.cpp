@@ -270,7 +270,7 @@ int pic_hyb_init(const pic_hyb_desc *desc, void *particles, size_t particle_byte
     P.rhsR = at<double>(grid, L.rhsR);
     P.rhsC = at<double>(grid, L.rhsC);
     for (int s = 0; s < 2; ++s)
-        for (int k = 0; k < 4; ++k) P.dep[s][k] = at<double>(grid, L.dep[s][k]);
+        for (int k = 0; k < 4; ++k) P.dep[s][k] = at<Fix>(grid, L.dep[s][k]);
     P.W = at<double2>(grid, L.W);
     P.twx = at<double2>(grid, L.twx);
     P.twy = at<double2>(grid, L.twy);
