@@ -191,8 +191,24 @@ COULOMB_VREF = 0.1
 BINARY_NU, BINARY_VREF = 0.05, 0.1
 
 
+def tune_shape(wl, tile: int, reserve: float, nsteps: int = 10):
+    """pic_tune_shape on the workload itself (mixed precision, one run):
+    the particle kernel's launch shape that steps it fastest."""
+    from paper_0808_4078_amd import pic
+
+    g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=tile, reserve=reserve)
+    t0 = time.time()
+    best, ms = pic.tune_shape(g, sp, nsteps=nsteps)
+    progress(f"{wl.name}: launch shape {best} {pic.SHAPES[best]} (threads, in flight) in {time.time() - t0:.1f} s; "
+             + ", ".join(f"{k} {pic.SHAPES[k]}: {v:.3f}" for k, v in ms.items()) + " ms/step")
+    return best, {"best": best, "threads_per_workgroup": pic.SHAPES[best][0],
+                  "particles_in_flight": pic.SHAPES[best][1], "nsteps": nsteps,
+                  "ms_per_step": {f"{k}: {pic.SHAPES[k][0]}x{pic.SHAPES[k][1]}": v for k, v in ms.items()},
+                  "gain_over_default": ms[0] / ms[best] - 1.0}
+
+
 def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, profile: bool = True,
-            reserve: float = 0.0):
+            reserve: float = 0.0, shape: int = 0):
     """Two fresh runs of the same workload.  Timed run: `warmup` untimed
     steps, then exactly `steps` steps as enqueued by pic_step (one captured
     graph replay per step), bracketed by device synchronisations and HIP
@@ -204,7 +220,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     from paper_0808_4078_amd import pic
 
     prec = pic.PIC_PREC_MIXED if precision == "mixed" else pic.PIC_PREC_FP64
-    g, sp = pic.workload_descs(wl, precision=prec, tile=tile, diag_every=diag_every, reserve=reserve)
+    g, sp = pic.workload_descs(wl, precision=prec, tile=tile, diag_every=diag_every, reserve=reserve, shape=shape)
     t0 = time.time()
     run = pic.Run(g, sp)
     run.sync()
@@ -225,6 +241,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: 
     # every timed (and warm-up) step was one replay of the captured graph
     if not (info["graph"] == 1 and info["graph_launches"] == warmup + steps and info["direct_steps"] == 0):
         raise RuntimeError(f"{wl.name}: steps were not graph replays: {info}")
+    if info["shape"] != shape:
+        raise RuntimeError(f"{wl.name}: ran in launch shape {info['shape']}, asked for {shape}")
     diag = run.diagnostics() if diag_every else None
     device_bytes = run.device_bytes
     run.close()
@@ -267,12 +285,12 @@ def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
 
     members = synth.c5_members()
     t0 = time.time()
-    tiles, report = autotune.choose_tiles(members, precision=pic.PIC_PREC_MIXED, nsteps=5, log=progress)
+    tiles, shapes, report = autotune.choose_launch(members, precision=pic.PIC_PREC_MIXED, nsteps=5, log=progress)
     tune_s = time.time() - t0
     t0 = time.time()
     runs = []
-    for i, (wl, t) in enumerate(zip(members, tiles)):
-        g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=t, diag_every=diag_every)
+    for i, (wl, t, sh) in enumerate(zip(members, tiles, shapes)):
+        g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=t, diag_every=diag_every, shape=sh)
         runs.append(pic.Run(g, sp))
     batch = pic.Batch(runs)
     init_s = time.time() - t0
@@ -308,9 +326,14 @@ def run_c5(steps: int, warmup: int, diag_every: int, prof_steps: int = 5):
             "runs": len(members), "particles": n, "steps": steps,
             "value": n * steps / (ms * 1e-3), "unit": "particle-steps/s", "ms_per_step": ms / steps,
             "tiles": {str(e): tiles.count(e) for e in (8, 16, 32)},
-            "autotune": {k: {"tile": v["tile"], "ms": v.get("ms"), "members": v["members"]}
-                         for k, v in report.items()},
+            "shapes_per_edge": {e: {"shape": sh, "threads_per_workgroup": pic.SHAPES[sh][0],
+                                    "particles_in_flight": pic.SHAPES[sh][1]}
+                                for e, sh in report["_edges"].items()},
+            "autotune": {k: {"tile": v["tile"], "ms": v.get("ms"), "shape": v["shape"], "shape_ms": v["shape_ms"],
+                             "members": v["members"]}
+                         for k, v in report.items() if not k.startswith("_")},
             "persistent_blocks": info["persistent_blocks"], "work_items": info["items"],
+            "batch_shapes": info["shapes"],
             "graph_replays": li["graph_launches"],
             "step_breakdown_ms": {k: v / prof_steps for k, v in groups.items()},
             "relayouts_total": rebins, "tune_s": tune_s, "init_s": init_s}
@@ -416,6 +439,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--shape", type=int, default=-1,
+                    help="particle-kernel launch shape 0..4 for the mixed runs (-1: chosen by pic_tune_shape)")
     ap.add_argument("--diag-every", type=int, default=10)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -442,11 +467,16 @@ def main():
         return
     import synth
     from dataclasses import replace
+    from paper_0808_4078_amd.pic import SHAPES
 
     wl = synth.C3
     if a.quick:
         wl = replace(wl, n=(256, 256), name="C3-quick-256^2")
-    mixed = run_gpu(wl, "mixed", a.steps, a.warmup, a.tile, a.diag_every, reserve=RESERVE_2D)
+    if a.shape >= 0:
+        shape, shape_tuning = a.shape, None
+    else:
+        shape, shape_tuning = tune_shape(wl, a.tile, RESERVE_2D)
+    mixed = run_gpu(wl, "mixed", a.steps, a.warmup, a.tile, a.diag_every, reserve=RESERVE_2D, shape=shape)
     fp64 = None if a.skip_fp64 else run_gpu(replace(wl, name="C2"), "fp64", a.steps, a.warmup, a.tile,
                                             a.diag_every, reserve=RESERVE_2D)
     n = mixed["particles"]
@@ -476,6 +506,9 @@ def main():
             "precision": "mixed: int32 cell + FP32 offset/momentum/push/tile current; FP64 grid current "
                          "reduction and diagnostics",
             "tile": a.tile,
+            "particle_kernel_shape": {"shape": shape, "threads_per_workgroup": SHAPES[shape][0],
+                                      "particles_in_flight": SHAPES[shape][1],
+                                      "chosen_by": "pic_tune_shape" if shape_tuning else "--shape"},
             "store_reserve": RESERVE_2D,
             "diag_every": a.diag_every,
             "parallelism": "single GPU",
@@ -486,6 +519,7 @@ def main():
                             "kernel_count_bytes": pk_bytes,
                             "kernel_count_GBs": pk_bytes / (pk_ms * 1e-3) / 1e9,
                             "kernel_count_frac": pk_bytes / (pk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "launch_tuning": shape_tuning,
         "graph_replays": mixed["graph_replays"],
         "step_breakdown_ms": {k: v / a.steps for k, v in mixed["groups_ms"].items()},
         "relayouts": mixed["diag"]["rebins"],
@@ -503,7 +537,11 @@ def main():
                        "step_breakdown_ms": {k: v / a.steps for k, v in fp64["groups_ms"].items()}}
         rec["mixed_over_fp64"] = rec["value"] / rec["fp64"]["value"]
     if a.c4 > 0:
-        c4 = run_gpu(synth.C4, "mixed", a.c4, min(a.warmup, 5), 8, a.diag_every, reserve=RESERVE_3D)
+        if a.shape >= 0:
+            c4_shape, c4_tuning = a.shape, None
+        else:
+            c4_shape, c4_tuning = tune_shape(synth.C4, 8, RESERVE_3D, nsteps=6)
+        c4 = run_gpu(synth.C4, "mixed", a.c4, min(a.warmup, 5), 8, a.diag_every, reserve=RESERVE_3D, shape=c4_shape)
         c4_pk = c4["groups_ms"]["particle"] / a.c4
         c4_bytes = particle_kernel_bytes(synth.C4, "mixed", 8)
         rec["c4"] = {"workload": "C4: 3D3V periodic 256x256x512, dx=0.2, dt=0.1, 8 ppc per species, beam "
@@ -512,12 +550,16 @@ def main():
                      "value": c4["particles"] / (c4["ms"] / a.c4 * 1e-3),
                      "ms_per_step": c4["ms"] / a.c4, "particle_kernel_ms": c4_pk,
                      "particle_kernel_GBs": c4_bytes / (c4_pk * 1e-3) / 1e9,
+                     "particle_kernel_shape": {"shape": c4_shape, "threads_per_workgroup": SHAPES[c4_shape][0],
+                                               "particles_in_flight": SHAPES[c4_shape][1]},
+                     "launch_tuning": c4_tuning,
                      "step_breakdown_ms": {k: v / a.c4 for k, v in c4["groups_ms"].items()}}
     if a.coulomb > 0:
         sp0, sp1 = wl.species
         wc = replace(wl, name=f"{wl.name}-coulomb",
                      species=(sp0, replace(sp1, coll_model=1, coll_vref=COULOMB_VREF)))
-        cm = run_gpu(wc, "mixed", a.coulomb, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D)
+        cm = run_gpu(wc, "mixed", a.coulomb, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D,
+                     shape=shape)
         cm_pk = cm["groups_ms"]["particle"] / a.coulomb
         rec["coulomb"] = {"workload": f"{wl.name} with the return-current plasma on the Coulomb small-angle "
                                       f"model (nu=0.05 at v={COULOMB_VREF}c, every plasma particle turned every "
@@ -530,7 +572,8 @@ def main():
     if a.binary > 0:
         wb = replace(wl, name=f"{wl.name}-binary", nu_ee=BINARY_NU, ee_vref=BINARY_VREF,
                      species=tuple(replace(sc, binary=True) for sc in wl.species))
-        bm = run_gpu(wb, "mixed", a.binary, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D)
+        bm = run_gpu(wb, "mixed", a.binary, min(a.warmup, 5), a.tile, a.diag_every, reserve=RESERVE_2D,
+                     shape=shape)
         rec["binary"] = {"workload": f"{wl.name} with binary electron-electron collisions among all particles "
                                      f"(beam-plasma and plasma-plasma pairs in every cell, nu_ee={BINARY_NU} at "
                                      f"relative speed {BINARY_VREF}c), mixed precision",

@@ -73,6 +73,15 @@ enum {
 
 #define PIC_MAX_SPECIES 8
 
+/* Launch shapes of the particle kernel (pic_grid_desc.shape): threads per
+ * workgroup / particles each lane keeps in flight (the loads of the next
+ * ones issued before the current one is processed).
+ *   0: 256 / 2 (default; the only shape of FP64 runs)   1: 256 / 1
+ *   2: 256 / 3   3: 512 / 2   4: 128 / 2
+ * The shape changes how the work is spread over the device, never the
+ * arithmetic; pic_tune_shape times them. */
+#define PIC_PARTICLE_SHAPES 5
+
 /* Grid and run parameters.
  *   ndim      2 (2D3V: x,y resolved, z ignorable -- the paper's transverse plane)
  *             or 3 (3D3V).
@@ -119,7 +128,10 @@ enum {
  *             Yonemura 1998).  nu_ee = 0: off.  With nu_ee > 0, ee_vref must
  *             be in (0, 1) and the participants need ids (they are tracked).
  *             Limit: 4096 participants in one cell (PIC_E_CAPACITY beyond);
- *             not available in ensembles. */
+ *             not available in ensembles.
+ *   shape     particle-kernel launch shape, 0..PIC_PARTICLE_SHAPES-1 (0 for
+ *             FP64 runs).  A launch choice, not part of the run's state:
+ *             pic_restore accepts a checkpoint taken with another shape. */
 typedef struct {
     int32_t ndim;
     int32_t n[3];
@@ -134,6 +146,7 @@ typedef struct {
     double reserve;
     double nu_ee;
     double ee_vref;
+    int32_t shape;
 } pic_grid_desc;
 
 /* One particle species.
@@ -284,7 +297,10 @@ int pic_sync(pic_run *run);
  *   graph_launches  steps enqueued as one graph replay.
  *   direct_steps    steps enqueued kernel by kernel (including the
  *                   measurement path pic_step_profiled).
- *   scratch_bytes   scratch the run uses (pic_query's scratch_bytes). */
+ *   scratch_bytes   scratch the run uses (pic_query's scratch_bytes).
+ *   shape, block_threads, inflight  the particle kernel's launch shape and
+ *                   its threads per workgroup and particles in flight per
+ *                   lane. */
 typedef struct {
     int32_t graph;
     int32_t static_scratch;
@@ -292,6 +308,9 @@ typedef struct {
     int64_t graph_launches;
     int64_t direct_steps;
     size_t scratch_bytes;
+    int32_t shape;
+    int32_t block_threads;
+    int32_t inflight;
 } pic_run_info;
 
 /* Host only.  Fills *out for the run.  Errors: INVALID_ARG (NULL). */
@@ -427,11 +446,15 @@ int pic_batch_sync(pic_batch *batch);
 int pic_batch_diagnostics(pic_batch *batch, int run, pic_diag *out);
 
 /* Host only.  For tile edges 8, 16, 32 (index 0..2): the particle kernel's
- * workgroups and work items (0 where no member uses the edge). */
-int pic_batch_info(pic_batch *batch, int32_t persistent_blocks[3], int32_t items[3]);
+ * workgroups, work items (0 where no member uses the edge) and launch shape
+ * (-1 where no member uses the edge).  The members of one edge share one
+ * particle kernel, so pic_batch_init refuses members of one edge with
+ * different shapes (PIC_E_INVALID_ARG).  Any pointer may be NULL. */
+int pic_batch_info(pic_batch *batch, int32_t persistent_blocks[3], int32_t items[3], int32_t shapes[3]);
 
 /* Host only.  How the batch enqueues its steps (pic_run_info; the fields
- * static_scratch and scratch_bytes are 0). */
+ * static_scratch, scratch_bytes and the shape fields are 0: the shapes are
+ * per tile edge, see pic_batch_info). */
 int pic_batch_launch_info(pic_batch *batch, pic_run_info *out);
 
 /* Waits for the stream, releases the members and frees the host state. */
@@ -448,15 +471,24 @@ int pic_batch_destroy(pic_batch *batch);
  * a member of a large ensemble) -- and returns the fastest edge in
  * *best_tile and each candidate's milliseconds per step in ms[3] (edge 8,
  * 16, 32; -1 where not tried).  grid->tile and PIC_FLAG_HOST_LOAD are
- * ignored.  Synchronising, on `hip_stream`; the workspace may be reused once
- * it returns.  pic_tune_query (host only) gives the workspace size.  Errors:
- * INVALID_ARG (copies out of 1..4096, no edge divides the grid, nsteps < 1),
- * BUFFER_TOO_SMALL, and those of pic_init. */
+ * ignored; every candidate runs in grid->shape.  Synchronising, on
+ * `hip_stream`; the workspace may be reused once it returns.
+ * pic_tune_query (host only) gives the workspace size, which also serves
+ * pic_tune_shape.  Errors: INVALID_ARG (copies out of 1..4096, no edge
+ * divides the grid, nsteps < 1), BUFFER_TOO_SMALL, and those of pic_init. */
 int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
                    int32_t copies, size_t *workspace_bytes);
 int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
              int32_t copies, void *workspace, size_t workspace_bytes, void *hip_stream,
              int32_t nsteps, int32_t *best_tile, double ms[3]);
+/* The same measurement over the particle kernel's launch shapes at the
+ * grid's tile edge (grid->tile, 0 = library default): ms[s] for shape s
+ * (-1 where not tried: FP64 runs try shape 0 only), the fastest in
+ * *best_shape.  grid->shape is ignored.  Errors as pic_tune, and
+ * INVALID_ARG when the tile edge does not divide the grid. */
+int pic_tune_shape(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies,
+                   int32_t copies, void *workspace, size_t workspace_bytes, void *hip_stream,
+                   int32_t nsteps, int32_t *best_shape, double ms[PIC_PARTICLE_SHAPES]);
 
 /* ---- The reduced quasi-neutral model ---------------------------------------
  * The paper's own model of the filamenting beam (the theory part, Eqs. 1-7):

@@ -1,4 +1,4 @@
-"""Tile-edge choice for ensembles of runs.
+"""Tile-edge and launch-shape choice for ensembles of runs.
 
 The tile edge fixes the particles one workgroup of the particle kernel owns
 (ppc * edge^ndim) and its LDS footprint; the best edge depends on the grid
@@ -13,6 +13,13 @@ count, so what decides is the cost per particle at saturation, not the
 latency of a member alone (alone, a small grid prefers small tiles only
 because they give more workgroups).  The representative is therefore timed
 as a batch of enough copies to hold about SATURATION particles.
+
+``choose_launch`` adds the particle kernel's launch shape (threads per
+workgroup and particles in flight per lane, ``pic.SHAPES``): each class's
+representative is timed in every shape at its chosen edge
+(``pic_tune_shape``), and since the members of one tile edge share one
+particle kernel in a batch, each edge takes the shape that wins for the
+most members at that edge.
 """
 from __future__ import annotations
 
@@ -104,3 +111,49 @@ def choose_tiles(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cach
         for i in idx:
             tiles[i] = int(report[key]["tile"])
     return tiles, report
+
+
+def choose_launch(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cache_path=DEFAULT_CACHE,
+                  log=None, saturate: bool = True):
+    """Tile edge and launch shape for every workload.  Returns (tiles,
+    shapes, report): report as choose_tiles, each class entry also holding
+    "shape" (its own fastest), "shape_ms" and "shape_cached", and
+    report["_edges"] mapping each edge in use to the shape applied to it."""
+    tiles, report = choose_tiles(workloads, precision, nsteps, cache_path, log, saturate)
+    cache = _read(cache_path)
+    classes = {}
+    for i, wl in enumerate(workloads):
+        classes.setdefault(class_key(wl, precision, saturate), []).append(i)
+    dirty = False
+    for key, idx in sorted(classes.items()):
+        ent = report[key]
+        skey = f"{key}-t{ent['tile']}-shape"
+        if skey in cache and "shape" in cache[skey]:
+            ent["shape"] = int(cache[skey]["shape"])
+            ent["shape_ms"] = dict(cache[skey]["ms"])
+            ent["shape_cached"] = True
+            continue
+        rep = ent["representative"]
+        g, sp = pic.workload_descs(workloads[rep], precision=precision, tile=int(ent["tile"]))
+        copies = copies_for(workloads[rep], saturate)
+        best, ms = pic.tune_shape(g, sp, nsteps=nsteps, copies=copies)
+        ent["shape"] = best
+        ent["shape_ms"] = {str(k): v for k, v in ms.items()}
+        ent["shape_cached"] = False
+        cache[skey] = {"shape": best, "ms": ent["shape_ms"]}
+        dirty = True
+        if log:
+            log(f"autotune {key}: shape {best} {pic.SHAPES[best]} at tile {ent['tile']} "
+                f"({', '.join(f'{k}: {v:.3f} ms' for k, v in ms.items())})")
+    if dirty:
+        _write(cache_path, cache)
+    # one shape per edge: the one whose classes hold the most members
+    votes = {}
+    for key, idx in classes.items():
+        e = report[key]
+        votes.setdefault(int(e["tile"]), {}).setdefault(int(e["shape"]), 0)
+        votes[int(e["tile"])][int(e["shape"])] += len(idx)
+    edge_shape = {t: max(sorted(v), key=lambda k: v[k]) for t, v in votes.items()}
+    report["_edges"] = {str(t): sh for t, sh in sorted(edge_shape.items())}
+    shapes = [edge_shape[t] for t in tiles]
+    return tiles, shapes, report

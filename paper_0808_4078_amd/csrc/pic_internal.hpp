@@ -15,7 +15,14 @@
 namespace pic {
 
 constexpr int kMaxSpecies = PIC_MAX_SPECIES;
-constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
+// Launch shapes of the particle kernel: threads per workgroup and the
+// particles each lane keeps in flight (their loads issued ahead of the one it
+// processes).  Shape 0 is the default and the only one of the FP64 kernels;
+// mixed-precision runs take any (pic_grid_desc.shape, chosen by the tuner).
+constexpr int kShapes = PIC_PARTICLE_SHAPES;
+constexpr int kShapeBlock[kShapes] = {256, 256, 256, 512, 128};
+constexpr int kShapeInflight[kShapes] = {2, 1, 3, 2, 2};
+constexpr int kBlock = kShapeBlock[0];
 constexpr int kRing = 4096;          // diagnostic records kept on the device
 constexpr int kTileDiag = 6;         // per tile and species: KE, px, py, pz, count, collisions
 constexpr int kFieldDiag = 10;       // per block: W[6], p_field[3], unused
@@ -119,6 +126,7 @@ struct KParams {
     uint8_t *tile_bucket;   // [tiles] load bucket of each tile, written by the particle kernel
     double order_scale;  // bucket = round(particles in the tile * order_scale): 16 per nominal load
     int32_t coulomb;     // 1 if a species scatters with the Coulomb model (selects the particle kernel)
+    int32_t shape;       // particle-kernel launch shape (index into kShapeBlock / kShapeInflight)
     double nu_ee;        // binary collisions: rate at relative speed ee_vref (0 = off)
     double ee_vref;
     int32_t binary;      // 1 if the binary-collision kernel runs (nu_ee > 0 and a species takes part)
@@ -145,6 +153,7 @@ struct BatchGroup {
     int cls_start[kBatchXcds];     // first item of each class
     int cls_len[kBatchXcds];       // items of each class
     int *queue;                    // [kBatchXcds] work counters of the persistent particle kernel
+    int shape;                     // particle-kernel launch shape of the runs with this edge
 };
 constexpr int kBatchGroups = 3;
 struct BatchTable {
@@ -184,7 +193,7 @@ hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, cons
                              const int pblocks[kBatchGroups], hipStream_t s, hipEvent_t *ev = nullptr);
 // Workgroups of the batch particle kernel of tile group g that fit on one
 // compute unit at once.
-hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool coulomb, int *blocks_per_cu);
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool coulomb, int shape, int *blocks_per_cu);
 // Initialisation shared by pic_init (static_device = -1, the caller's
 // scratch) and pic_init_static_scratch (the library's scratch of that
 // device, already claimed; pic_destroy releases it).

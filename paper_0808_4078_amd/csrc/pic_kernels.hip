@@ -488,16 +488,17 @@ constexpr int kXcds = kBatchXcds;        // accelerator dies (XCDs), each with i
 template <typename R, int D>
 constexpr int kMoverStage = sizeof(R) == 4 ? (D == 3 ? 24 : 64) : 1;
 
-constexpr int kBatch = 2;   // particles each lane keeps in flight ahead of the one it processes
-
 // KP: pointer to the run's parameters -- the kernel argument, or (batched
 // runs) a constant-address-space pointer, which lets the parameter loads be
 // scalar loads (the parameter blocks are never written by a kernel).
 // CB: the kernel carries the Coulomb scattering branch (runs with a species on
 // that model); without it the branch and its registers are compiled out.
-template <typename R, typename A, int D, int T, bool CB, typename KP>
+// SH: launch shape (kBlock threads, kBatch particles in flight per lane).
+template <typename R, typename A, int D, int T, bool CB, int SH, typename KP>
 __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
 {
+    constexpr int kBlock = kShapeBlock[SH];
+    constexpr int kBatch = kShapeInflight[SH];
     constexpr int NF = T + 2;
     constexpr int NJ = T + 3;
     constexpr int NF_D = D == 3 ? NF * NF * NF : NF * NF;
@@ -2178,11 +2179,11 @@ typedef __attribute__((address_space(4))) const KParams KParamsC;
 
 // One workgroup per tile; workgroup b takes tile order[b] (see the work
 // order built at the end of each step).
-template <typename R, typename A, int D, int T, bool CB>
-__global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__ kp)
+template <typename R, typename A, int D, int T, bool CB, int SH>
+__global__ __launch_bounds__(kShapeBlock[SH]) void k_particle(const KParams *__restrict__ kp)
 {
     const KParamsC *kc = (const KParamsC *)kp;
-    particle_body<R, A, D, T, CB>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
+    particle_body<R, A, D, T, CB, SH>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
 }
 
 // Persistent: workgroup w (on XCD w mod 8) takes the items of its XCD
@@ -2190,8 +2191,8 @@ __global__ __launch_bounds__(kBlock) void k_particle(const KParams *__restrict__
 // in a run stepped alone -- and, when its class is exhausted, the remaining
 // items of the other classes.  The counters only grow, so every workgroup
 // reaches the exit.
-template <typename R, typename A, int D, int T, bool CB>
-__global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restrict__ bt)
+template <typename R, typename A, int D, int T, bool CB, int SH>
+__global__ __launch_bounds__(kShapeBlock[SH]) void kb_particle(const BatchTable *__restrict__ bt)
 {
     constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
     __shared__ int s_item;
@@ -2209,7 +2210,7 @@ __global__ __launch_bounds__(kBlock) void kb_particle(const BatchTable *__restri
             if (i >= len) break;
             const int2 it = items[i];
             const KParamsC *kp = (const KParamsC *)wave_uniform_ptr(bt->kp[wave_uniform(it.x)]);
-            particle_body<R, A, D, T, CB>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
+            particle_body<R, A, D, T, CB, SH>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
         }
     }
 }
@@ -2447,6 +2448,45 @@ struct Launcher {
     }
 };
 
+// The particle kernel of a run or batch group in launch shape `shape` (FP64
+// kernels exist in shape 0 only; the runtime refuses others).
+template <typename R, typename A, int D, int T, bool CB>
+static auto particle_kernel(int shape)
+{
+    using F = void (*)(const KParams *);
+    F f = k_particle<R, A, D, T, CB, 0>;
+    if constexpr (sizeof(R) == 4) {
+        switch (shape) {
+        case 1: f = k_particle<R, A, D, T, CB, 1>; break;
+        case 2: f = k_particle<R, A, D, T, CB, 2>; break;
+        case 3: f = k_particle<R, A, D, T, CB, 3>; break;
+        case 4: f = k_particle<R, A, D, T, CB, 4>; break;
+        default: break;
+        }
+    }
+    return f;
+}
+template <typename R, typename A, int D, int T, bool CB>
+static auto batch_particle_kernel(int shape)
+{
+    using F = void (*)(const BatchTable *);
+    F f = kb_particle<R, A, D, T, CB, 0>;
+    if constexpr (sizeof(R) == 4) {
+        switch (shape) {
+        case 1: f = kb_particle<R, A, D, T, CB, 1>; break;
+        case 2: f = kb_particle<R, A, D, T, CB, 2>; break;
+        case 3: f = kb_particle<R, A, D, T, CB, 3>; break;
+        case 4: f = kb_particle<R, A, D, T, CB, 4>; break;
+        default: break;
+        }
+    }
+    return f;
+}
+static int shape_block(int precision_is_mixed, int shape)
+{
+    return precision_is_mixed && shape > 0 && shape < kShapes ? kShapeBlock[shape] : kShapeBlock[0];
+}
+
 // Kernel order of a step (groups in brackets): [0 Gauss checks: charge,
 // residual] | [0] field diag | [1] particle | [2] 6 x re-layout | [1] binary
 // collisions (if any) | [3] J reduction | [0 continuity check: charge,
@@ -2467,8 +2507,9 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, Launcher &L
     L.grp = 0;
     L(k_field_diag<R>, dim3(hp.fd_blocks), dim3(256), dp);
     L.grp = 1;
-    if (hp.coulomb) L(k_particle<R, A, D, T, true>, dim3(ntiles), dim3(kBlock), dp);
-    else L(k_particle<R, A, D, T, false>, dim3(ntiles), dim3(kBlock), dp);
+    const unsigned pbk = (unsigned)shape_block(sizeof(R) == 4, hp.shape);
+    if (hp.coulomb) L(particle_kernel<R, A, D, T, true>(hp.shape), dim3(ntiles), dim3(pbk), dp);
+    else L(particle_kernel<R, A, D, T, false>(hp.shape), dim3(ntiles), dim3(pbk), dp);
     L.grp = 2;
     L(k_rebin_count, dim3(nst), dim3(256), dp);
     L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
@@ -2542,8 +2583,10 @@ static void batch_particle(Launcher &L, const BatchTable &ht, const BatchTable *
 {
     constexpr int g = T == 8 ? 0 : (T == 16 ? 1 : 2);
     const unsigned nb = ht.grp[g].n_items > 0 ? (unsigned)std::max(1, pblocks) : 1u;
-    if (ht.coulomb) L(kb_particle<R, A, D, T, true>, dim3(nb), dim3(kBlock), dt);
-    else L(kb_particle<R, A, D, T, false>, dim3(nb), dim3(kBlock), dt);
+    const int shape = ht.grp[g].shape;
+    const unsigned pbk = (unsigned)shape_block(sizeof(R) == 4, shape);
+    if (ht.coulomb) L(batch_particle_kernel<R, A, D, T, true>(shape), dim3(nb), dim3(pbk), dt);
+    else L(batch_particle_kernel<R, A, D, T, false>(shape), dim3(nb), dim3(pbk), dt);
 }
 
 template <typename R, int D>
@@ -2592,20 +2635,21 @@ hipError_t launch_batch_step(int precision, int ndim, const BatchTable &ht, cons
 }
 
 template <typename R, int D, int T>
-static hipError_t occupancy(bool cb, int *n)
+static hipError_t occupancy(bool cb, int shape, int *n)
 {
-    return cb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T, true>, kBlock, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, kb_particle<R, double, D, T, false>, kBlock, 0);
+    const int bk = shape_block(sizeof(R) == 4, shape);
+    return cb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, batch_particle_kernel<R, double, D, T, true>(shape), bk, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, batch_particle_kernel<R, double, D, T, false>(shape), bk, 0);
 }
 
-hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool cb, int *n)
+hipError_t batch_particle_occupancy(int precision, int ndim, int g, bool cb, int shape, int *n)
 {
     const bool mx = precision == PIC_PREC_MIXED;
-    if (ndim == 3) return mx ? occupancy<float, 3, 8>(cb, n) : occupancy<double, 3, 8>(cb, n);
+    if (ndim == 3) return mx ? occupancy<float, 3, 8>(cb, shape, n) : occupancy<double, 3, 8>(cb, shape, n);
     switch (g) {
-    case 0: return mx ? occupancy<float, 2, 8>(cb, n) : occupancy<double, 2, 8>(cb, n);
-    case 1: return mx ? occupancy<float, 2, 16>(cb, n) : occupancy<double, 2, 16>(cb, n);
-    case 2: return mx ? occupancy<float, 2, 32>(cb, n) : occupancy<double, 2, 32>(cb, n);
+    case 0: return mx ? occupancy<float, 2, 8>(cb, shape, n) : occupancy<double, 2, 8>(cb, shape, n);
+    case 1: return mx ? occupancy<float, 2, 16>(cb, shape, n) : occupancy<double, 2, 16>(cb, shape, n);
+    case 2: return mx ? occupancy<float, 2, 32>(cb, shape, n) : occupancy<double, 2, 32>(cb, shape, n);
     default: return hipErrorInvalidValue;
     }
 }

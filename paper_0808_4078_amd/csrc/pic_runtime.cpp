@@ -89,6 +89,10 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
     if (!(g->nu_ee >= 0.0) || !std::isfinite(g->nu_ee)) return fail(err, PIC_E_INVALID_ARG, "nu_ee must be >= 0");
     if (g->nu_ee > 0.0 && !(g->ee_vref > 0.0 && g->ee_vref < 1.0))
         return fail(err, PIC_E_INVALID_ARG, "binary collisions need 0 < ee_vref < 1");
+    if (g->shape < 0 || g->shape >= kShapes)
+        return fail(err, PIC_E_INVALID_ARG, "shape %d out of 0..%d", g->shape, kShapes - 1);
+    if (g->shape != 0 && g->precision != PIC_PREC_MIXED)
+        return fail(err, PIC_E_INVALID_ARG, "shape %d: FP64 runs take shape 0 only", g->shape);
     const double reserve = g->reserve > 0.0 ? g->reserve : 1.0;
     Geometry &G = L->g;
     memset(&G, 0, sizeof(G));
@@ -611,6 +615,7 @@ pic_grid_desc canonical_grid(const pic_grid_desc &g)
     c.reserve = g.reserve;
     c.nu_ee = g.nu_ee;
     c.ee_vref = g.ee_vref;
+    c.shape = g.shape;
     return c;
 }
 
@@ -750,6 +755,7 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
     K.nspecies = nspecies;
     K.precision = grid->precision;
     K.diag_every = grid->diag_every;
+    K.shape = grid->shape;
     K.flags = grid->flags;
     K.seed = grid->seed;
     K.run = grid->run;
@@ -1022,6 +1028,9 @@ int pic_info(pic_run *r, pic_run_info *out)
     out->graph_launches = r->graph_launches;
     out->direct_steps = r->direct_steps;
     out->scratch_bytes = r->L.scratch_bytes;
+    out->shape = r->hp.shape;
+    out->block_threads = kShapeBlock[r->hp.shape];
+    out->inflight = kShapeInflight[r->hp.shape];
     return PIC_OK;
 }
 
@@ -1357,6 +1366,16 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
         if (runs[i]->stream != runs[0]->stream)
             return fail(nullptr, PIC_E_INVALID_ARG, "run %d: members must be bound to the same stream", i);
     }
+    // the members of one tile edge share one particle kernel, so one shape
+    int group_shape[kBatchGroups] = {-1, -1, -1};
+    for (int i = 0; i < nruns; ++i) {
+        int &gs = group_shape[tile_group(runs[i])];
+        if (gs >= 0 && gs != runs[i]->hp.shape)
+            return fail(nullptr, PIC_E_INVALID_ARG,
+                        "run %d: shape %d, but an earlier member with tile edge %d has shape %d", i,
+                        runs[i]->hp.shape, runs[i]->grid.tile[0], gs);
+        gs = runs[i]->hp.shape;
+    }
     pic_batch *b = new (std::nothrow) pic_batch();
     if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "host allocation failed");
     b->runs.assign(runs, runs + nruns);
@@ -1412,6 +1431,7 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
     H.kp = (const KParams *const *)(base + B.kp);
     H.cell_blocks = (const int2 *)(base + B.cell_blocks);
     for (int g = 0; g < kBatchGroups; ++g) {
+        H.grp[g].shape = group_shape[g] < 0 ? 0 : group_shape[g];
         H.grp[g].n_items = (int)items[g].size();
         H.grp[g].items = (const int2 *)(base + B.items[g]);
         for (int c = 0; c < kBatchXcds; ++c) {
@@ -1431,7 +1451,7 @@ int pic_batch_init(int nruns, pic_run *const *runs, void *table, size_t table_by
             continue;
         }
         int per_cu = 0;
-        he = batch_particle_occupancy(b->precision, b->ndim, g, H.coulomb != 0, &per_cu);
+        he = batch_particle_occupancy(b->precision, b->ndim, g, H.coulomb != 0, H.grp[g].shape, &per_cu);
         b->pblocks[g] = std::max(1, per_cu) * std::max(1, cus);
     }
     const std::vector<int> zeros((size_t)kBatchGroups * kBatchXcds, 0);
@@ -1538,12 +1558,13 @@ int pic_batch_diagnostics(pic_batch *b, int run, pic_diag *out)
     return rc;
 }
 
-int pic_batch_info(pic_batch *b, int32_t *persistent_blocks, int32_t *items)
+int pic_batch_info(pic_batch *b, int32_t *persistent_blocks, int32_t *items, int32_t *shapes)
 {
     if (!b) return fail(nullptr, PIC_E_INVALID_ARG, "null handle");
     for (int g = 0; g < kBatchGroups; ++g) {
         if (persistent_blocks) persistent_blocks[g] = b->ht.grp[g].n_items ? b->pblocks[g] : 0;
         if (items) items[g] = b->ht.grp[g].n_items;
+        if (shapes) shapes[g] = b->ht.grp[g].n_items ? b->ht.grp[g].shape : -1;
     }
     return PIC_OK;
 }
@@ -1612,70 +1633,119 @@ int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, i
     return PIC_OK;
 }
 
-int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
-             void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_tile,
-             double *ms)
+// Milliseconds per step of `copies` fresh device-loaded runs of the described
+// configuration at tile edge `tile` and particle-kernel shape `shape` (alone
+// when copies == 1, as one batch otherwise), over nsteps graph-replayed steps
+// after 2 warm-up steps.
+static int tune_time(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
+                     void *workspace, void *hip_stream, int32_t nsteps, int tile, int shape, double *ms)
 {
-    if (!grid || !species || !workspace || !best_tile || !ms || nsteps < 1)
+    hipStream_t st = (hipStream_t)hip_stream;
+    TuneCarve T;
+    int rc = tune_carve(grid, species, nspecies, copies, tile, &T);
+    if (rc) return rc;
+    std::vector<pic_run *> runs;
+    pic_batch *b = nullptr;
+    for (int i = 0; !rc && i < copies; ++i) {
+        pic_grid_desc g = *grid;
+        for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? tile : 0;
+        g.shape = shape;
+        g.flags &= ~(uint32_t)PIC_FLAG_HOST_LOAD;
+        g.run = grid->run + (uint32_t)i;
+        char *base = (char *)workspace + T.per_copy * (size_t)i;
+        pic_buffers buf;
+        memset(&buf, 0, sizeof(buf));
+        for (int s = 0; s < nspecies; ++s) buf.particles[s] = base + T.part[s];
+        buf.fields = base + T.fields;
+        buf.scratch = base + T.scratch;
+        buf.diag = base + T.diag;
+        pic_run *r = nullptr;
+        rc = pic_init(&g, species, nspecies, &buf, hip_stream, &r);
+        if (!rc) runs.push_back(r);
+    }
+    if (!rc && copies > 1)
+        rc = pic_batch_init(copies, runs.data(), (char *)workspace + T.table, T.table_bytes, 0, 0, &b);
+    auto steps = [&](int32_t n) { return b ? pic_batch_step(b, n) : pic_step(runs[0], n); };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float el = 0.f;
+    hipError_t he = hipSuccess;
+    if (!rc) he = hipEventCreate(&e0);
+    if (!rc && he == hipSuccess) he = hipEventCreate(&e1);
+    if (!rc && he == hipSuccess) rc = steps(2);
+    if (!rc && he == hipSuccess) he = hipEventRecord(e0, st);
+    if (!rc && he == hipSuccess) rc = steps(nsteps);
+    if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
+    if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&el, e0, e1);
+    if (!rc && he == hipSuccess) rc = b ? pic_batch_sync(b) : pic_sync(runs[0]);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    if (b) pic_batch_destroy(b);
+    for (pic_run *r : runs) pic_destroy(r);
+    if (he != hipSuccess) return fail(nullptr, PIC_E_HIP, "tuner timing: %s", hipGetErrorString(he));
+    if (rc) return rc;
+    *ms = (double)el / nsteps;
+    return PIC_OK;
+}
+
+static int tune_prologue(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
+                         void *workspace, size_t workspace_bytes, int32_t nsteps, const void *best, const double *ms)
+{
+    if (!grid || !species || !workspace || !best || !ms || nsteps < 1)
         return fail(nullptr, PIC_E_INVALID_ARG, "bad argument");
     size_t need = 0;
     int rc = pic_tune_query(grid, species, nspecies, copies, &need);
     if (rc) return rc;
     if (workspace_bytes < need)
         return fail(nullptr, PIC_E_BUFFER_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
-    hipStream_t st = (hipStream_t)hip_stream;
+    return PIC_OK;
+}
+
+int pic_tune(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
+             void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_tile,
+             double *ms)
+{
+    int rc = tune_prologue(grid, species, nspecies, copies, workspace, workspace_bytes, nsteps, best_tile, ms);
+    if (rc) return rc;
     *best_tile = 0;
     double best = 0.0;
     for (int k = 0, t = 8; t <= 32; ++k, t *= 2) {
         ms[k] = -1.0;
         if (!tile_fits(grid, t)) continue;
-        TuneCarve T;
-        rc = tune_carve(grid, species, nspecies, copies, t, &T);
+        rc = tune_time(grid, species, nspecies, copies, workspace, hip_stream, nsteps, t, grid->shape, &ms[k]);
         if (rc) return rc;
-        std::vector<pic_run *> runs;
-        pic_batch *b = nullptr;
-        for (int i = 0; !rc && i < copies; ++i) {
-            pic_grid_desc g = *grid;
-            for (int a = 0; a < 3; ++a) g.tile[a] = a < g.ndim ? t : 0;
-            g.flags &= ~(uint32_t)PIC_FLAG_HOST_LOAD;
-            g.run = grid->run + (uint32_t)i;
-            char *base = (char *)workspace + T.per_copy * (size_t)i;
-            pic_buffers buf;
-            memset(&buf, 0, sizeof(buf));
-            for (int s = 0; s < nspecies; ++s) buf.particles[s] = base + T.part[s];
-            buf.fields = base + T.fields;
-            buf.scratch = base + T.scratch;
-            buf.diag = base + T.diag;
-            pic_run *r = nullptr;
-            rc = pic_init(&g, species, nspecies, &buf, hip_stream, &r);
-            if (!rc) runs.push_back(r);
-        }
-        if (!rc && copies > 1)
-            rc = pic_batch_init(copies, runs.data(), (char *)workspace + T.table, T.table_bytes, 0, 0, &b);
-        auto steps = [&](int32_t n) { return b ? pic_batch_step(b, n) : pic_step(runs[0], n); };
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        float el = 0.f;
-        hipError_t he = hipSuccess;
-        if (!rc) he = hipEventCreate(&e0);
-        if (!rc && he == hipSuccess) he = hipEventCreate(&e1);
-        if (!rc && he == hipSuccess) rc = steps(2);
-        if (!rc && he == hipSuccess) he = hipEventRecord(e0, st);
-        if (!rc && he == hipSuccess) rc = steps(nsteps);
-        if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
-        if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
-        if (!rc && he == hipSuccess) he = hipEventElapsedTime(&el, e0, e1);
-        if (!rc && he == hipSuccess) rc = b ? pic_batch_sync(b) : pic_sync(runs[0]);
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        (void)hipStreamSynchronize(st);
-        if (b) pic_batch_destroy(b);
-        for (pic_run *r : runs) pic_destroy(r);
-        if (he != hipSuccess) return fail(nullptr, PIC_E_HIP, "tuner timing: %s", hipGetErrorString(he));
-        if (rc) return rc;
-        ms[k] = (double)el / nsteps;
         if (*best_tile == 0 || ms[k] < best) {
             best = ms[k];
             *best_tile = t;
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_tune_shape(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
+                   void *workspace, size_t workspace_bytes, void *hip_stream, int32_t nsteps, int32_t *best_shape,
+                   double *ms)
+{
+    int rc = tune_prologue(grid, species, nspecies, copies, workspace, workspace_bytes, nsteps, best_shape, ms);
+    if (rc) return rc;
+    int t = grid->tile[0];
+    if (t == 0) {
+        t = grid->ndim == 3 ? 8 : 16;
+        if (!tile_fits(grid, t)) t = 8;
+    }
+    if (!tile_fits(grid, t)) return fail(nullptr, PIC_E_INVALID_ARG, "tile %d does not divide the grid", t);
+    const int nshapes = grid->precision == PIC_PREC_MIXED ? kShapes : 1;
+    *best_shape = -1;
+    double best = 0.0;
+    for (int k = 0; k < kShapes; ++k) {
+        ms[k] = -1.0;
+        if (k >= nshapes) continue;
+        rc = tune_time(grid, species, nspecies, copies, workspace, hip_stream, nsteps, t, k, &ms[k]);
+        if (rc) return rc;
+        if (*best_shape < 0 || ms[k] < best) {
+            best = ms[k];
+            *best_shape = k;
         }
     }
     return PIC_OK;

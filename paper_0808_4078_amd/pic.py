@@ -44,7 +44,7 @@ class GridDesc(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("run", C.c_uint32),
                 ("tile", C.c_int32 * 3), ("diag_every", C.c_int32), ("flags", C.c_uint32),
-                ("reserve", C.c_double), ("nu_ee", C.c_double), ("ee_vref", C.c_double)]
+                ("reserve", C.c_double), ("nu_ee", C.c_double), ("ee_vref", C.c_double), ("shape", C.c_int32)]
 
 
 class SpeciesDesc(C.Structure):
@@ -86,7 +86,8 @@ class Diag(C.Structure):
 class RunInfo(C.Structure):
     """pic_run_info: how a run or batch enqueues its steps."""
     _fields_ = [("graph", C.c_int32), ("static_scratch", C.c_int32), ("steps_enqueued", C.c_int64),
-                ("graph_launches", C.c_int64), ("direct_steps", C.c_int64), ("scratch_bytes", C.c_size_t)]
+                ("graph_launches", C.c_int64), ("direct_steps", C.c_int64), ("scratch_bytes", C.c_size_t),
+                ("shape", C.c_int32), ("block_threads", C.c_int32), ("inflight", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -106,7 +107,7 @@ EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_
            "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_launch_info",
            "pic_batch_diagnostics",
            "pic_batch_destroy", "pic_tune_query",
-           "pic_tune", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
+           "pic_tune", "pic_tune_shape", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
            "pic_hyb_step_profiled", "pic_hyb_sync", "pic_hyb_read_grid", "pic_hyb_read_particles",
            "pic_hyb_diag_history", "pic_hyb_last_error", "pic_hyb_destroy"]
 
@@ -170,13 +171,15 @@ def lib():
         L.pic_batch_step.argtypes = [vp, C.c_int32]
         L.pic_batch_step_profiled.argtypes = [vp, C.c_int32, P(C.c_double)]
         L.pic_batch_sync.argtypes = [vp]
-        L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.pic_batch_info.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
         L.pic_batch_launch_info.argtypes = [vp, P(RunInfo)]
         L.pic_batch_diagnostics.argtypes = [vp, C.c_int, P(Diag)]
         L.pic_batch_destroy.argtypes = [vp]
         L.pic_tune_query.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, P(C.c_size_t)]
         L.pic_tune.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp, C.c_int32,
                                P(C.c_int32), P(C.c_double)]
+        L.pic_tune_shape.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp,
+                                     C.c_int32, P(C.c_int32), P(C.c_double)]
         L.pic_hyb_query.argtypes = [P(HybDesc), P(C.c_size_t), P(C.c_size_t)]
         L.pic_hyb_init.argtypes = [P(HybDesc), vp, C.c_size_t, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
         L.pic_hyb_step.argtypes = [vp, C.c_int32]
@@ -203,7 +206,7 @@ def _check(rc: int, what: str, handle=None):
 
 
 def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0, tile=0,
-               diag_every=0, flags=0, reserve=0.0, nu_ee=0.0, ee_vref=0.0):
+               diag_every=0, flags=0, reserve=0.0, nu_ee=0.0, ee_vref=0.0, shape=0):
     """Descriptors from plain values.  species: list of dicts with keys
     charge, mass, density, ppc, drift_u, u_th, cancel_current_of, nu_coll
     (optional: coll_model, coll_vref, binary)."""
@@ -222,6 +225,7 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
     g.reserve = float(reserve)
     g.nu_ee = float(nu_ee)
     g.ee_vref = float(ee_vref)
+    g.shape = int(shape)
     arr = (SpeciesDesc * len(species))()
     for i, s in enumerate(species):
         arr[i].charge = float(s.get("charge", -1.0))
@@ -240,7 +244,7 @@ def make_descs(ndim, n, d, dt, species, precision=PIC_PREC_MIXED, seed=0, run=0,
     return g, arr
 
 
-def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0, reserve=0.0):
+def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, run=0, reserve=0.0, shape=0):
     """Descriptors of a synthetic workload object (attributes ndim, n, d, dt,
     seed, species[name, q, m, density, ppc, drift_u, u_th, nu, cancel_current_of, and
     optionally coll_model, coll_vref])."""
@@ -252,7 +256,7 @@ def workload_descs(wl, precision=PIC_PREC_MIXED, tile=0, diag_every=0, flags=0, 
     if getattr(wl, "lattice", False):
         flags |= PIC_FLAG_LATTICE_LOAD
     return make_descs(wl.ndim, wl.n, wl.d, wl.dt, sp, precision, wl.seed, run, tile, diag_every, flags, reserve,
-                      getattr(wl, "nu_ee", 0.0), getattr(wl, "ee_vref", 0.0))
+                      getattr(wl, "nu_ee", 0.0), getattr(wl, "ee_vref", 0.0), shape)
 
 
 def query(grid: GridDesc, species) -> Sizes:
@@ -453,8 +457,9 @@ class Batch:
     def info(self) -> dict:
         pb = (C.c_int32 * 3)()
         it = (C.c_int32 * 3)()
-        _check(lib().pic_batch_info(self.h, pb, it), "pic_batch_info")
-        return {"persistent_blocks": list(pb), "items": list(it)}
+        sh = (C.c_int32 * 3)()
+        _check(lib().pic_batch_info(self.h, pb, it, sh), "pic_batch_info")
+        return {"persistent_blocks": list(pb), "items": list(it), "shapes": list(sh)}
 
     def launch_info(self) -> dict:
         """pic_batch_launch_info: graph or kernel-by-kernel steps, and the counts."""
@@ -502,6 +507,28 @@ def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None
                           int(ws.numel()), C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
     del ws
     return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}
+
+
+# pic_particle shapes (PIC_PARTICLE_SHAPES): threads per workgroup, particles in flight per lane
+SHAPES = {0: (256, 2), 1: (256, 1), 2: (256, 3), 3: (512, 2), 4: (128, 2)}
+
+
+def tune_shape(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None):
+    """pic_tune_shape: (best launch shape, {shape: ms per step}) at the
+    grid's tile edge (copies > 1: a batch of that many copies)."""
+    import torch
+    nbytes = C.c_size_t()
+    _check(lib().pic_tune_query(C.byref(grid), species, len(species), int(copies), C.byref(nbytes)),
+           "pic_tune_query")
+    ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    best = C.c_int32()
+    ms = (C.c_double * len(SHAPES))()
+    _check(lib().pic_tune_shape(C.byref(grid), species, len(species), int(copies), C.c_void_p(ws.data_ptr()),
+                                int(ws.numel()), C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms),
+           "pic_tune_shape")
+    del ws
+    return int(best.value), {k: ms[k] for k in SHAPES if ms[k] >= 0}
 
 
 # ---------------------------------------------------------------------------

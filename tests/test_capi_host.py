@@ -31,11 +31,12 @@ def test_library_exports_every_declared_entry_point():
 def test_ctypes_structs_match_the_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include "pic.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(void){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_grid_desc),'
                     'sizeof(pic_species_desc), sizeof(pic_sizes), sizeof(pic_buffers), sizeof(pic_diag),'
                     'offsetof(pic_grid_desc, flags), offsetof(pic_diag, rebins), sizeof(pic_hyb_desc),'
                     'offsetof(pic_hyb_desc, flags), sizeof(pic_hyb_diag), offsetof(pic_hyb_diag, mean_psi),'
-                    'offsetof(pic_grid_desc, ee_vref), offsetof(pic_diag, ee_pairs));'
+                    'offsetof(pic_grid_desc, ee_vref), offsetof(pic_diag, ee_pairs), offsetof(pic_grid_desc, shape),'
+                    'sizeof(pic_run_info), offsetof(pic_run_info, inflight));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -44,7 +45,8 @@ def test_ctypes_structs_match_the_header(tmp_path):
     want = [C.sizeof(pic.GridDesc), C.sizeof(pic.SpeciesDesc), C.sizeof(pic.Sizes), C.sizeof(pic.Buffers),
             C.sizeof(pic.Diag), pic.GridDesc.flags.offset, pic.Diag.rebins.offset, C.sizeof(pic.HybDesc),
             pic.HybDesc.flags.offset, C.sizeof(pic.HybDiag), pic.HybDiag.mean_psi.offset,
-            pic.GridDesc.ee_vref.offset, pic.Diag.ee_pairs.offset]
+            pic.GridDesc.ee_vref.offset, pic.Diag.ee_pairs.offset, pic.GridDesc.shape.offset,
+            C.sizeof(pic.RunInfo), pic.RunInfo.inflight.offset]
     assert got == want
 
 
@@ -131,6 +133,26 @@ def test_batch_and_tuner_queries_validate_on_the_host():
     ms = (C.c_double * 3)()
     g, sp = pic.workload_descs(synth.C1)
     assert L.pic_tune(C.byref(g), sp, len(sp), 1, None, 0, None, 4, C.byref(best), ms) == -1
+    ms5 = (C.c_double * len(pic.SHAPES))()
+    assert L.pic_tune_shape(C.byref(g), sp, len(sp), 1, None, 0, None, 4, C.byref(best), ms5) == -1
+
+
+@pytest.mark.parametrize("prec,shape,code", [
+    (pic.PIC_PREC_MIXED, 0, 0), (pic.PIC_PREC_MIXED, 4, 0), (pic.PIC_PREC_MIXED, 5, -1),
+    (pic.PIC_PREC_MIXED, -1, -1), (pic.PIC_PREC_FP64, 0, 0), (pic.PIC_PREC_FP64, 3, -1)])
+def test_query_validates_the_launch_shape(prec, shape, code):
+    """Shapes 0..4 in mixed precision; FP64 runs take shape 0 only."""
+    import ctypes as C
+    g, sp = pic.workload_descs(synth.C1, precision=prec, shape=shape)
+    out = pic.Sizes()
+    assert pic.lib().pic_query(C.byref(g), sp, len(sp), C.byref(out)) == code
+
+
+def test_shape_table_matches_the_header():
+    src = open(HEADER).read()
+    assert int(re.search(r"#define PIC_PARTICLE_SHAPES (\d+)", src).group(1)) == len(pic.SHAPES)
+    for k, (blk, inflight) in pic.SHAPES.items():
+        assert re.search(rf"\b{k}: {blk} / {inflight}\b", src), k
 
 
 def test_checkpoint_entry_points_reject_null_handles(tmp_path):

@@ -52,10 +52,10 @@ def _node_currents(orc, wl, E_step, before, after, nodes):
     return Jacc
 
 
-def _sampled_step(pic, prec, warm, x_tol, u_tol, flags=0, j_nodes=0):
+def _sampled_step(pic, prec, warm, x_tol, u_tol, flags=0, j_nodes=0, shape=0):
     wl = synth.C3
     p = pic.PIC_PREC_MIXED if prec == "mixed" else pic.PIC_PREC_FP64
-    g, sp = pic.workload_descs(wl, precision=p, tile=16, diag_every=10, flags=flags)
+    g, sp = pic.workload_descs(wl, precision=p, tile=16, diag_every=10, flags=flags, shape=shape)
     tracked = [sc.nu > 0 or bool(flags & pic.PIC_FLAG_TRACK_IDS) for sc in wl.species]
     r = pic.Run(g, sp)
     r.step(warm)
@@ -124,9 +124,12 @@ def _sampled_step(pic, prec, warm, x_tol, u_tol, flags=0, j_nodes=0):
     return worst_x, worst_u
 
 
-def test_full_size_mixed_sampled_step(pic):
-    log("case full size C3 mixed (sampled)")
-    _sampled_step(pic, "mixed", 10, 2e-5, 2e-5)
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+def test_full_size_mixed_sampled_step(pic, shape):
+    """In every launch shape of the particle kernel (bench.py takes the one
+    pic_tune_shape finds fastest)."""
+    log(f"case full size C3 mixed (sampled), shape {shape}")
+    _sampled_step(pic, "mixed", 10, 2e-5, 2e-5, shape=shape)
 
 
 def test_full_size_fp64_sampled_step(pic):
@@ -143,18 +146,19 @@ def test_full_size_mixed_both_species(pic):
     _sampled_step(pic, "mixed", 30, 2e-5, 2e-5, flags=pic.PIC_FLAG_TRACK_IDS, j_nodes=8)
 
 
-def test_full_size_c4_gauss_and_counts(pic):
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+def test_full_size_c4_gauss_and_counts(pic, shape):
     """C4 at its full size in the configuration bench.py times (256 x 256 x
     512 cells, 8 particles per cell per species, 536 870 912 particles, 8^3
     tiles, 200% store reserve): reading the particles back is out of reach,
     so the check is on properties that hold at any size -- Gauss's law kept
     to the FP32 level of the mixed deposit at every record, and every
-    particle present."""
-    log("case full size C4 mixed (Gauss residual, counts)")
+    particle present; in every launch shape of the particle kernel."""
+    log(f"case full size C4 mixed (Gauss residual, counts), shape {shape}")
     import bench
     wl = synth.C4
     g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=8, diag_every=10,
-                               flags=pic.PIC_FLAG_GAUSS_RESIDUAL, reserve=bench.RESERVE_3D)
+                               flags=pic.PIC_FLAG_GAUSS_RESIDUAL, reserve=bench.RESERVE_3D, shape=shape)
     r = pic.Run(g, sp)
     r.step(31)
     r.sync()
