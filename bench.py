@@ -475,7 +475,7 @@ def main():
     if a.shape >= 0:
         shape, shape_tuning = a.shape, None
     else:
-        shape, shape_tuning = tune_shape(wl, a.tile, RESERVE_2D)
+        shape, shape_tuning = tune_shape(wl, a.tile, RESERVE_2D, nsteps=20)
     mixed = run_gpu(wl, "mixed", a.steps, a.warmup, a.tile, a.diag_every, reserve=RESERVE_2D, shape=shape)
     fp64 = None if a.skip_fp64 else run_gpu(replace(wl, name="C2"), "fp64", a.steps, a.warmup, a.tile,
                                             a.diag_every, reserve=RESERVE_2D)

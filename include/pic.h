@@ -465,8 +465,8 @@ int pic_batch_destroy(pic_batch *batch);
  * LDS footprint of the particle kernel.  pic_tune builds, inside the caller's
  * workspace, `copies` fresh device-loaded runs of the described configuration
  * (run indices grid->run + i) for every edge in {8, 16, 32} that divides each
- * resolved axis (3D: 8 only), times `nsteps` graph-replayed steps after 2
- * warm-up steps -- of the run alone when copies == 1, of a batch of the
+ * resolved axis (3D: 8 only), times `nsteps` graph-replayed steps after
+ * max(2, nsteps) warm-up steps -- of the run alone when copies == 1, of a batch of the
  * copies otherwise (enough copies fill the device, which is the situation of
  * a member of a large ensemble) -- and returns the fastest edge in
  * *best_tile and each candidate's milliseconds per step in ms[3] (edge 8,

@@ -1636,7 +1636,7 @@ int pic_tune_query(const pic_grid_desc *grid, const pic_species_desc *species, i
 // Milliseconds per step of `copies` fresh device-loaded runs of the described
 // configuration at tile edge `tile` and particle-kernel shape `shape` (alone
 // when copies == 1, as one batch otherwise), over nsteps graph-replayed steps
-// after 2 warm-up steps.
+// after as many warm-up steps (at least 2).
 static int tune_time(const pic_grid_desc *grid, const pic_species_desc *species, int nspecies, int32_t copies,
                      void *workspace, void *hip_stream, int32_t nsteps, int tile, int shape, double *ms)
 {
@@ -1671,7 +1671,7 @@ static int tune_time(const pic_grid_desc *grid, const pic_species_desc *species,
     hipError_t he = hipSuccess;
     if (!rc) he = hipEventCreate(&e0);
     if (!rc && he == hipSuccess) he = hipEventCreate(&e1);
-    if (!rc && he == hipSuccess) rc = steps(2);
+    if (!rc && he == hipSuccess) rc = steps(std::max(2, nsteps));
     if (!rc && he == hipSuccess) he = hipEventRecord(e0, st);
     if (!rc && he == hipSuccess) rc = steps(nsteps);
     if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
