@@ -131,6 +131,8 @@ struct KParams {
     double ee_vref;
     int32_t binary;      // 1 if the binary-collision kernel runs (nu_ee > 0 and a species takes part)
     int64_t *ee_tile;    // [tiles] binary-collision pairs scattered in the tile this step
+    uint32_t *ee_ent;    // binary collisions: each tile's participants in cell order (slot | species << 29),
+                         // the tile's list at the sum over participating species of its bin starts
     // Gauss-law and continuity checks (PIC_FLAG_GAUSS_RESIDUAL only; null otherwise)
     double *rho_tile;    // [tiles][(T+1)^ndim] per-tile charge partials
     double *rho0;        // [cells] charge on the nodes at step 0

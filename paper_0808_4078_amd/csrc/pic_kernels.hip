@@ -1331,14 +1331,16 @@ __global__ __launch_bounds__(256) void k_continuity(const KParams *__restrict__ 
 // heavier particle takes its new momentum with probability w_small/w_large
 // (Nanbu and Yonemura 1998).
 //
-// One workgroup per tile.  The tile's participants are counted per cell,
-// then handled in ranges of consecutive cells holding at most kBinCap of
-// them: their slots go to LDS with a 64-bit sort key (cell in the range,
-// Philox key, low id bits), a bitonic sort puts them in (cell, key)
-// order (equal keys, about 2^-32 per pair, are then ordered by the full id),
-// and the pairs (a triple counts as one unit, done by one thread in order)
-// are spread over the threads; the momenta are read and written in the
-// particle store in place.
+// One workgroup per tile.  The tile's participants are counted per cell and
+// put in cell order by a counting sort into a list in scratch memory (store
+// slot and species of each), then handled in ranges of consecutive cells
+// holding at most kBinCap of them: the range's entries go to LDS with the
+// 64-bit key (Philox key << 32 | id), each entry's rank among its cell's
+// entries in key order places it (a rank sort per cell: a cell holds a few
+// hundred participants at most, and the lanes of a wave mostly share one
+// cell, so they read the same keys), and the pairs (a triple counts as one
+// unit, done by one thread in order) are spread over the threads; the
+// momenta are read and written in the particle store in place.
 constexpr int kBinCap = 4096;
 
 template <typename R>
@@ -1439,15 +1441,16 @@ template <typename R, int D, int T>
 __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restrict__ kp)
 {
     constexpr int TC = D == 3 ? T * T * T : T * T;      // cells of the tile
-    __shared__ uint32_t s_cnt[TC];                       // participants per cell
+    constexpr uint32_t kSlotMask = (1u << 29) - 1u;
+    __shared__ uint32_t s_cnt[TC];                       // participants per cell, then fill cursors
     __shared__ uint32_t s_off[TC + 1];                   // tile-wide exclusive prefix of the counts
     __shared__ uint32_t s_unit[TC + 1];                  // prefix of the work units of the range's cells
-    __shared__ uint64_t s_k64[kBinCap];                  // sort key: cell in range | Philox key | low id bits
-    __shared__ uint16_t s_idx[kBinCap];                  // entry of each sorted position
-    __shared__ uint32_t s_slot[kBinCap];                 // store slot of each entry
-    __shared__ uint8_t s_sp[kBinCap];                    // species of each entry
+    __shared__ uint64_t s_k64[kBinCap];                  // sort key of each entry: Philox key << 32 | id
+    __shared__ uint32_t s_ent[kBinCap];                  // slot | species << 29 of each entry
+    __shared__ uint16_t s_cell[kBinCap];                 // cell (in the range) of each entry
+    __shared__ uint16_t s_idx[kBinCap];                  // entry at each sorted position
     __shared__ uint32_t s_range[2];
-    __shared__ uint32_t s_fill, s_pairs, s_tie;
+    __shared__ uint32_t s_pairs;
     const DevState *st = kp->state;
     DevState *stw = kp->state;
     if (st->fatal & 4) return;                           // the store was not re-laid out
@@ -1458,7 +1461,6 @@ __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restric
     const int t0[3] = {(tile % ntx) * T, ((tile / ntx) % nty) * T, (tile / (ntx * nty)) * T};
     const uint32_t seed0 = (uint32_t)kp->seed, seed1 = (uint32_t)(kp->seed >> 32), run = kp->run;
     const R cee = R(0.5 * kp->nu_ee * kp->g.dt * kp->ee_vref * kp->ee_vref * kp->ee_vref);
-    const int lane = threadIdx.x & 63;
 
     // local cell of a stored particle (-1 if outside the tile)
     auto local_cell = [&](const SpeciesDev &S, int64_t slot) {
@@ -1479,6 +1481,13 @@ __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restric
     auto slot_of = [&](const SpeciesDev &S, int64_t k, int64_t nf, int64_t nb) {
         return k < nf ? (int64_t)S.start[tile] + k : (int64_t)S.start[tile] + S.cap[tile] - nb + (k - nf);
     };
+    // the tile's list of participants: at the sum of the participating
+    // species' bin starts (bins are laid out in tile order in every species,
+    // so the lists of different tiles do not overlap)
+    int64_t lbase = 0;
+    for (int s = 0; s < kp->nspecies; ++s)
+        if (kp->sp[s].binary) lbase += kp->sp[s].start[tile];
+    uint32_t *list = kp->ee_ent + lbase;
 
     for (int c = threadIdx.x; c < TC; c += blockDim.x) s_cnt[c] = 0;
     if (threadIdx.x == 0) s_pairs = 0;
@@ -1503,6 +1512,23 @@ __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restric
         s_off[TC] = run_total;
     }
     __syncthreads();
+    for (int c = threadIdx.x; c < TC; c += blockDim.x) s_cnt[c] = 0;
+    __syncthreads();
+    // counting sort of the participants by cell into the tile's list (the
+    // order inside a cell is free: the rank sort below fixes it)
+    for (int s = 0; s < kp->nspecies; ++s) {
+        const SpeciesDev &S = kp->sp[s];
+        if (!S.binary) continue;
+        const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
+        for (int64_t k = threadIdx.x; k < nf + nb; k += blockDim.x) {
+            const int64_t slot = slot_of(S, k, nf, nb);
+            const int lc = local_cell(S, slot);
+            if (lc < 0) continue;
+            const uint32_t pos = s_off[lc] + atomicAdd(&s_cnt[lc], 1u);
+            list[pos] = (uint32_t)slot | ((uint32_t)s << 29);
+        }
+    }
+    __syncthreads();                                     // the list is visible to the whole workgroup
     uint32_t my_pairs = 0;
     int c0 = 0;
     while (c0 < TC) {
@@ -1517,88 +1543,41 @@ __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restric
                 s_range[1] = 0;
             }
             s_range[0] = (uint32_t)c1;
-            s_fill = 0;
-            s_tie = 0;
         }
         __syncthreads();
         const int c1 = (int)s_range[0];
         const bool skip = s_range[1] != 0;
         const uint32_t base = s_off[c0], n_in = s_off[c1] - base;
         if (!skip && n_in >= 2) {
-            // the range's participants, in any order, with their sort keys
-            for (int s = 0; s < kp->nspecies; ++s) {
-                const SpeciesDev &S = kp->sp[s];
-                if (!S.binary) continue;
-                const int64_t nf = S.cnt_front[par * ntiles + tile], nb = S.cnt_back[par * ntiles + tile];
-                for (int64_t k0 = 0; k0 < nf + nb; k0 += blockDim.x) {
-                    const int64_t k = k0 + threadIdx.x;
-                    int64_t slot = 0;
-                    int lc = -1;
-                    if (k < nf + nb) {
-                        slot = slot_of(S, k, nf, nb);
-                        lc = local_cell(S, slot);
-                    }
-                    const bool in = lc >= c0 && lc < c1;
-                    const uint64_t m = __ballot(in);
-                    if (!m) continue;
-                    const int leader = __ffsll((unsigned long long)m) - 1;
-                    uint32_t b0 = 0;
-                    if (lane == leader) b0 = atomicAdd(&s_fill, (uint32_t)__popcll(m));
-                    b0 = __builtin_amdgcn_readlane(b0, leader);
-                    if (in) {
-                        const uint32_t pos = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        const uint32_t id = S.id[par][slot];
-                        const uint32_t key = philox10(make_uint4(id, step, kPurposeBinaryKey, run), seed0, seed1).x;
-                        s_k64[pos] = ((uint64_t)(uint32_t)(lc - c0) << 48) | ((uint64_t)key << 16) | (id & 0xFFFFu);
-                        s_idx[pos] = (uint16_t)pos;
-                        s_slot[pos] = (uint32_t)slot;
-                        s_sp[pos] = (uint8_t)s;
-                    }
+            // the range's entries with their sort keys and cells
+            for (uint32_t i = threadIdx.x; i < n_in; i += blockDim.x) {
+                const uint32_t e = list[base + i];
+                const uint32_t slot = e & kSlotMask;
+                const uint32_t id = kp->sp[e >> 29].id[par][slot];
+                const uint32_t key = philox10(make_uint4(id, step, kPurposeBinaryKey, run), seed0, seed1).x;
+                s_k64[i] = ((uint64_t)key << 32) | id;
+                s_ent[i] = e;
+                int lo = c0, hi = c1 - 1;                    // cell holding list position base + i
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= base + i) lo = mid;
+                    else hi = mid - 1;
                 }
-            }
-            // bitonic sort of (key, entry) over the next power of two, padded with the largest key
-            uint32_t P2 = 2;
-            while (P2 < n_in) P2 <<= 1;
-            __syncthreads();
-            for (uint32_t i = n_in + threadIdx.x; i < P2; i += blockDim.x) {
-                s_k64[i] = ~0ull;
-                s_idx[i] = (uint16_t)i;
+                s_cell[i] = (uint16_t)(lo - c0);
             }
             __syncthreads();
-            for (uint32_t kk = 2; kk <= P2; kk <<= 1) {
-                for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = threadIdx.x; i < P2; i += blockDim.x) {
-                        const uint32_t l = i ^ j;
-                        if (l > i) {
-                            const uint64_t a = s_k64[i], b = s_k64[l];
-                            const bool up = (i & kk) == 0;
-                            if ((a > b) == up) {
-                                s_k64[i] = b;
-                                s_k64[l] = a;
-                                const uint16_t t = s_idx[i];
-                                s_idx[i] = s_idx[l];
-                                s_idx[l] = t;
-                            }
-                        }
-                    }
-                    __syncthreads();
+            // rank of each entry among its cell's entries in (key, id) order
+            // (ties, only possible with repeated ids, by list position)
+            for (uint32_t i = threadIdx.x; i < n_in; i += blockDim.x) {
+                const int c = c0 + s_cell[i];
+                const uint32_t lo = s_off[c] - base, hi = s_off[c + 1] - base;
+                const uint64_t k = s_k64[i];
+                uint32_t r = 0;
+                for (uint32_t j = lo; j < hi; ++j) {
+                    const uint64_t kj = s_k64[j];
+                    r += (kj < k || (kj == k && j < i)) ? 1u : 0u;
                 }
-            }
-            // equal Philox keys in one cell (~2^-32 per pair): the low id bits
-            // ordered them; the full ids decide, put in order by one thread
-            for (uint32_t i = threadIdx.x; i + 1 < n_in; i += blockDim.x)
-                if ((s_k64[i] >> 16) == (s_k64[i + 1] >> 16)) s_tie = 1;
-            __syncthreads();
-            auto id_of = [&](uint32_t e) { return kp->sp[s_sp[e]].id[par][s_slot[e]]; };
-            if (s_tie && threadIdx.x == 0) {
-                for (uint32_t i = 1; i < n_in; ++i)
-                    for (uint32_t j = i; j > 0 && (s_k64[j - 1] >> 16) == (s_k64[j] >> 16) &&
-                                         id_of(s_idx[j - 1]) > id_of(s_idx[j]); --j) {
-                        const uint16_t t = s_idx[j];
-                        s_idx[j] = s_idx[j - 1];
-                        s_idx[j - 1] = t;
-                    }
+                s_idx[lo + r] = (uint16_t)i;
             }
             // work units per cell: N/2 pairs, or the triple and (N-3)/2 pairs
             if (threadIdx.x == 0) {
@@ -1638,17 +1617,17 @@ __global__ __launch_bounds__(kBinThreads) void k_binary(const KParams *__restric
                     eb[0] = s_idx[seg + k + 1];
                 }
                 for (int q = 0; q < np; ++q) {
-                    const SpeciesDev &SA = kp->sp[s_sp[ea[q]]];
-                    const SpeciesDev &SB = kp->sp[s_sp[eb[q]]];
-                    const uint32_t sa = s_slot[ea[q]], sb = s_slot[eb[q]];
+                    const SpeciesDev &SA = kp->sp[s_ent[ea[q]] >> 29];
+                    const SpeciesDev &SB = kp->sp[s_ent[eb[q]] >> 29];
+                    const uint32_t sa = s_ent[ea[q]] & kSlotMask, sb = s_ent[eb[q]] & kSlotMask;
                     R ua[3], ub[3];
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         ua[i] = ((const R *)SA.u[par][i])[sa];
                         ub[i] = ((const R *)SB.u[par][i])[sb];
                     }
-                    if (binary_pair<R>(ua, R(SA.m), R(SA.w), SA.id[par][sa], ub, R(SB.m), R(SB.w), fct, step, seed0,
-                                       seed1, run, cee)) {
+                    if (binary_pair<R>(ua, R(SA.m), R(SA.w), (uint32_t)s_k64[ea[q]], ub, R(SB.m), R(SB.w), fct,
+                                       step, seed0, seed1, run, cee)) {
                         ++my_pairs;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) {

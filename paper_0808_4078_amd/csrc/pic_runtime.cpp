@@ -37,6 +37,7 @@ struct Layout {
     size_t Jtile, tile_diag, field_diag, moments, state, kparams, rb[4], order, bucket;   // scratch
     size_t rho_tile, rho0, rho_n, gauss_part, cont_part;    // scratch (Gauss-law and continuity checks)
     size_t ee_tile;                                         // scratch (binary-collision counts per tile)
+    size_t ee_ent = 0;                                      // scratch (binary collisions: cell-sorted participants)
     bool checks = false;                                    // PIC_FLAG_GAUSS_RESIDUAL: the above are carved
     Geometry g;
     int nj;
@@ -211,6 +212,20 @@ int validate(const pic_grid_desc *g, const pic_species_desc *sp, int ns, Layout 
         L->order = c.take((size_t)G.ntiles * 4);
         L->bucket = c.take((size_t)G.ntiles);
         L->ee_tile = c.take((size_t)G.ntiles * 8);
+        {
+            // binary collisions: one 32-bit entry (slot | species << 29) per
+            // store slot of each participating species
+            int64_t ent = 0;
+            const bool ee_on = g->nu_ee > 0.0 && !(g->flags & PIC_FLAG_NO_COLLIDE);
+            for (int s = 0; ee_on && s < ns; ++s)
+                if (sp[s].binary) {
+                    if (L->sp[s].ncap >= ((int64_t)1 << 29))
+                        return fail(err, PIC_E_CAPACITY, "species %d: binary collisions need a store below 2^29 "
+                                    "slots (%lld)", s, (long long)L->sp[s].ncap);
+                    ent += L->sp[s].ncap;
+                }
+            if (ent > 0) L->ee_ent = c.take((size_t)ent * 4);
+        }
         L->checks = (g->flags & PIC_FLAG_GAUSS_RESIDUAL) != 0;
         if (L->checks) {
             int64_t n1 = 1;
@@ -821,6 +836,7 @@ int pic::init_run(const pic_grid_desc *grid, const pic_species_desc *species, in
     K.fd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFieldDiagBlocks, (L.g.cells + 2047) / 2048));
     K.order = (int32_t *)at(buffers->scratch, L.order);
     K.ee_tile = (int64_t *)at(buffers->scratch, L.ee_tile);
+    K.ee_ent = L.ee_ent ? (uint32_t *)at(buffers->scratch, L.ee_ent) : nullptr;
     K.tile_bucket = (uint8_t *)at(buffers->scratch, L.bucket);
     if (L.checks) {
         K.rho_tile = (double *)at(buffers->scratch, L.rho_tile);
