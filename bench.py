@@ -198,13 +198,15 @@ def tune_shape(wl, tile: int, reserve: float, nsteps: int = 10):
 
     g, sp = pic.workload_descs(wl, precision=pic.PIC_PREC_MIXED, tile=tile, reserve=reserve)
     t0 = time.time()
-    best, ms = pic.tune_shape(g, sp, nsteps=nsteps)
+    fastest, ms = pic.tune_shape(g, sp, nsteps=nsteps)
+    best = pic.pick_shape(ms)
     progress(f"{wl.name}: launch shape {best} {pic.SHAPES[best]} (threads, in flight) in {time.time() - t0:.1f} s; "
              + ", ".join(f"{k} {pic.SHAPES[k]}: {v:.3f}" for k, v in ms.items()) + " ms/step")
-    return best, {"best": best, "threads_per_workgroup": pic.SHAPES[best][0],
+    return best, {"chosen": best, "fastest": fastest, "threads_per_workgroup": pic.SHAPES[best][0],
                   "particles_in_flight": pic.SHAPES[best][1], "nsteps": nsteps,
+                  "rule": f"the fastest shape if it beats shape 0 by more than {pic.SHAPE_MARGIN:.0%}, else shape 0",
                   "ms_per_step": {f"{k}: {pic.SHAPES[k][0]}x{pic.SHAPES[k][1]}": v for k, v in ms.items()},
-                  "gain_over_default": ms[0] / ms[best] - 1.0}
+                  "gain_of_fastest_over_default": ms[0] / ms[fastest] - 1.0}
 
 
 def run_gpu(wl, precision: str, steps: int, warmup: int, tile: int, diag_every: int, profile: bool = True,

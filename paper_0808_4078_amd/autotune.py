@@ -19,7 +19,8 @@ workgroup and particles in flight per lane, ``pic.SHAPES``): each class's
 representative is timed in every shape at its chosen edge
 (``pic_tune_shape``), and since the members of one tile edge share one
 particle kernel in a batch, each edge takes the shape that wins for the
-most members at that edge.
+most members at that edge.  A class takes a shape other than the default
+only when it beats the default by more than ``pic.SHAPE_MARGIN``.
 """
 from __future__ import annotations
 
@@ -117,7 +118,7 @@ def choose_launch(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cac
                   log=None, saturate: bool = True):
     """Tile edge and launch shape for every workload.  Returns (tiles,
     shapes, report): report as choose_tiles, each class entry also holding
-    "shape" (its own fastest), "shape_ms" and "shape_cached", and
+    "shape" (its own choice), "shape_ms" and "shape_cached", and
     report["_edges"] mapping each edge in use to the shape applied to it."""
     tiles, report = choose_tiles(workloads, precision, nsteps, cache_path, log, saturate)
     cache = _read(cache_path)
@@ -136,7 +137,8 @@ def choose_launch(workloads, precision=pic.PIC_PREC_MIXED, nsteps: int = 10, cac
         rep = ent["representative"]
         g, sp = pic.workload_descs(workloads[rep], precision=precision, tile=int(ent["tile"]))
         copies = copies_for(workloads[rep], saturate)
-        best, ms = pic.tune_shape(g, sp, nsteps=nsteps, copies=copies)
+        _, ms = pic.tune_shape(g, sp, nsteps=nsteps, copies=copies)
+        best = pic.pick_shape(ms)
         ent["shape"] = best
         ent["shape_ms"] = {str(k): v for k, v in ms.items()}
         ent["shape_cached"] = False

@@ -511,6 +511,16 @@ def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None
 
 # pic_particle shapes (PIC_PARTICLE_SHAPES): threads per workgroup, particles in flight per lane
 SHAPES = {0: (256, 2), 1: (256, 1), 2: (256, 3), 3: (512, 2), 4: (128, 2)}
+# a shape other than the default is taken only when it beats the default by
+# more than this fraction (the tuner's run-to-run spread is about 1%)
+SHAPE_MARGIN = 0.02
+
+
+def pick_shape(ms: dict, margin: float = SHAPE_MARGIN) -> int:
+    """The launch shape to use from tune_shape's timings: the fastest if it
+    beats shape 0 by more than `margin`, else shape 0."""
+    best = min(ms, key=lambda k: ms[k])
+    return best if 0 not in ms or ms[best] < (1.0 - margin) * ms[0] else 0
 
 
 def tune_shape(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None):

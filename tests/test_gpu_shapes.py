@@ -172,6 +172,7 @@ def test_choose_launch_and_cache(pic, tmp_path):
     wls = [synth.beam_plasma((64, 64), ppc=16, name="a"), synth.beam_plasma((64, 64), ppc=12, name="b"),
            synth.beam_plasma((32, 32), ppc=16, name="c")]
     cache = str(tmp_path / "launch.json")
+    assert pic.pick_shape({0: 1.0, 1: 0.99, 3: 0.995}) == 0 and pic.pick_shape({0: 1.0, 3: 0.9, 1: 0.95}) == 3
     tiles, shapes, rep = autotune.choose_launch(wls, nsteps=3, cache_path=cache)
     assert len(tiles) == len(shapes) == 3 and all(s in pic.SHAPES for s in shapes)
     edges = rep["_edges"]
