@@ -167,6 +167,20 @@ __device__ __forceinline__ int sort_key(int i, int j, const Params &P)
 // run, therefore does not depend on the order in which particles are stored
 // or atomics land.  |node value| < 2^15 (far above any density or current of
 // this model), rounding 2^-49 per term.
+//
+// The rounding to an integer: for |x| < 2^51, x + 1.5 * 2^52 lies in
+// [2^52, 2^53), where FP64 numbers are the integers, so the addition itself
+// rounds x to the nearest integer (ties to even, as llrint) and the low
+// mantissa bits hold it: one add and a 64-bit subtract instead of the
+// general FP64 -> int64 conversion.  `big` is raised for a term outside
+// that range (|v| >= 4; a particle's terms are far smaller), which the
+// caller then converts the general way.
+__device__ __forceinline__ Fix to_fix_fast(double v, bool &big)
+{
+    const double x = v * kDepScale;
+    big |= !(fabs(x) < 2251799813685248.0);              // 2^51
+    return __double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000ll;
+}
 __device__ __forceinline__ Fix to_fix(double v) { return (Fix)llrint(v * kDepScale); }
 __device__ __forceinline__ void fix_add(Fix *p, Fix v)
 {
@@ -461,8 +475,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
                 for (int k = 0; k < 16; ++k) v[k] = 0;
             }
+            Fix fx[16];
+            bool big = false;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] += to_fix(vv[k]);
+            for (int k = 0; k < 16; ++k) fx[k] = to_fix_fast(vv[k], big);
+            if (big) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) fx[k] = to_fix(vv[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] += fx[k];
         }
         if (segment_sums(v, key) && key >= 0) flush_run(win, dst, (const Fix(*)[4])v, ci0, cj0, wx0, wy0, P);
     }

@@ -279,10 +279,12 @@ def test_hybrid_paper_hot_beam_cases(pic):
     assert 0.6 * want < rate < 1.6 * want
 
 
-@pytest.mark.parametrize("case", ["empty", "ragged", "one_tile_fast"])
+@pytest.mark.parametrize("case", ["empty", "ragged", "heavy", "one_tile_fast"])
 def test_hybrid_edge_cases(pic, case):
     """No particles (the potential stays 0); 1000 particles at random
-    positions (no whole wave, runs or tiles of them); an 8 x 8 grid (one
+    positions (no whole wave, runs or tiles of them); 16 heavy particles
+    (weight 6.4: deposit terms beyond the fast fixed-point conversion's
+    range, which take the general one); an 8 x 8 grid (one
     tile whose LDS windows alias the periodic grid) with a transverse spread
     of u_th = 2, so particles cross the box several times and leave their
     tile's window between sorts.  FP64 against the oracle after 50 steps."""
@@ -291,9 +293,9 @@ def test_hybrid_edge_cases(pic, case):
     if case == "empty":
         wl = replace(synth.H1, n=(32, 32), steps=50)
         x, u, uz = np.zeros((2, 0)), np.zeros((2, 0)), np.zeros(0)
-    elif case == "ragged":
+    elif case in ("ragged", "heavy"):
         wl = replace(synth.H1, n=(32, 32), steps=50)
-        N = 1000
+        N = 1000 if case == "ragged" else 16
         L = np.array(wl.n) * np.array(wl.d)
         x = rng.uniform(0, 1, (2, N)) * L[:, None]
         u = 0.2 * rng.standard_normal((2, N))
