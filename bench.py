@@ -80,6 +80,52 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 5):
                       "ms": ms, "GBs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def copy_ceiling(words: int = 1 << 27, reps: int = 5):
+    """Copy ceilings of the device for the particle kernel's access pattern:
+    pic_copy_probe over 1..8 arrays of `words` 4-byte words (one launch, each
+    lane copying its word of every array: one SoA stream per array, as the
+    particle state), and torch's own copy of one array of the same total size
+    for reference.  Bytes counted: read + written."""
+    import torch
+    from paper_0808_4078_amd import pic
+    out = {"words_per_array": words, "reps": reps, "pic_copy_probe_GBs": {}}
+    for na in (1, 2, 4, 6, 7, 8):
+        src = [torch.full((words,), float(k + 1), dtype=torch.float32, device="cuda") for k in range(na)]
+        dst = [torch.empty_like(t) for t in src]
+        pic.copy_probe(src, dst)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pic.copy_probe(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if not all(bool(torch.equal(a, b)) for a, b in zip(src, dst)):
+            raise RuntimeError("copy probe: destination differs from source")
+        out["pic_copy_probe_GBs"][str(na)] = 2 * 4 * words * na / (ms * 1e-3) / 1e9
+        progress(f"copy probe: {na} arrays of {words} words, {ms:.3f} ms, "
+                 f"{out['pic_copy_probe_GBs'][str(na)]:.0f} GB/s read + write")
+        del src, dst
+        torch.cuda.empty_cache()
+    a = torch.ones(7 * words, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["torch_copy_one_array_GBs"] = 2 * 4 * 7 * words / (ms * 1e-3) / 1e9
+    progress(f"torch copy of one array of {7 * words} words: {out['torch_copy_one_array_GBs']:.0f} GB/s")
+    print(json.dumps(out), flush=True)
+
+
 def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
     """Algorithmic HBM bytes of one particle-kernel launch.
 
@@ -438,6 +484,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 1 GiB copy that calibrates the HBM byte counters, then exit")
+    ap.add_argument("--copy-ceiling", action="store_true",
+                    help="measure the copy ceilings of the particle state's access pattern (pic_copy_probe) and exit")
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
@@ -466,6 +514,9 @@ def main():
         sys.exit(2)
     if a.copy_probe:
         copy_probe()
+        return
+    if a.copy_ceiling:
+        copy_ceiling()
         return
     import synth
     from dataclasses import replace

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_runtime.cpp", "pic_static.hip", "hyb_kernels.hip", "hyb_runtime.cpp"]
+SOURCES = ["pic_kernels.hip", "pic_runtime.cpp", "pic_static.hip", "pic_probe.hip", "hyb_kernels.hip", "hyb_runtime.cpp"]
 ARCH = "gfx950"
 
 # FP32 packed math is disabled: hipcc emits it from ordinary float code, and

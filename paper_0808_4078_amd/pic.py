@@ -107,7 +107,7 @@ EXPORTS = ["pic_query", "pic_init", "pic_load_particles", "pic_step", "pic_step_
            "pic_batch_step_profiled", "pic_batch_sync", "pic_batch_info", "pic_batch_launch_info",
            "pic_batch_diagnostics",
            "pic_batch_destroy", "pic_tune_query",
-           "pic_tune", "pic_tune_shape", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
+           "pic_tune", "pic_tune_shape", "pic_copy_probe", "pic_checkpoint", "pic_restore", "pic_hyb_query", "pic_hyb_init", "pic_hyb_step",
            "pic_hyb_step_profiled", "pic_hyb_sync", "pic_hyb_read_grid", "pic_hyb_read_particles",
            "pic_hyb_diag_history", "pic_hyb_last_error", "pic_hyb_destroy"]
 
@@ -180,6 +180,7 @@ def lib():
                                P(C.c_int32), P(C.c_double)]
         L.pic_tune_shape.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp,
                                      C.c_int32, P(C.c_int32), P(C.c_double)]
+        L.pic_copy_probe.argtypes = [P(vp), P(vp), C.c_int, C.c_int64, vp]
         L.pic_hyb_query.argtypes = [P(HybDesc), P(C.c_size_t), P(C.c_size_t)]
         L.pic_hyb_init.argtypes = [P(HybDesc), vp, C.c_size_t, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
         L.pic_hyb_step.argtypes = [vp, C.c_int32]
@@ -507,6 +508,23 @@ def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None
                           int(ws.numel()), C.c_void_p(st.cuda_stream), int(nsteps), C.byref(best), ms), "pic_tune")
     del ws
     return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}
+
+
+def copy_probe(src, dst, stream=None):
+    """pic_copy_probe: copy the 4-byte-word device tensors src[a] -> dst[a]
+    (equal sizes, at most 8) in one launch (asynchronous on the stream)."""
+    import torch
+    n = len(src)
+    if n != len(dst) or not 1 <= n <= 8:
+        raise ValueError("copy_probe: 1..8 source and destination tensors")
+    words = src[0].numel() * src[0].element_size() // 4
+    for t in list(src) + list(dst):
+        if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() != words * 4:
+            raise ValueError("copy_probe: contiguous device tensors of equal size")
+    sa = (C.c_void_p * n)(*[t.data_ptr() for t in src])
+    da = (C.c_void_p * n)(*[t.data_ptr() for t in dst])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().pic_copy_probe(sa, da, n, words, C.c_void_p(st.cuda_stream)), "pic_copy_probe")
 
 
 # pic_particle shapes (PIC_PARTICLE_SHAPES): threads per workgroup, particles in flight per lane
