@@ -80,33 +80,39 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 5):
                       "ms": ms, "GBs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+COPY_CHUNKS = (256, 1024, 4096, 32768)     # words per workgroup; 32768: a C3 tile's bin per species
+
+
 def copy_ceiling(words: int = 1 << 27, reps: int = 5):
     """Copy ceilings of the device for the particle kernel's access pattern:
-    pic_copy_probe over 1..8 arrays of `words` 4-byte words (one launch, each
-    lane copying its word of every array: one SoA stream per array, as the
-    particle state), and torch's own copy of one array of the same total size
-    for reference.  Bytes counted: read + written."""
+    pic_copy_probe over 1..8 arrays of `words` 4-byte words (one launch, one
+    SoA stream per array, as the particle state), with each workgroup
+    streaming chunks of 256 (one word per lane) to 32768 words (a C3 tile's
+    bin per species), and torch's own copy of one array of the same total
+    size for reference.  Bytes counted: read + written."""
     import torch
     from paper_0808_4078_amd import pic
     out = {"words_per_array": words, "reps": reps, "pic_copy_probe_GBs": {}}
     for na in (1, 2, 4, 6, 7, 8):
         src = [torch.full((words,), float(k + 1), dtype=torch.float32, device="cuda") for k in range(na)]
         dst = [torch.empty_like(t) for t in src]
-        pic.copy_probe(src, dst)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            pic.copy_probe(src, dst)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        if not all(bool(torch.equal(a, b)) for a, b in zip(src, dst)):
-            raise RuntimeError("copy probe: destination differs from source")
-        out["pic_copy_probe_GBs"][str(na)] = 2 * 4 * words * na / (ms * 1e-3) / 1e9
-        progress(f"copy probe: {na} arrays of {words} words, {ms:.3f} ms, "
-                 f"{out['pic_copy_probe_GBs'][str(na)]:.0f} GB/s read + write")
+        for chunk in COPY_CHUNKS if na == 7 else COPY_CHUNKS[:1]:
+            pic.copy_probe(src, dst, chunk=chunk)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pic.copy_probe(src, dst, chunk=chunk)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if not all(bool(torch.equal(a, b)) for a, b in zip(src, dst)):
+                raise RuntimeError("copy probe: destination differs from source")
+            gbs = 2 * 4 * words * na / (ms * 1e-3) / 1e9
+            out["pic_copy_probe_GBs"][f"{na} arrays, chunk {chunk}"] = gbs
+            progress(f"copy probe: {na} arrays of {words} words, chunks of {chunk}: {ms:.3f} ms, "
+                     f"{gbs:.0f} GB/s read + write")
         del src, dst
         torch.cuda.empty_cache()
     a = torch.ones(7 * words, dtype=torch.float32, device="cuda")

@@ -393,14 +393,18 @@ int pic_init_static_scratch(const pic_grid_desc *grid, const pic_species_desc *s
 const char *pic_status_string(int status);
 
 /* Bandwidth probe (measurement only, no part of a step): copies `narrays`
- * (1..8) device arrays of n 4-byte words, src[a] -> dst[a], in one launch
- * whose lanes read and write 4-byte words of every array in turn -- the
- * access pattern of the particle kernel's state streams without its
- * arithmetic, binning or LDS work -- so its rate is the practical copy
- * ceiling of that pattern.  src and dst are host arrays of device pointers;
- * the arrays must not overlap.  Asynchronous on `hip_stream`.  Errors:
- * INVALID_ARG (NULL, narrays out of range, n < 0), HIP. */
-int pic_copy_probe(const void *const *src, void *const *dst, int narrays, int64_t n, void *hip_stream);
+ * (1..8) device arrays of n 4-byte words, src[a] -> dst[a], in one launch of
+ * workgroups of 256 lanes, workgroup b copying words [b chunk, (b+1) chunk)
+ * of every array, 256 consecutive words at a time -- the access pattern of
+ * the particle kernel's state streams (a workgroup per tile's bin) without
+ * its arithmetic, binning or LDS work -- so its rate is the practical copy
+ * ceiling of that pattern at that chunk length (chunk = 256: one word of
+ * each array per lane).  src and dst are host arrays of device pointers; the
+ * arrays must not overlap.  Asynchronous on `hip_stream`.  Errors:
+ * INVALID_ARG (NULL, narrays out of range, n < 0, chunk not a positive
+ * multiple of 256), HIP. */
+int pic_copy_probe(const void *const *src, void *const *dst, int narrays, int64_t n, int64_t chunk,
+                   void *hip_stream);
 
 /* Copies the last error message of the handle (or of the last failed
  * pic_init / pic_query when run is NULL) into buf. */

@@ -668,20 +668,21 @@ extern "C" {
 
 namespace pic {
 hipError_t launch_copy_probe(const uint32_t *const *src, uint32_t *const *dst, int narrays, int64_t n,
-                             hipStream_t st);    // pic_probe.hip
+                             int64_t chunk, hipStream_t st);    // pic_probe.hip
 }
 
 extern "C" {
 
-int pic_copy_probe(const void *const *src, void *const *dst, int narrays, int64_t n, void *hip_stream)
+int pic_copy_probe(const void *const *src, void *const *dst, int narrays, int64_t n, int64_t chunk,
+                   void *hip_stream)
 {
-    if (!src || !dst || narrays < 1 || narrays > 8 || n < 0)
+    if (!src || !dst || narrays < 1 || narrays > 8 || n < 0 || chunk < 256 || chunk % 256)
         return fail(nullptr, PIC_E_INVALID_ARG, "copy probe: bad argument");
     for (int k = 0; k < narrays; ++k)
         if (!src[k] || !dst[k]) return fail(nullptr, PIC_E_INVALID_ARG, "copy probe: NULL array %d", k);
     if (n == 0) return PIC_OK;
     const hipError_t e = pic::launch_copy_probe((const uint32_t *const *)src, (uint32_t *const *)dst, narrays, n,
-                                                (hipStream_t)hip_stream);
+                                                chunk, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, PIC_E_HIP, "copy probe: %s", hipGetErrorString(e));
     return PIC_OK;
 }

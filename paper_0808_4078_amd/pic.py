@@ -180,7 +180,7 @@ def lib():
                                P(C.c_int32), P(C.c_double)]
         L.pic_tune_shape.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, C.c_int32, vp, C.c_size_t, vp,
                                      C.c_int32, P(C.c_int32), P(C.c_double)]
-        L.pic_copy_probe.argtypes = [P(vp), P(vp), C.c_int, C.c_int64, vp]
+        L.pic_copy_probe.argtypes = [P(vp), P(vp), C.c_int, C.c_int64, C.c_int64, vp]
         L.pic_hyb_query.argtypes = [P(HybDesc), P(C.c_size_t), P(C.c_size_t)]
         L.pic_hyb_init.argtypes = [P(HybDesc), vp, C.c_size_t, vp, C.c_size_t, vp, vp, vp, vp, vp, vp, P(vp)]
         L.pic_hyb_step.argtypes = [vp, C.c_int32]
@@ -510,9 +510,10 @@ def tune(grid: GridDesc, species, nsteps: int = 10, copies: int = 1, stream=None
     return int(best.value), {e: ms[k] for k, e in enumerate((8, 16, 32)) if ms[k] >= 0}
 
 
-def copy_probe(src, dst, stream=None):
+def copy_probe(src, dst, chunk: int = 256, stream=None):
     """pic_copy_probe: copy the 4-byte-word device tensors src[a] -> dst[a]
-    (equal sizes, at most 8) in one launch (asynchronous on the stream)."""
+    (equal sizes, at most 8) in one launch, a workgroup per `chunk` words of
+    every array (asynchronous on the stream)."""
     import torch
     n = len(src)
     if n != len(dst) or not 1 <= n <= 8:
@@ -524,7 +525,7 @@ def copy_probe(src, dst, stream=None):
     sa = (C.c_void_p * n)(*[t.data_ptr() for t in src])
     da = (C.c_void_p * n)(*[t.data_ptr() for t in dst])
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().pic_copy_probe(sa, da, n, words, C.c_void_p(st.cuda_stream)), "pic_copy_probe")
+    _check(lib().pic_copy_probe(sa, da, n, words, int(chunk), C.c_void_p(st.cuda_stream)), "pic_copy_probe")
 
 
 # pic_particle shapes (PIC_PARTICLE_SHAPES): threads per workgroup, particles in flight per lane

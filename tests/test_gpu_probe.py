@@ -14,14 +14,15 @@ def pic():
     return p
 
 
-@pytest.mark.parametrize("narrays,words", [(1, 1), (3, 1000003), (7, 4097), (8, 65536 * 257 + 5)])
-def test_copy_probe_copies_every_word(pic, narrays, words):
+@pytest.mark.parametrize("narrays,words,chunk", [(1, 1, 256), (3, 1000003, 256), (7, 4097, 1024),
+                                                 (8, 65536 * 257 + 5, 32768), (2, 100, 4096)])
+def test_copy_probe_copies_every_word(pic, narrays, words, chunk):
     import torch
     g = torch.Generator(device="cuda").manual_seed(narrays)
     src = [torch.randint(-2 ** 31, 2 ** 31 - 1, (words,), dtype=torch.int32, device="cuda", generator=g)
            for _ in range(narrays)]
     dst = [torch.zeros_like(t) for t in src]
-    pic.copy_probe(src, dst)
+    pic.copy_probe(src, dst, chunk=chunk)
     torch.cuda.synchronize()
     assert all(bool(torch.equal(a, b)) for a, b in zip(src, dst))
 
@@ -33,12 +34,14 @@ def test_copy_probe_rejects_bad_arguments(pic):
     arr_a = (C.c_void_p * 9)(*([a.data_ptr()] * 9))
     arr_b = (C.c_void_p * 9)(*([b.data_ptr()] * 9))
     L = pic.lib()
-    assert L.pic_copy_probe(arr_a, arr_b, 0, 16, None) == pic.PIC_E_INVALID_ARG
-    assert L.pic_copy_probe(arr_a, arr_b, 9, 16, None) == pic.PIC_E_INVALID_ARG
-    assert L.pic_copy_probe(arr_a, arr_b, 1, -1, None) == pic.PIC_E_INVALID_ARG
-    assert L.pic_copy_probe(None, arr_b, 1, 16, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 0, 16, 256, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 9, 16, 256, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 1, -1, 256, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 1, 16, 100, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 1, 16, 0, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(None, arr_b, 1, 16, 256, None) == pic.PIC_E_INVALID_ARG
     nul = (C.c_void_p * 1)(None)
-    assert L.pic_copy_probe(nul, arr_b, 1, 16, None) == pic.PIC_E_INVALID_ARG
-    assert L.pic_copy_probe(arr_a, arr_b, 1, 0, None) == 0
+    assert L.pic_copy_probe(nul, arr_b, 1, 16, 256, None) == pic.PIC_E_INVALID_ARG
+    assert L.pic_copy_probe(arr_a, arr_b, 1, 0, 256, None) == 0
     with pytest.raises(ValueError):
         pic.copy_probe([a], [torch.zeros(8, dtype=torch.int32, device="cuda")])
