@@ -188,8 +188,9 @@ __device__ __forceinline__ void fix_add(Fix *p, Fix v)
 }
 
 // Adds the four quantities acc[k][n] of one cell's run of particles (node n
-// of cell (i0, j0)) into the tile's LDS window when the cell lies inside it,
-// else straight into the global deposit.
+// of cell (i0, j0)) into the tile's LDS window when the cell lies inside it
+// (unconditionally: a run's sums are almost never exactly zero), else
+// straight into the global deposit.
 __device__ __forceinline__ void flush_run(Fix (*win)[kWin * kWin], Fix *const *dst, const Fix acc[4][4],
                                           int i0, int j0, int wx0, int wy0, const Params &P)
 {
@@ -198,10 +199,10 @@ __device__ __forceinline__ void flush_run(Fix (*win)[kWin * kWin], Fix *const *d
         const int e = dj * kWin + di;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            fix_add(&win[k][e], acc[k][0]);
-            fix_add(&win[k][e + 1], acc[k][1]);
-            fix_add(&win[k][e + kWin], acc[k][2]);
-            fix_add(&win[k][e + kWin + 1], acc[k][3]);
+            atomicAdd((unsigned long long *)&win[k][e], (unsigned long long)acc[k][0]);
+            atomicAdd((unsigned long long *)&win[k][e + 1], (unsigned long long)acc[k][1]);
+            atomicAdd((unsigned long long *)&win[k][e + kWin], (unsigned long long)acc[k][2]);
+            atomicAdd((unsigned long long *)&win[k][e + kWin + 1], (unsigned long long)acc[k][3]);
         }
     } else {
         const int i1 = wrapi(i0 + 1, P.nx), j1 = wrapi(j0 + 1, P.ny);
