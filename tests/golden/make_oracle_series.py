@@ -14,6 +14,11 @@ Two families:
   the Weibel / resistive filamentation of the beam (theory part; field-energy
   diagnostic of the 2D PIC paragraph), against which the GPU's mixed and
   FP64 paths are compared.
+* ``c3full``: the headline workload itself (C3: 1024^2 cells, 64 particles
+  per cell per species, 134 217 728 particles) for 800 steps, through the
+  linear filamentation (t ~ 25 to 65) into saturation: the full-size series
+  the GPU's mixed and FP64 runs of the benchmark workload are compared with
+  (about two hours of host time on 8 cores).
 * ``paper-a`` .. ``paper-d``: the four 2D cases of the paper at its own
   parameters (2D PIC paragraph; captions of Figs. 1-2): 160^2 cells of
   0.125 c/w_p, 64 particles per cell per species, v_b = 0.9 c, n_p/n_b = 9,
@@ -27,7 +32,7 @@ The paper cases also store, every 50 steps, the transverse magnetic energy
 spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
-Usage: python tests/golden/make_oracle_series.py [c3phys] [paper-a] ...
+Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [paper-a] ...
 (no argument: all; ``annotate`` only rewrites the fit line of the c3phys
 header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
@@ -53,6 +58,10 @@ import synth  # noqa: E402
 C3PHYS = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=1000,
                            name="c3phys-256")
 C3PHYS_DIAG = 10
+
+# The headline workload at its full size, through its linear phase.
+C3FULL = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
+                           name="c3-1024")
 
 # The paper's four 2D cases.
 PAPER_N, PAPER_DX, PAPER_DT = 160, 0.125, 0.0625
@@ -106,8 +115,7 @@ def _rec_line(r, dt):
             f"{r['collisions']}")
 
 
-def run_c3phys(path):
-    wl = C3PHYS
+def run_c3phys(path, wl=C3PHYS):
     parts = synth.load(wl)
     orc = oracle.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, _species(wl, parts), wl.seed, 0)
     lines = _header(wl, C3PHYS_DIAG)
@@ -118,10 +126,14 @@ def run_c3phys(path):
             lines.append(_rec_line(recs[0], wl.dt))
             if s % 100 == 0:
                 r = recs[0]
-                print(f"c3phys step {s} W_Bperp {r['W'][3] + r['W'][4]:.4e} ({time.time() - t0:.0f} s)",
+                print(f"{wl.name} step {s} W_Bperp {r['W'][3] + r['W'][4]:.4e} ({time.time() - t0:.0f} s)",
                       flush=True)
+                with open(path + ".part", "w") as fh:          # progress, for runs of hours
+                    fh.write("\n".join(lines) + "\n")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    if os.path.exists(path + ".part"):
+        os.remove(path + ".part")
 
 
 def run_paper(case, path_w, path_m):
@@ -170,13 +182,16 @@ def annotate_c3phys(path):
 
 
 def main(argv):
-    which = argv or ["c3phys"] + [f"paper-{c}" for c in PAPER_CASES]
+    which = argv or ["c3phys"] + [f"paper-{c}" for c in PAPER_CASES] + ["c3full"]
     for w in which:
         if w == "c3phys":
             run_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w == "annotate":
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "c3full":
+            run_c3phys(os.path.join(HERE, "oracle_c3_1024.txt"), C3FULL)
+            annotate_c3phys(os.path.join(HERE, "oracle_c3_1024.txt"))
         elif w.startswith("paper-"):
             c = w.split("-", 1)[1]
             run_paper(c, os.path.join(HERE, f"oracle_paper_{c}_energy.txt"),
