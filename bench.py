@@ -162,7 +162,7 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
 # partials.  The kernel's own count of what its layout moves,
 # particle_kernel_bytes() (a 16-bit in-tile cell; the id written back as
 # well), is reported beside it.
-SURVEY_BYTES_PER_PARTICLE_STEP = 51.1
+MODEL_BYTES_PER_PARTICLE_STEP = 51.1
 
 GOLDEN_C3PHYS = os.path.join(ROOT, "tests", "golden", "oracle_c3phys_256.txt")
 
@@ -543,7 +543,7 @@ def main():
     value = n / (ms_step * 1e-3)
     pk_ms = mixed["groups_ms"]["particle"] / a.steps
     pk_bytes = particle_kernel_bytes(wl, "mixed", a.tile)
-    model_bytes = SURVEY_BYTES_PER_PARTICLE_STEP * n
+    model_bytes = MODEL_BYTES_PER_PARTICLE_STEP * n
     achieved = model_bytes / (pk_ms * 1e-3) / 1e9
     rec = {
         "metric": METRIC,
@@ -574,7 +574,7 @@ def main():
         },
         "particle_kernel": {"ms": pk_ms, "particle_steps_per_s": n / (pk_ms * 1e-3),
                             "algorithmic_bytes": model_bytes,
-                            "bytes_per_particle_step": SURVEY_BYTES_PER_PARTICLE_STEP,
+                            "bytes_per_particle_step": MODEL_BYTES_PER_PARTICLE_STEP,
                             "kernel_count_bytes": pk_bytes,
                             "kernel_count_GBs": pk_bytes / (pk_ms * 1e-3) / 1e9,
                             "kernel_count_frac": pk_bytes / (pk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
