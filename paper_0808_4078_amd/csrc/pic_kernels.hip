@@ -2519,8 +2519,8 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, Launcher &L
 }
 
 // The tile current is accumulated in FP64 in LDS in both modes: on gfx950 an
-// FP32 LDS atomic add (ds_add_f32) measured 5.4x slower than the FP64 one
-// (ds_add_f64) in this kernel (C3, 14.7 ms against 2.7 ms per launch).  The
+// FP32 LDS atomic add (ds_add_f32) measured about 4x slower than the FP64
+// one (ds_add_f64) in this kernel (C3: 6.1 ms against 1.6 ms per launch).  The
 // partial written to HBM is in the run's precision (FP32 in mixed mode).
 template <typename R>
 static hipError_t step_prec(const KParams &hp, const KParams *dp, Launcher &L)
