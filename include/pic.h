@@ -7,8 +7,11 @@
  * neutralising ion background (problem statement at the start of the theory
  * part; the 2D and 3D PIC-simulation paragraphs).  One step is: field gather,
  * relativistic Boris push, charge-conserving (Esirkepov) current deposit,
- * isotropic scattering of collisional species off the ions (whose fluid
- * limit is the drag term of Eq. (3)), and a Yee update of E and B.
+ * scattering of collisional species off the ions (isotropic at a fixed rate,
+ * whose fluid limit is the drag term of Eq. (3), or Coulomb small-angle),
+ * optional binary electron-electron collisions within each cell, and a Yee
+ * update of E and B.  The paper's reduced quasi-neutral model has its own
+ * entry points (pic_hyb_*, at the end).
  *
  * Units are normalised: t in 1/w_p, x in c/w_p, u = gamma v/c, fields
  * eF/(m c w_p) (the normalisation of the paper's field-energy diagnostic),
