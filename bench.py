@@ -507,6 +507,8 @@ def main():
                     help="also time K steps of C3 with the plasma on the Coulomb scattering model (0 = skip)")
     ap.add_argument("--binary", type=int, default=50, metavar="K",
                     help="also time K steps of C3 with binary electron-electron collisions (mixed; 0 = skip)")
+    ap.add_argument("--paper", type=int, default=500, metavar="K",
+                    help="also time K steps of the paper's 2D case (d) at its own parameters (0: skip)")
     ap.add_argument("--hybrid", type=int, default=200, metavar="K",
                     help="also time K steps of the reduced quasi-neutral model on 1024^2 nodes (FP64; 0 = skip)")
     ap.add_argument("--no-c3-error", dest="c3_error", action="store_false",
@@ -641,6 +643,25 @@ def main():
                          "ms_per_step": bm["ms"] / a.binary,
                          "pairs_last_record": bm["diag"]["ee_pairs"] if bm["diag"] else None,
                          "step_breakdown_ms": {k: v / a.binary for k, v in bm["groups_ms"].items()}}
+    if a.paper > 0:
+        # the paper's collisional hot-beam case (d): 160^2 cells of 0.125 c/w_p, 64 ppc per species,
+        # v_b = 0.9 c, u_th = 0.37, nu = 0.15, dt = 0.0625 (2011 steps to T = 20 plasma periods)
+        import math
+        u_b = 0.9 / math.sqrt(1.0 - 0.81)
+        wp = synth.beam_plasma((160, 160), d=(0.125, 0.125), dt=0.0625, steps=a.paper, ppc=64, u_th_beam=0.37,
+                               nu=0.15, u_beam=u_b, name="paper-d")
+        from paper_0808_4078_amd import pic
+        gt, st = pic.workload_descs(wp, precision=pic.PIC_PREC_MIXED)
+        ptile, ptile_ms = pic.tune(gt, st, nsteps=10)
+        pm = run_gpu(wp, "mixed", a.paper, min(a.warmup, 5), ptile, a.diag_every, shape=0)
+        rec["paper_d"] = {"workload": "the paper's 2D case (d): 160x160 cells, dx=0.125, dt=0.0625, 64 ppc per "
+                                      "species, v_b=0.9c, u_th=0.37, nu=0.15, mixed precision",
+                          "tile": ptile, "tile_ms_per_step": {str(k): v for k, v in ptile_ms.items()},
+                          "particles": pm["particles"], "steps": a.paper,
+                          "value": pm["particles"] / (pm["ms"] / a.paper * 1e-3),
+                          "ms_per_step": pm["ms"] / a.paper,
+                          "steps_to_T20_s": pm["ms"] / a.paper * 2011 * 1e-3,
+                          "step_breakdown_ms": {k: v / a.paper for k, v in pm["groups_ms"].items()}}
     if a.hybrid > 0:
         rec["hybrid"] = run_hybrid(a.hybrid, a.warmup, a.diag_every)
     if a.c5 > 0:
