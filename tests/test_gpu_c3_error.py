@@ -29,6 +29,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_c3phys_256.txt")
 C3PHYS = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=1000,
                            name="c3phys-256")
+GOLDEN_FULL = os.path.join(os.path.dirname(__file__), "golden", "oracle_c3_1024.txt")
+C3FULL = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
+                           name="c3-1024")
 
 
 @pytest.fixture(scope="module")
@@ -38,8 +41,8 @@ def pic():
     return p
 
 
-def oracle_series():
-    o = np.loadtxt(GOLDEN)
+def oracle_series(path=GOLDEN):
+    o = np.loadtxt(path)
     return dict(step=o[:, 0].astype(int), t=o[:, 1], W=o[:, 2:8], K=o[:, 8:10], coll=o[:, 12].astype(int))
 
 
@@ -82,3 +85,50 @@ def test_c3_physics_against_the_oracle_series(pic, prec, w_bar, k_bar, rate_bar)
     assert Wbo[-1] > 1e3 * Wbo[1]                # saturated far above the initial noise
     assert w_err < w_bar and k_err < k_bar
     assert abs(rate_g / rate_o - 1) < rate_bar
+
+
+# measured on one MI355X: mixed W_i 2.5e-6, K 1.2e-7, rate 5e-8; FP64 W_i
+# 2.8e-13, K 4.4e-14, rate 7e-16.
+def test_c3_full_size_against_the_oracle_series(pic):
+    """The benchmark workload itself at its full size (C3 / C2: 1024^2
+    cells, 64 particles per cell per species, 134 217 728 particles), in
+    the launch configuration bench.py times (tile 16, 300% store reserve,
+    graph replay, diagnostics every 10 steps), against the FP64 oracle's
+    800-step series from the same seeded particles
+    (tests/golden/oracle_c3_1024.txt): every record's six field energies and
+    two kinetic energies, the scattering counts, and the growth rate of the
+    transverse magnetic energy over the oracle's linear window; mixed to the
+    mixed path's field bar, FP64 to 1e-9."""
+    import bench
+    o = oracle_series(GOLDEN_FULL)
+    parts = synth.load(C3FULL)
+    Wbo = o["W"][:, 3] + o["W"][:, 4]
+    win = growth_window(o["t"], Wbo)
+    rate_o = theory.fit_growth_rate(o["t"], Wbo, win)
+    assert o["t"][win[0]] > 15 and o["t"][win[1] - 1] < 80 and win[1] - win[0] >= 15
+    assert 0.05 < rate_o < 0.12 and Wbo[-1] > 1e3 * Wbo[1]
+    for prec, w_bar, k_bar, rate_bar in (("mixed", 1e-3, 1e-6, 1e-4), ("fp64", 1e-9, 1e-11, 1e-9)):
+        log(f"case c3 full size 1024^2 x 800 steps {prec}")
+        p = pic.PIC_PREC_FP64 if prec == "fp64" else pic.PIC_PREC_MIXED
+        g, sp = pic.workload_descs(C3FULL, precision=p, tile=16, diag_every=10, reserve=bench.RESERVE_2D,
+                                   flags=pic.PIC_FLAG_HOST_LOAD | pic.PIC_FLAG_TRACK_IDS)
+        r = pic.Run(g, sp)
+        for s_, q in enumerate(parts):
+            r.load_particles(s_, q.x, q.u, q.id)
+        r.step(C3FULL.steps)
+        h = r.history()
+        info = r.info()
+        r.close()
+        assert info["graph"] == 1 and info["graph_launches"] == C3FULL.steps
+        assert [x["step"] for x in h] == list(o["step"])
+        assert [x["collisions"] for x in h] == list(o["coll"])
+        W = np.array([x["W"] for x in h])
+        K = np.array([x["kinetic"][:2] for x in h])
+        w_err = float(np.max(np.abs(W - o["W"])[1:] / np.abs(o["W"])[1:]))
+        k_err = float(np.max(np.abs(K - o["K"]) / o["K"]))
+        rate_g = theory.fit_growth_rate(o["t"], W[:, 3] + W[:, 4], win)
+        log(f"  worst record: W_i {w_err:.2e}, kinetic {k_err:.2e}; growth rate over t = "
+            f"{o['t'][win[0]]:.0f}..{o['t'][win[1] - 1]:.0f}: gpu {rate_g:.6f} oracle {rate_o:.6f} "
+            f"({rate_g / rate_o - 1:.1e})")
+        assert w_err < w_bar and k_err < k_bar
+        assert abs(rate_g / rate_o - 1) < rate_bar
