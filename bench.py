@@ -164,33 +164,34 @@ def particle_kernel_bytes(wl, precision: str, tile: int) -> float:
 # well), is reported beside it.
 MODEL_BYTES_PER_PARTICLE_STEP = 51.1
 
-GOLDEN_C3PHYS = os.path.join(ROOT, "tests", "golden", "oracle_c3phys_256.txt")
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "oracle_c3_1024.txt")
 
 
 def c3_error(log_every: int = 10):
-    """The headline physics on a 256^2 box over 1000 steps (the 1024^2
-    workload's per-cell load, seed and physics), stepped on the GPU in mixed
-    precision and in FP64 from the same host-loaded particles as the stored
-    FP64-oracle series (tests/golden/oracle_c3phys_256.txt, written by the
-    oracle alone): the worst per-record relative error of the six field
-    energies W_i and of the kinetic energies, and the growth rate of the
-    transverse magnetic energy over the oracle's linear window (a
-    least-squares fit of ln W), against the oracle's."""
+    """C3 itself (1024^2, 64 ppc per species, 134 217 728 particles) over 800
+    steps, in the launch configuration of the timed line (tile 16, the
+    store reserve, graph replay), stepped on the GPU in mixed precision and
+    in FP64 from the same host-loaded particles as the stored FP64-oracle
+    series (tests/golden/oracle_c3_1024.txt, written by the oracle alone):
+    the worst per-record relative error of the six field energies W_i and
+    of the kinetic energies, and the growth rate of the transverse magnetic
+    energy over the oracle's linear window (a least-squares fit of ln W),
+    against the oracle's."""
     import numpy as np
     import synth
     from paper_0808_4078_amd import pic
-    header = [ln for ln in open(GOLDEN_C3PHYS) if ln.startswith("# fit:")][0].split()
+    header = [ln for ln in open(GOLDEN_C3) if ln.startswith("# fit:")][0].split()
     a, b, rate_o = int(header[4]), int(header[5]), float(header[-1])
-    o = np.loadtxt(GOLDEN_C3PHYS)
+    o = np.loadtxt(GOLDEN_C3)
     t, Wo, Ko = o[:, 1], o[:, 2:8], o[:, 8:10]
-    wl = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=1000,
-                           name="c3phys-256")
+    wl = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
+                           name="c3-1024")
     parts = synth.load(wl)
-    out = {"workload": "the headline physics on 256x256 (64 ppc per species, 8388608 particles), 1000 steps, "
-                       "records every 10 steps, same initial particles as the FP64 oracle series",
+    out = {"workload": "C3 (1024x1024, 64 ppc per species, 134217728 particles), 800 steps, records every "
+                       "10 steps, same initial particles as the FP64 oracle series",
            "oracle_growth_rate": rate_o, "fit_window_t": [float(t[a]), float(t[b - 1])]}
     for name, prec in (("mixed", pic.PIC_PREC_MIXED), ("fp64", pic.PIC_PREC_FP64)):
-        g, sp = pic.workload_descs(wl, precision=prec, diag_every=log_every,
+        g, sp = pic.workload_descs(wl, precision=prec, tile=16, diag_every=log_every, reserve=RESERVE_2D,
                                    flags=pic.PIC_FLAG_HOST_LOAD | pic.PIC_FLAG_TRACK_IDS)
         run = pic.Run(g, sp)
         for s_, p_ in enumerate(parts):
@@ -205,8 +206,8 @@ def c3_error(log_every: int = 10):
         out[name] = {"W_rel_err_max": float(np.max(np.abs(W - Wo)[1:] / np.abs(Wo)[1:])),
                      "kinetic_rel_err_max": float(np.max(np.abs(K - Ko) / Ko)),
                      "growth_rate": rate, "growth_rate_rel_err": rate / rate_o - 1.0}
-        progress(f"C3 physics 256^2 {name}: worst W_i error {out[name]['W_rel_err_max']:.2e}, growth rate "
-                 f"{rate:.6f} vs oracle {rate_o:.6f}")
+        progress(f"C3 1024^2 vs the oracle series, {name}: worst W_i error {out[name]['W_rel_err_max']:.2e}, "
+                 f"growth rate {rate:.6f} vs oracle {rate_o:.6f}")
     return out
 
 
