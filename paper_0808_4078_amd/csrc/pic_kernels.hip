@@ -494,7 +494,10 @@ constexpr int kMoverStage = sizeof(R) == 4 ? (D == 3 ? 24 : 64) : 1;
 // CB: the kernel carries the Coulomb scattering branch (runs with a species on
 // that model); without it the branch and its registers are compiled out.
 // SH: launch shape (kBlock threads, kBatch particles in flight per lane).
-template <typename R, typename A, int D, int T, bool CB, int SH, typename KP>
+// BS: the field stage issues all of a thread's loads before its LDS writes
+// (one workgroup per tile); the persistent batched kernel keeps the plain
+// loop, whose registers do not add to those it holds across work items.
+template <typename R, typename A, int D, int T, bool CB, int SH, bool BS, typename KP>
 __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
 {
     constexpr int kBlock = kShapeBlock[SH];
@@ -553,32 +556,38 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         const GLB R *F = gbl((const R *)kp->F);
         const int64_t plane = kp->g.cells;
         constexpr int NS = 6 * NF_D;
-        constexpr int NIT = (NS + kBlock - 1) / kBlock;
-        R fv[NIT];
-#pragma unroll
-        for (int k = 0; k < NIT; ++k) {
-            const int i = threadIdx.x + k * kBlock;
-            fv[k] = R(0);
-            if ((k + 1) * kBlock <= NS || i < NS) {
-                const int c = i / NF_D, r = i - c * NF_D;
-                const int lx = r % NF, ly = (r / NF) % NF, lz = D == 3 ? r / (NF * NF) : 0;
-                int gx = t0[0] - 1 + lx, gy = t0[1] - 1 + ly, gz = D == 3 ? t0[2] - 1 + lz : 0;
-                gx += gx < 0 ? n[0] : 0;
-                gx -= gx >= n[0] ? n[0] : 0;
-                gy += gy < 0 ? n[1] : 0;
-                gy -= gy >= n[1] ? n[1] : 0;
-                if constexpr (D == 3) {
-                    gz += gz < 0 ? n[2] : 0;
-                    gz -= gz >= n[2] ? n[2] : 0;
-                }
-                fv[k] = F[c * plane + ((int64_t)gz * n[1] + gy) * n[0] + gx];
+        auto src_of = [&](int i) {
+            const int c = i / NF_D, r = i - c * NF_D;
+            const int lx = r % NF, ly = (r / NF) % NF, lz = D == 3 ? r / (NF * NF) : 0;
+            int gx = t0[0] - 1 + lx, gy = t0[1] - 1 + ly, gz = D == 3 ? t0[2] - 1 + lz : 0;
+            gx += gx < 0 ? n[0] : 0;
+            gx -= gx >= n[0] ? n[0] : 0;
+            gy += gy < 0 ? n[1] : 0;
+            gy -= gy >= n[1] ? n[1] : 0;
+            if constexpr (D == 3) {
+                gz += gz < 0 ? n[2] : 0;
+                gz -= gz >= n[2] ? n[2] : 0;
             }
-        }
-        for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) sJ[i] = A(0);
+            return c * plane + ((int64_t)gz * n[1] + gy) * n[0] + gx;
+        };
+        if constexpr (BS) {
+            constexpr int NIT = (NS + kBlock - 1) / kBlock;
+            R fv[NIT];
 #pragma unroll
-        for (int k = 0; k < NIT; ++k) {
-            const int i = threadIdx.x + k * kBlock;
-            if ((k + 1) * kBlock <= NS || i < NS) sF[i] = fv[k];
+            for (int k = 0; k < NIT; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                fv[k] = R(0);
+                if ((k + 1) * kBlock <= NS || i < NS) fv[k] = F[src_of(i)];
+            }
+            for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) sJ[i] = A(0);
+#pragma unroll
+            for (int k = 0; k < NIT; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                if ((k + 1) * kBlock <= NS || i < NS) sF[i] = fv[k];
+            }
+        } else {
+            for (int i = threadIdx.x; i < NS; i += kBlock) sF[i] = F[src_of(i)];
+            for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) sJ[i] = A(0);
         }
     }
     __syncthreads();
@@ -2246,7 +2255,7 @@ template <typename R, typename A, int D, int T, bool CB, int SH>
 __global__ __launch_bounds__(kShapeBlock[SH]) void k_particle(const KParams *__restrict__ kp)
 {
     const KParamsC *kc = (const KParamsC *)kp;
-    particle_body<R, A, D, T, CB, SH>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
+    particle_body<R, A, D, T, CB, SH, true>(kc, wave_uniform(kc->order[blockIdx.x]), 0);
 }
 
 // Persistent: workgroup w (on XCD w mod 8) takes the items of its XCD
@@ -2273,7 +2282,7 @@ __global__ __launch_bounds__(kShapeBlock[SH]) void kb_particle(const BatchTable 
             if (i >= len) break;
             const int2 it = items[i];
             const KParamsC *kp = (const KParamsC *)wave_uniform_ptr(bt->kp[wave_uniform(it.x)]);
-            particle_body<R, A, D, T, CB, SH>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
+            particle_body<R, A, D, T, CB, SH, false>(kp, wave_uniform(kp->order[wave_uniform(it.y)]), 0);
         }
     }
 }
