@@ -130,7 +130,7 @@ enum {
  *             new momentum with probability w_small/w_large; Nanbu and
  *             Yonemura 1998).  nu_ee = 0: off.  With nu_ee > 0, ee_vref must
  *             be in (0, 1) and the participants need ids (they are tracked).
- *             Limit: 4096 participants in one cell (PIC_E_CAPACITY beyond);
+ *             Limit: 2048 participants in one cell (PIC_E_CAPACITY beyond);
  *             not available in ensembles.
  *   shape     particle-kernel launch shape, 0..PIC_PARTICLE_SHAPES-1 (0 for
  *             FP64 runs).  A launch choice, not part of the run's state:

@@ -89,7 +89,7 @@ def test_binary_triples_and_plasma_only(pic):
 
 
 def test_binary_capacity_limit_is_reported(pic):
-    """More than 4096 participants in one cell: the run reports
+    """More than 2048 participants in one cell: the run reports
     PIC_E_CAPACITY at the next synchronising call (the kernel leaves that
     cell alone and finishes normally)."""
     log("case binary collisions capacity")
