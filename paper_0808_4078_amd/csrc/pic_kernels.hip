@@ -519,7 +519,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
     constexpr int MW = D + 5;                            // cell, offsets, momenta, id
     __shared__ int sMt[kBlock / 64][MS];
     __shared__ uint32_t sMw[kBlock / 64][MW][MS];
-    __shared__ uint32_t s_front;
+    __shared__ uint32_t s_front[kMaxSpecies];           // stayers written to the front of each species' bin
     __shared__ double sred[kBlock / 64][kTileDiag];
 
     const int tile = bid;
@@ -590,6 +590,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             for (int i = threadIdx.x; i < 3 * NJ_D; i += kBlock) sJ[i] = A(0);
         }
     }
+    if (threadIdx.x < kMaxSpecies) s_front[threadIdx.x] = 0;
     __syncthreads();
 
     const R *sEx = sF, *sEy = sF + NF_D, *sEz = sF + 2 * NF_D;
@@ -636,9 +637,6 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         GLB R *__restrict__ ou1 = gbl((R *)S.u[dst][1]);
         GLB R *__restrict__ ou2 = gbl((R *)S.u[dst][2]);
         GLB uint32_t *__restrict__ oid = gbl(S.id[dst]);
-
-        if (threadIdx.x == 0) s_front = 0;
-        __syncthreads();
 
         // Raw fields of one particle as stored.  Each lane holds the next
         // kBatch particles (k, k+256, ...): before processing the oldest it
@@ -1002,7 +1000,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
             if (smask) {
                 const int leader = __ffsll((unsigned long long)smask) - 1;
                 uint32_t bfront = 0;
-                if (lane == leader) bfront = atomicAdd(&s_front, (uint32_t)__popcll(smask));
+                if (lane == leader) bfront = atomicAdd(&s_front[s], (uint32_t)__popcll(smask));
                 bfront = __builtin_amdgcn_readlane(bfront, leader);
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(smask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)smask, 0u));
@@ -1087,8 +1085,9 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         }
         if ((uint32_t)lane < nqa) drain(lane, true);
         if ((uint32_t)lane < nqb) drain((uint32_t)QC - 1u - lane, false);
-        __syncthreads();
-        if (threadIdx.x == 0) S.cnt_front[dst * ntiles + tile] = s_front;
+        // no barrier between species (each has its own front counter, the
+        // stacks and stages are per wave): a wave goes on to the next
+        // species while the others finish; diagnostic steps sum per species
         if (diag) {
             block_sum<kTileDiag>(acc, sred);
             if (threadIdx.x == 0)
@@ -1097,6 +1096,7 @@ __device__ __forceinline__ void particle_body(KP kp, int bid, int nb)
         }
     }
     __syncthreads();
+    if (threadIdx.x < (unsigned)kp->nspecies) kp->sp[threadIdx.x].cnt_front[dst * ntiles + tile] = s_front[threadIdx.x];
     if (threadIdx.x == 0)
         kp->tile_bucket[tile] = (uint8_t)min(kOrderBuckets - 1, (int)((double)load * kp->order_scale + 0.5));
     GLB R *Jt = gbl((R *)kp->Jtile) + (int64_t)tile * 3 * NJ_D;
