@@ -236,7 +236,7 @@ def progress(msg: str):
 # default, which makes store re-layouts (triggered when a filament outgrows
 # its tile's spare room) rarer.  The ensemble keeps the default.
 RESERVE_2D = 3.0      # C2/C3: 32 GB of particle store
-RESERVE_3D = 2.0      # C4: 112 GB
+RESERVE_3D = 2.9      # C4: ~145 GB; the largest below the library's 4 GiB cap per particle array
 # Coulomb-model line: the momentum-transfer rate is nu at this speed (about
 # the return current's drift speed in C3)
 COULOMB_VREF = 0.1
