@@ -1,6 +1,7 @@
 """Edge cases of the HIP path against the FP64 oracle (through the C ABI):
 an empty species, a ragged particle count that fills no whole wave, a grid of
-one tile (every mover re-enters the tile it left), a non-square grid, a
+one tile (every mover re-enters the tile it left), 3D grids of 1-3 tiles per
+axis, a non-square grid, a
 collision rate at which every draw below 2^32 - 1 scatters, and a species of
 zero weight (pushed, but carrying no current)."""
 import numpy as np
@@ -71,6 +72,17 @@ def test_single_tile_grid(pic):
     log("case edge: one tile (8 x 8)")
     wl = synth.beam_plasma((8, 8), ppc=16, u_th_beam=0.3, nu=0.05)
     _parity(pic, wl, synth.load(wl), 30, tile=8)
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (8, 8, 16), (16, 8, 24)])
+def test_3d_small_and_uneven_grids(pic, n):
+    """3D grids of one tile, of one tile across x and y, and of 1-3 tiles per
+    axis: the current reduction's neighbour tiles coincide with the node's
+    own tile or wrap around, and every mover re-enters a neighbour that may
+    be its own tile."""
+    log(f"case edge: 3D grid {n}")
+    wl = synth.beam_plasma(n, ppc=4, u_th_beam=0.3, nu=0.05)
+    _parity(pic, wl, synth.load(wl), 20, tile=8)
 
 
 def test_non_square_grid(pic):
