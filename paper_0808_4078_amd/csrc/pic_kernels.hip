@@ -2586,7 +2586,10 @@ static hipError_t step_kernels(const KParams &hp, const KParams *dp, Launcher &L
     L(k_rebin_count, dim3(nst), dim3(256), dp);
     L(k_rebin_count_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_scan, dim3(hp.nspecies), dim3(256), dp);
-    L(k_rebin_scatter<R>, dim3(1024), dim3(256), dp);
+    // one workgroup per 8 (species, tile) bins, 1024 to 16384 (the copy
+    // needs many workgroups in flight; an idle launch costs the same)
+    const unsigned scb = (unsigned)std::min<int64_t>(16384, std::max<int64_t>(1024, (int64_t)ntiles * hp.nspecies / 8));
+    L(k_rebin_scatter<R>, dim3(scb), dim3(256), dp);
     L(k_rebin_scatter_ovf<R>, dim3(256), dim3(256), dp);
     L(k_rebin_finalize, dim3(nst), dim3(256), dp);
     if (hp.binary) {
