@@ -5,7 +5,7 @@ and the seeded input generator (``synth/``), never the GPU library.  The
 series are too long for the GPU tests to recompute (minutes to tens of
 minutes of host time), so the tests read them from here.
 
-Two families:
+Families:
 
 * ``c3phys``: the headline workload's physics (beam n_b = 0.1, u_z = sqrt(8),
   u_th = 0.3; return-current plasma u_th = 0.01 scattering off the ions at
@@ -19,6 +19,10 @@ Two families:
   linear filamentation (t ~ 25 to 65) into saturation: the full-size series
   the GPU's mixed and FP64 runs of the benchmark workload are compared with
   (about two hours of host time on 8 cores).
+* ``c4phys``: the 3D workload's physics (C4: beam u_th = 0.1, 8 particles
+  per cell per species, collisionless; dx = 0.2, dt = 0.1) on a 64 x 64 x
+  128 box (8 388 608 particles) for 500 steps, through the 3D filamentation
+  of the beam into saturation (about ten minutes of host time on 8 cores).
 * ``paper-a`` .. ``paper-d``: the four 2D cases of the paper at its own
   parameters (2D PIC paragraph; captions of Figs. 1-2): 160^2 cells of
   0.125 c/w_p, 64 particles per cell per species, v_b = 0.9 c, n_p/n_b = 9,
@@ -32,7 +36,7 @@ The paper cases also store, every 50 steps, the transverse magnetic energy
 spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
-Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [paper-a] ...
+Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c4phys] [paper-a] ...
 (no argument: all; ``annotate`` only rewrites the fit line of the c3phys
 header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
@@ -62,6 +66,9 @@ C3PHYS_DIAG = 10
 # The headline workload at its full size, through its linear phase.
 C3FULL = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
                            name="c3-1024")
+
+# The 3D workload's physics on a box the oracle can step through its linear phase.
+C4PHYS = synth.beam_plasma((64, 64, 128), steps=500, ppc=8, u_th_beam=0.1, name="c4phys-64x64x128")
 
 # The paper's four 2D cases.
 PAPER_N, PAPER_DX, PAPER_DT = 160, 0.125, 0.0625
@@ -189,6 +196,9 @@ def main(argv):
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w == "annotate":
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "c4phys":
+            run_c3phys(os.path.join(HERE, "oracle_c4phys_64x64x128.txt"), C4PHYS)
+            annotate_c3phys(os.path.join(HERE, "oracle_c4phys_64x64x128.txt"))
         elif w == "c3full":
             run_c3phys(os.path.join(HERE, "oracle_c3_1024.txt"), C3FULL)
             annotate_c3phys(os.path.join(HERE, "oracle_c3_1024.txt"))
