@@ -23,6 +23,10 @@ Families:
   per cell per species, collisionless; dx = 0.2, dt = 0.1) on a 64 x 64 x
   128 box (8 388 608 particles) for 500 steps, through the 3D filamentation
   of the beam into saturation (about ten minutes of host time on 8 cores).
+* ``c3bin``: C3's physics on 256^2 with the binary electron-electron
+  collisions on (beam-plasma and plasma-plasma pairs in every cell, nu_ee =
+  0.05 at the reference speed 0.1) for 300 steps; the records add the
+  number of scattered pairs (about 16 minutes of host time on 8 cores).
 * ``paper-a`` .. ``paper-d``: the four 2D cases of the paper at its own
   parameters (2D PIC paragraph; captions of Figs. 1-2): 160^2 cells of
   0.125 c/w_p, 64 particles per cell per species, v_b = 0.9 c, n_p/n_b = 9,
@@ -36,7 +40,7 @@ The paper cases also store, every 50 steps, the transverse magnetic energy
 spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
-Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c4phys] [paper-a] ...
+Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c3bin] [c4phys] [paper-a] ...
 (no argument: all; ``annotate`` only rewrites the fit line of the c3phys
 header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
@@ -66,6 +70,10 @@ C3PHYS_DIAG = 10
 # The headline workload at its full size, through its linear phase.
 C3FULL = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
                            name="c3-1024")
+
+# The headline physics with binary collisions (the values of the benchmark's binary line).
+C3BIN = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=300,
+                          nu_ee=0.05, ee_vref=0.1, name="c3bin-256")
 
 # The 3D workload's physics on a box the oracle can step through its linear phase.
 C4PHYS = synth.beam_plasma((64, 64, 128), steps=500, ppc=8, u_th_beam=0.1, name="c4phys-64x64x128")
@@ -100,7 +108,8 @@ def ring_spectrum(Bx: np.ndarray, By: np.ndarray, d: float, mmax: int = 4) -> np
 
 def _species(wl, parts):
     return [oracle.SpeciesState(sc.q, sc.m, sc.weight, sc.nu, p.x.copy(), p.u.copy(), p.id.copy(),
-                                sc.coll_model, sc.coll_vref) for sc, p in zip(wl.species, parts)]
+                                sc.coll_model, sc.coll_vref, sc.binary and wl.nu_ee > 0.0)
+            for sc, p in zip(wl.species, parts)]
 
 
 def _header(wl, diag_every, extra=()):
@@ -141,6 +150,26 @@ def run_c3phys(path, wl=C3PHYS):
         fh.write("\n".join(lines) + "\n")
     if os.path.exists(path + ".part"):
         os.remove(path + ".part")
+
+
+def run_c3bin(path, wl=C3BIN):
+    """As run_c3phys, with the binary collisions on and the scattered pairs
+    appended to every record."""
+    parts = synth.load(wl)
+    orc = oracle.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, _species(wl, parts), wl.seed, 0,
+                           nu_ee=wl.nu_ee, ee_vref=wl.ee_vref)
+    lines = _header(wl, C3PHYS_DIAG, (f"binary collisions nu_ee {wl.nu_ee} ee_vref {wl.ee_vref} (all species); "
+                                      "last column: scattered pairs",))
+    t0 = time.time()
+    for s in range(wl.steps):
+        recs = orc.step(1, diag=(s % C3PHYS_DIAG == 0))
+        if recs:
+            lines.append(_rec_line(recs[0], wl.dt) + f" {recs[0]['ee_pairs']}")
+            if s % 50 == 0:
+                print(f"{wl.name} step {s} W_Bperp {recs[0]['W'][3] + recs[0]['W'][4]:.4e} "
+                      f"({time.time() - t0:.0f} s)", flush=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def run_paper(case, path_w, path_m):
@@ -196,6 +225,8 @@ def main(argv):
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w == "annotate":
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "c3bin":
+            run_c3bin(os.path.join(HERE, "oracle_c3bin_256.txt"))
         elif w == "c4phys":
             run_c3phys(os.path.join(HERE, "oracle_c4phys_64x64x128.txt"), C4PHYS)
             annotate_c3phys(os.path.join(HERE, "oracle_c4phys_64x64x128.txt"))
