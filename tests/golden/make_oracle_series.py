@@ -23,6 +23,9 @@ Families:
   per cell per species, collisionless; dx = 0.2, dt = 0.1) on a 64 x 64 x
   128 box (8 388 608 particles) for 500 steps, through the 3D filamentation
   of the beam into saturation (about ten minutes of host time on 8 cores).
+* ``c3coul``: C3's physics on 256^2 with the return-current plasma on the
+  Coulomb small-angle model (nu = 0.05 at the reference speed 0.1, every
+  plasma particle turned every step) for 600 steps (about five minutes).
 * ``c3bin``: C3's physics on 256^2 with the binary electron-electron
   collisions on (beam-plasma and plasma-plasma pairs in every cell, nu_ee =
   0.05 at the reference speed 0.1) for 300 steps; the records add the
@@ -40,7 +43,7 @@ The paper cases also store, every 50 steps, the transverse magnetic energy
 spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
-Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c3bin] [c4phys] [paper-a] ...
+Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c3coul] [c3bin] [c4phys] [paper-a] ...
 (no argument: all; ``annotate`` only rewrites the fit line of the c3phys
 header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
@@ -70,6 +73,10 @@ C3PHYS_DIAG = 10
 # The headline workload at its full size, through its linear phase.
 C3FULL = synth.beam_plasma((1024, 1024), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=800,
                            name="c3-1024")
+
+# The headline physics with the plasma on the Coulomb model (the benchmark's Coulomb line).
+C3COUL = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=600,
+                           coll_model=1, coll_vref=0.1, name="c3coul-256")
 
 # The headline physics with binary collisions (the values of the benchmark's binary line).
 C3BIN = synth.beam_plasma((256, 256), ppc=64, u_th_beam=0.3, u_th_plasma=0.01, nu=0.05, steps=300,
@@ -134,7 +141,9 @@ def _rec_line(r, dt):
 def run_c3phys(path, wl=C3PHYS):
     parts = synth.load(wl)
     orc = oracle.OracleRun(wl.ndim, wl.n, wl.d, wl.dt, _species(wl, parts), wl.seed, 0)
-    lines = _header(wl, C3PHYS_DIAG)
+    extra = ((f"plasma scattering: Coulomb small-angle model, coll_vref {wl.species[1].coll_vref}",)
+             if wl.species[1].coll_model == 1 else ())
+    lines = _header(wl, C3PHYS_DIAG, extra)
     t0 = time.time()
     for s in range(wl.steps):
         recs = orc.step(1, diag=(s % C3PHYS_DIAG == 0))
@@ -225,6 +234,9 @@ def main(argv):
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w == "annotate":
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "c3coul":
+            run_c3phys(os.path.join(HERE, "oracle_c3coul_256.txt"), C3COUL)
+            annotate_c3phys(os.path.join(HERE, "oracle_c3coul_256.txt"))
         elif w == "c3bin":
             run_c3bin(os.path.join(HERE, "oracle_c3bin_256.txt"))
         elif w == "c4phys":
