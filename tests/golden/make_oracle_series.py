@@ -30,6 +30,11 @@ Families:
   collisions on (beam-plasma and plasma-plasma pairs in every cell, nu_ee =
   0.05 at the reference speed 0.1) for 300 steps; the records add the
   number of scattered pairs (about 16 minutes of host time on 8 cores).
+* ``hyb-d``: the paper's collisional hot-beam case (d) in its reduced
+  quasi-neutral model (oracle/hybrid.py): 128^2 nodes over 20 x 20 c/w_p,
+  64 beam particles per cell, v_b = 0.9 c, u_th = 0.37, nu = 0.15, dt =
+  0.0625, to 20 plasma periods (2011 steps; about 35 minutes); records every
+  10 steps of W_Bperp, the beam's energy and z momentum, W_Ez and Eq. (7).
 * ``paper-a`` .. ``paper-d``: the four 2D cases of the paper at its own
   parameters (2D PIC paragraph; captions of Figs. 1-2): 160^2 cells of
   0.125 c/w_p, 64 particles per cell per species, v_b = 0.9 c, n_p/n_b = 9,
@@ -43,7 +48,7 @@ The paper cases also store, every 50 steps, the transverse magnetic energy
 spectrum |B_x(k)|^2 + |B_y(k)|^2 summed over the rings |k| = m 2 pi / L,
 m = 0..4 (the k-resolved growth of Eq. (12)).
 
-Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c3coul] [c3bin] [c4phys] [paper-a] ...
+Usage: python tests/golden/make_oracle_series.py [c3phys] [c3full] [c3coul] [c3bin] [c4phys] [hyb-d] [paper-a] ...
 (no argument: all; ``annotate`` only rewrites the fit line of the c3phys
 header from its stored data).  Set OMP_NUM_THREADS to share the host; the results do
 not depend on the thread count.
@@ -181,6 +186,39 @@ def run_c3bin(path, wl=C3BIN):
         fh.write("\n".join(lines) + "\n")
 
 
+HYB_DIAG = 10
+
+
+def hybrid_paper_d():
+    u_b = PAPER_VB / math.sqrt(1.0 - PAPER_VB * PAPER_VB)
+    n, L = 128, 20.0
+    return synth.HybridWorkload("hyb-paper-d", (n, n), (L / n, L / n), PAPER_DT, PAPER_STEPS, 0.1, 64, u_b, 0.37,
+                                0.15, seed=synth.SEED + 7)
+
+
+def run_hybrid(path):
+    from oracle.hybrid import Hybrid
+    wl = hybrid_paper_d()
+    x, u, uz = synth.hybrid_load(wl)
+    orc = Hybrid(wl.n, wl.d, wl.dt, wl.nu, x, u, uz, wl.weight, iters=wl.iters)
+    lines = [f"# oracle series {wl.name}: written by tests/golden/make_oracle_series.py (FP64 reduced-model "
+             f"oracle only)",
+             f"# grid {wl.n[0]}x{wl.n[1]} d {wl.d[0]} dt {wl.dt} steps {wl.steps} seed {wl.seed:#x} n_b {wl.n_b} "
+             f"ppc {wl.ppc} u_z {wl.u_b!r} u_th {wl.u_th} nu {wl.nu} sweeps {wl.iters}",
+             f"# record every {HYB_DIAG} steps: step time W_Bperp beam_energy beam_pz W_Ez eq7"]
+    t0 = time.time()
+    for s in range(wl.steps):
+        recs = orc.step(1, diag=(s % HYB_DIAG == 0))
+        if recs:
+            r = recs[0]
+            lines.append(f"{r['step']} {r['time']:.10g} {r['W_Bperp']:.17e} {r['beam_energy']:.17e} "
+                         f"{r['beam_pz']:.17e} {r['W_Ez']:.17e} {r['eq7']:.17e}")
+            if s % 200 == 0:
+                print(f"{wl.name} step {s} W_Bperp {r['W_Bperp']:.4e} ({time.time() - t0:.0f} s)", flush=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def run_paper(case, path_w, path_m):
     wl = paper_workload(case)
     parts = synth.load(wl)
@@ -234,6 +272,8 @@ def main(argv):
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
         elif w == "annotate":
             annotate_c3phys(os.path.join(HERE, "oracle_c3phys_256.txt"))
+        elif w == "hyb-d":
+            run_hybrid(os.path.join(HERE, "oracle_hybrid_paper_d.txt"))
         elif w == "c3coul":
             run_c3phys(os.path.join(HERE, "oracle_c3coul_256.txt"), C3COUL)
             annotate_c3phys(os.path.join(HERE, "oracle_c3coul_256.txt"))

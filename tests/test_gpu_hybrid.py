@@ -6,6 +6,7 @@ against the model's dispersion relation; and, at the benchmark size, one
 step recomputed by the oracle (the solve over the whole grid, sampled
 particles one by one)."""
 import math
+import os
 from dataclasses import replace
 
 import numpy as np
@@ -324,3 +325,44 @@ def test_hybrid_edge_cases(pic, case):
         assert np.max(np.abs(ug[:, o] - orc.u)) < 1e-9
         assert np.max(np.abs(pzg[o] - orc.P)) < 1e-9
     g.close()
+
+
+GOLDEN_HYB = os.path.join(os.path.dirname(__file__), "golden", "oracle_hybrid_paper_d.txt")
+
+
+def test_hybrid_paper_d_against_the_oracle_series(pic):
+    """The paper's collisional hot-beam case (d) in its reduced model
+    (128^2 nodes, 1M beam particles, to 20 plasma periods: 2011 steps, sort
+    every 10) against the reduced-model oracle's stored series from the same
+    particles (tests/golden/oracle_hybrid_paper_d.txt): W_Bperp, the beam's
+    energy and z momentum, W_Ez and Eq. (7) in every record, and the growth
+    rate of W_Bperp over t = 25..75."""
+    log("case hybrid paper (d) against the oracle series, 2011 steps")
+    N, L, dt = 128, 20.0, 0.0625
+    u_b = 0.9 / math.sqrt(1 - 0.81)
+    wl = synth.HybridWorkload("hyb-paper-d", (N, N), (L / N, L / N), dt, int(round(20 * 2 * math.pi / dt)), 0.1,
+                              64, u_b, 0.37, 0.15, seed=synth.SEED + 7)
+    o = np.loadtxt(GOLDEN_HYB)
+    x, u, uz = synth.hybrid_load(wl)
+    g = pic.HybridRun(pic.hyb_desc(wl, x.shape[1], diag_every=10, sort_every=10), x[0], x[1], u[0], u[1], uz)
+    g.step(wl.steps)
+    h = g.history()
+    g.close()
+    assert [r["step"] for r in h] == list(o[:, 0].astype(int))
+    errs = {}
+    for col, k in ((2, "W_Bperp"), (3, "beam_energy"), (4, "beam_pz"), (5, "W_Ez")):
+        got = np.array([r[k] for r in h])
+        errs[k] = float(np.max(np.abs(got - o[:, col]) / np.abs(o[:, col])))
+    t, Wg, Wo = o[:, 1], np.array([r["W_Bperp"] for r in h]), o[:, 2]
+    i0, i1 = int(np.argmin(abs(t - 25))), int(np.argmin(abs(t - 75)))
+    rate_g = 0.5 * math.log(Wg[i1] / Wg[i0]) / (t[i1] - t[i0])
+    rate_o = 0.5 * math.log(Wo[i1] / Wo[i0]) / (t[i1] - t[i0])
+    log("  worst record: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+        + f"; growth over t = 25..75: gpu {rate_g:.6f} oracle {rate_o:.6f} ({rate_g / rate_o - 1:.1e})")
+    # measured on one MI355X: W_Bperp 1.0e-13, beam energy 1.1e-15, beam p_z
+    # 1.5e-15, W_Ez 1.4e-9 (it starts near 5e-13, so its rounding is relatively
+    # large), growth rate 2e-14
+    assert Wo[i1] > 20 * Wo[i0]
+    assert errs["beam_energy"] < 1e-12 and errs["beam_pz"] < 1e-12
+    assert errs["W_Bperp"] < 1e-10 and errs["W_Ez"] < 1e-6
+    assert abs(rate_g / rate_o - 1) < 1e-10
